@@ -1,0 +1,244 @@
+"""Python binding of the FP64 CPU oracle of SaCD (oracle/sacd_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  The oracle checks the GPU library; only the tests,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` use it.
+It shares no code with the GPU library and never imports it.
+
+Paper: Balasubramaniam, Nayak, Yuen, "Efficient Nonnegative Tensor
+Factorization via Saturating Coordinate Descent" (arXiv 2003.03572).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle_sacd.so")
+SRC_PATH = os.path.join(_HERE, "sacd_oracle.c")
+
+UPDATE_GS = 0
+UPDATE_JACOBI = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        L = C.CDLL(LIB_PATH)
+        p = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        L.ora_tensor_create.argtypes = [p, i64, p, p, C.POINTER(p)]
+        L.ora_tensor_destroy.argtypes = [p]
+        L.ora_tensor_destroy.restype = None
+        L.ora_tensor_nnz.argtypes = [p]
+        L.ora_tensor_nnz.restype = i64
+        L.ora_tensor_norm2.argtypes = [p]
+        L.ora_tensor_norm2.restype = dbl
+        L.ora_tensor_mode_coo.argtypes = [p, i32, p, p, p]
+        L.ora_mttkrp.argtypes = [p, i32, i32, p, p, p, p]
+        L.ora_splitmix64.argtypes = [C.c_uint64, i64, p]
+        L.ora_splitmix64.restype = None
+        L.ora_cd_delta.argtypes = [dbl, dbl, dbl]
+        L.ora_cd_delta.restype = dbl
+        L.ora_importance.argtypes = [dbl, dbl, dbl]
+        L.ora_importance.restype = dbl
+        L.ora_select.argtypes = [i64, C.c_float, C.c_float, i32]
+        L.ora_select.restype = i32
+        L.ora_model_create.argtypes = [p, i32, C.c_uint64, i32, C.POINTER(p)]
+        L.ora_model_destroy.argtypes = [p]
+        L.ora_model_destroy.restype = None
+        L.ora_model_get_factor.argtypes = [p, i32, p]
+        L.ora_model_set_factor.argtypes = [p, i32, p]
+        L.ora_model_get_state.argtypes = [p, i32, p, p, p]
+        L.ora_model_set_state.argtypes = [p, i32, p, dbl, i64]
+        L.ora_model_force_flip.argtypes = [p, i32]
+        L.ora_model_force_flip.restype = None
+        L.ora_model_set_tie_tol.argtypes = [p, dbl]
+        L.ora_model_set_tie_tol.restype = None
+        L.ora_sweep.argtypes = [p, i32]
+        L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p, p]
+        L.ora_objective.argtypes = [p]
+        L.ora_objective.restype = dbl
+        L.ora_fit.argtypes = [p, p, p]
+        L.ora_run_until.argtypes = [p, dbl, i32, p, p, p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise OracleError(f"{what} failed with status {rc}")
+
+
+class Tensor:
+    """Sparse 3-way tensor (observed set Omega, Sec. 3)."""
+
+    def __init__(self, dims, idx: np.ndarray, vals: np.ndarray):
+        self.dims = tuple(int(d) for d in dims)
+        idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 3)
+        vals = np.ascontiguousarray(vals, dtype=np.float32).reshape(-1)
+        if idx.shape[0] != vals.shape[0]:
+            raise ValueError("idx and vals disagree on nnz")
+        d = np.array(self.dims, dtype=np.int64)
+        h = C.c_void_p()
+        _check(lib().ora_tensor_create(_ptr(d), idx.shape[0], _ptr(idx), _ptr(vals),
+                                       C.byref(h)), "ora_tensor_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ora_tensor_destroy(h)
+            self._h = None
+
+    @property
+    def nnz(self) -> int:
+        return int(lib().ora_tensor_nnz(self._h))
+
+    @property
+    def norm2(self) -> float:
+        return float(lib().ora_tensor_norm2(self._h))
+
+    def mode_coo(self, mode: int):
+        """(coords (nnz x 3: i_n, i_a, i_b), vals, ptr) sorted for `mode`."""
+        nnz = self.nnz
+        coords = np.empty((nnz, 3), np.int32)
+        vals = np.empty(nnz, np.float32)
+        ptr = np.empty(self.dims[mode] + 1, np.int64)
+        _check(lib().ora_tensor_mode_coo(self._h, mode, _ptr(coords), _ptr(vals), _ptr(ptr)),
+               "ora_tensor_mode_coo")
+        return coords, vals, ptr
+
+    def mttkrp(self, mode: int, factors) -> np.ndarray:
+        R = factors[0].shape[1]
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+        M = np.empty((self.dims[mode], R), np.float64)
+        _check(lib().ora_mttkrp(self._h, mode, R, _ptr(fs[0]), _ptr(fs[1]), _ptr(fs[2]), _ptr(M)),
+               "ora_mttkrp")
+        return M
+
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    out = np.empty(count, np.uint64)
+    lib().ora_splitmix64(C.c_uint64(seed), count, _ptr(out))
+    return out
+
+
+def cd_delta(a: float, g: float, h: float) -> float:
+    return float(lib().ora_cd_delta(a, g, h))
+
+
+def importance(g: float, delta: float, L: float) -> float:
+    return float(lib().ora_importance(g, delta, L))
+
+
+def select(k: int, z: float, zprev: float, flip: bool) -> bool:
+    return bool(lib().ora_select(k, z, zprev, int(flip)))
+
+
+class Model:
+    """SaCD state for one tensor (Alg. 1): factors, Grams, Z^{k-1}, ti^{k-1}, k."""
+
+    def __init__(self, tensor: Tensor, R: int, seed: int, update: int = UPDATE_GS):
+        self.t = tensor
+        self.R = int(R)
+        h = C.c_void_p()
+        _check(lib().ora_model_create(tensor._h, self.R, C.c_uint64(seed), update, C.byref(h)),
+               "ora_model_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().ora_model_destroy(h)
+            self._h = None
+
+    def factor(self, mode: int) -> np.ndarray:
+        out = np.empty((self.t.dims[mode], self.R), np.float64)
+        _check(lib().ora_model_get_factor(self._h, mode, _ptr(out)), "get_factor")
+        return out
+
+    def set_factor(self, mode: int, A: np.ndarray):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        assert A.shape == (self.t.dims[mode], self.R)
+        _check(lib().ora_model_set_factor(self._h, mode, _ptr(A)), "set_factor")
+
+    def state(self, mode: int):
+        zp = np.empty((self.t.dims[mode], self.R), np.float32)
+        ti = C.c_double()
+        k = C.c_int64()
+        _check(lib().ora_model_get_state(self._h, mode, _ptr(zp), C.byref(ti), C.byref(k)),
+               "get_state")
+        return zp, ti.value, k.value
+
+    def set_state(self, mode: int, zprev: np.ndarray, ti_prev: float, k: int):
+        zp = np.ascontiguousarray(zprev, dtype=np.float32)
+        assert zp.shape == (self.t.dims[mode], self.R)
+        _check(lib().ora_model_set_state(self._h, mode, _ptr(zp), float(ti_prev), int(k)),
+               "set_state")
+
+    def force_flip(self, v: int):
+        lib().ora_model_force_flip(self._h, int(v))
+
+    def set_tie_tol(self, tau: float):
+        lib().ora_model_set_tie_tol(self._h, float(tau))
+
+    def sweep(self, mode: int):
+        _check(lib().ora_sweep(self._h, mode), "ora_sweep")
+
+    def info(self, mode: int) -> dict:
+        I, R = self.t.dims[mode], self.R
+        M = np.empty((I, R), np.float64)
+        G0 = np.empty((I, R), np.float64)
+        z = np.empty((I, R), np.float32)
+        sel = np.empty((I, R), np.uint8)
+        tie = np.empty((I, R), np.uint8)
+        H = np.empty((R, R), np.float64)
+        sc = np.empty(6, np.float64)
+        _check(lib().ora_sweep_info(self._h, mode, _ptr(M), _ptr(G0), _ptr(z), _ptr(sel),
+                                    _ptr(tie), _ptr(H), _ptr(sc)), "sweep_info")
+        return dict(M=M, G0=G0, z=z, sel=sel.astype(bool), tie=tie.astype(bool), H=H,
+                    L=sc[0], ti=sc[1], flip=bool(sc[2]), tie_global=bool(sc[3]), f=sc[4],
+                    nsel=int(sc[5]))
+
+    def objective(self) -> float:
+        return float(lib().ora_objective(self._h))
+
+    def fit(self):
+        fit = C.c_double()
+        f = C.c_double()
+        _check(lib().ora_fit(self._h, C.byref(fit), C.byref(f)), "ora_fit")
+        return fit.value, f.value
+
+    def run_until(self, tol: float, max_iter: int):
+        trace = np.zeros(max_iter, np.float64)
+        it = C.c_int()
+        fit = C.c_double()
+        _check(lib().ora_run_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit),
+                                   _ptr(trace)), "ora_run_until")
+        return it.value, fit.value, trace[: it.value]

@@ -1,0 +1,103 @@
+/*
+ * sacd_oracle.h -- plain FP64 CPU oracle of Saturating Coordinate Descent (SaCD)
+ * for sparse nonnegative CP factorization of a 3-way tensor.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle exists to check the GPU library.  Only
+ * the test suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header, table or helper with the GPU library.
+ *
+ * Paper: Balasubramaniam, Nayak, Yuen, "Efficient Nonnegative Tensor
+ * Factorization via Saturating Coordinate Descent", ACM TKDD 2020
+ * (arXiv 2003.03572).  Every function below cites the passage it follows.
+ *
+ * Conventions
+ *   - dims[3] = (I0, I1, I2) = (Q, P, S) in the paper's notation (Table of
+ *     Symbols); mode n's factor A_n is I_n x R, row-major, FP64.
+ *   - For mode n the two other modes are a < b.
+ *   - Return codes: 0 ok, -1 invalid argument, -2 index out of range,
+ *     -3 out of memory, -4 bad state, -6 non-finite value.
+ */
+#ifndef SACD_ORACLE_H
+#define SACD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ora_tensor ora_tensor;
+typedef struct ora_model ora_model;
+
+/* Sparse tensor (Sec. 3, observed set Omega).  idx is nnz x 3, 0-based.
+ * Duplicate coordinates are merged by FP32 addition in input order. */
+int ora_tensor_create(const int64_t dims[3], int64_t nnz, const int32_t *idx,
+                      const float *vals, ora_tensor **out);
+void ora_tensor_destroy(ora_tensor *t);
+int64_t ora_tensor_nnz(const ora_tensor *t);
+double ora_tensor_norm2(const ora_tensor *t);
+/* Mode-n sorted coordinates: coords is nnz x 3 holding (i_n, i_a, i_b) in
+ * lexicographic order; ptr has dims[mode]+1 entries (slice Omega^n_i is
+ * ptr[i]..ptr[i+1]). */
+int ora_tensor_mode_coo(const ora_tensor *t, int mode, int32_t *coords,
+                        float *vals, int64_t *ptr);
+
+/* Sparse MTTKRP (eq. 9 first term; Sec. 4.4 column form):
+ * M[i_n, r] = sum over Omega of x * A_a[i_a, r] * A_b[i_b, r]. */
+int ora_mttkrp(const ora_tensor *t, int mode, int R, const double *A0,
+               const double *A1, const double *A2, double *M);
+
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): writes the first `count`
+ * outputs of the generator seeded with `seed`. */
+void ora_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
+
+/* Single-coordinate pieces, exposed for the pins. */
+double ora_cd_delta(double a, double g, double h);          /* eq. 11-12 */
+double ora_importance(double g, double delta, double L);    /* eq. 20 */
+int ora_select(int64_t k, float z, float zprev, int flip);  /* eq. 24-27, Alg. 1 */
+
+enum { ORA_UPDATE_GS = 0, ORA_UPDATE_JACOBI = 1 };
+
+/* Model: factors initialised from SplitMix64(seed): A_0, A_1, A_2 in that
+ * order, row-major with R columns, each output x mapped to (x >> 40) * 2^-24. */
+int ora_model_create(const ora_tensor *t, int R, uint64_t seed, int update_rule,
+                     ora_model **out);
+void ora_model_destroy(ora_model *m);
+int ora_model_get_factor(const ora_model *m, int mode, double *dst);
+int ora_model_set_factor(ora_model *m, int mode, const double *src);
+/* Selection state of one mode: previous importances (FP32, I_n x R), the
+ * previous total importance and the per-mode sweep counter k. */
+int ora_model_get_state(const ora_model *m, int mode, float *zprev,
+                        double *ti_prev, int64_t *k);
+int ora_model_set_state(ora_model *m, int mode, const float *zprev,
+                        double ti_prev, int64_t k);
+/* force_flip: -1 = decide from ti (normal), 0 / 1 = force the eq. 27 branch
+ * off / on (used to enumerate both outcomes at a total-importance tie). */
+void ora_model_force_flip(ora_model *m, int force_flip);
+/* Relative width of the tie band used for the diagnostics (default 1e-6). */
+void ora_model_set_tie_tol(ora_model *m, double tau);
+
+/* One SaCD sweep of mode n (Alg. 1 body for one factor matrix). */
+int ora_sweep(ora_model *m, int mode);
+
+/* Diagnostics of the last sweep of `mode`.  Any pointer may be NULL.
+ * M, G0 (I_n x R FP64), z (FP32 as used in the decision), sel / tie (uint8
+ * I_n x R), H (R x R), scalars: L, ti, flip, tie_global, f (objective after
+ * the sweep), nsel. */
+int ora_sweep_info(const ora_model *m, int mode, double *M, double *G0,
+                   float *z, uint8_t *sel, uint8_t *tie, double *H,
+                   double *scalars /* [L, ti, flip, tie_global, f, nsel] */);
+
+/* Objective eq. 6 (full-tensor least squares) and fit 1 - sqrt(f)/||X||. */
+double ora_objective(const ora_model *m);
+int ora_fit(const ora_model *m, double *fit, double *f);
+
+/* Outer loop of Alg. 1: iterations of sweep(0), sweep(1), sweep(2); stops
+ * after iteration k >= 2 when |fit_k - fit_{k-1}| < tol * |fit_{k-1}|, or at
+ * max_iter.  fit_trace (may be NULL) receives one fit per iteration. */
+int ora_run_until(ora_model *m, double tol, int max_iter, int *iters_done,
+                  double *final_fit, double *fit_trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,368 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: a published
+known-answer value, a textbook identity computed a different way (dense
+unfolding times an explicit Khatri-Rao product), brute force on tiny inputs,
+a library routine (numpy lexsort, scipy NNLS), a closed form, or a
+hand-worked example stored under tests/golden/ with its derivation.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2003_03572_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dense(dims, idx, vals):
+    X = np.zeros(dims, np.float64)
+    np.add.at(X, (idx[:, 0], idx[:, 1], idx[:, 2]), vals.astype(np.float64))
+    return X
+
+
+def _unfold(X, mode):
+    """Mode-n matricization with the column ordering of Kolda & Bader: for
+    mode 0, column p + s*P holds X[:, p, s] (the paper's X_1 in eq. 9)."""
+    return np.reshape(np.moveaxis(X, mode, 0), (X.shape[mode], -1), order="F")
+
+
+def _khatri_rao(B, C):
+    """Column-wise Kronecker product (eq. 3): column r is kron(B[:, r], C[:, r])."""
+    return np.stack([np.kron(B[:, r], C[:, r]) for r in range(B.shape[1])], axis=1)
+
+
+def _dense_objective(X, A):
+    Xhat = np.einsum("ir,jr,kr->ijk", A[0], A[1], A[2])
+    return float(np.sum((X - Xhat) ** 2))  # eq. 6 / eq. 7, all cells
+
+
+def _tiny(seed, dims=(4, 3, 5), nnz=25):
+    rng = np.random.default_rng(seed)
+    total = dims[0] * dims[1] * dims[2]
+    lin = rng.choice(total, size=nnz, replace=False)
+    idx = np.stack(np.unravel_index(lin, dims), axis=1).astype(np.int32)
+    vals = rng.integers(1, 6, size=nnz).astype(np.float32)
+    return dims, idx, vals
+
+
+# ---------------------------------------------------------------- init -----
+
+def test_splitmix64_known_answers(oracle_mod):
+    # Published first outputs of SplitMix64 seeded with 0.
+    out = oracle_mod.splitmix64(0, 3)
+    assert [int(x) for x in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                     0x06C45D188009454F]
+
+
+def test_init_uses_top_24_bits_in_mode_order(oracle_mod):
+    dims, idx, vals = _tiny(1)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 2, seed=0)
+    # first output 0xE220A8397B1DCDAF -> top 24 bits 0xE220A8
+    assert m.factor(0)[0, 0] == 0xE220A8 / 2 ** 24
+    assert m.factor(0)[0, 1] == 0x6E789E / 2 ** 24
+    # mode 1 starts after I0 * R outputs
+    raw = oracle_mod.splitmix64(0, dims[0] * 2 + 1)
+    assert m.factor(1)[0, 0] == (int(raw[dims[0] * 2]) >> 40) / 2 ** 24
+    for n in range(3):
+        A = m.factor(n)
+        assert A.min() >= 0.0 and A.max() < 1.0
+
+
+# -------------------------------------------------------------- ingest -----
+
+def test_mode_sort_matches_lexsort(oracle_mod):
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    others = {0: (1, 2), 1: (0, 2), 2: (0, 1)}
+    for n in range(3):
+        a, b = others[n]
+        order = np.lexsort((idx[:, b], idx[:, a], idx[:, n]))
+        coords, v, ptr = T.mode_coo(n)
+        np.testing.assert_array_equal(coords, idx[order][:, [n, a, b]])
+        np.testing.assert_array_equal(v, vals[order])
+        counts = np.bincount(idx[:, n], minlength=dims[n])
+        np.testing.assert_array_equal(ptr, np.concatenate([[0], np.cumsum(counts)]))
+
+
+def test_duplicates_are_added_in_input_order(oracle_mod):
+    dims = (2, 2, 2)
+    idx = np.array([[1, 1, 1], [0, 0, 0], [1, 1, 1], [0, 1, 0], [1, 1, 1]], np.int32)
+    vals = np.array([1e8, 3.0, 1.0, 2.0, -1e8], np.float32)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    assert T.nnz == 3
+    coords, v, ptr = T.mode_coo(0)
+    np.testing.assert_array_equal(coords, [[0, 0, 0], [0, 1, 0], [1, 1, 1]])
+    # FP32, input order: (1e8 + 1) rounds to 1e8, then - 1e8 gives 0
+    assert v[2] == np.float32(np.float32(np.float32(1e8) + np.float32(1.0)) - np.float32(1e8))
+    assert v[2] == 0.0
+    np.testing.assert_array_equal(ptr, [0, 2, 3])
+
+
+def test_rejects_bad_inputs(oracle_mod):
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.Tensor((2, 2, 2), np.array([[0, 2, 0]], np.int32), np.ones(1, np.float32))
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.Tensor((2, 2, 2), np.array([[0, 1, 0]], np.int32),
+                          np.array([np.nan], np.float32))
+
+
+# -------------------------------------------------------------- MTTKRP -----
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mttkrp_is_unfolding_times_khatri_rao(oracle_mod, seed):
+    dims, idx, vals = _tiny(seed, dims=(4, 3, 5), nnz=30)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    rng = np.random.default_rng(100 + seed)
+    R = 3
+    A = [rng.random((d, R)) for d in dims]
+    X = _dense(dims, idx, vals)
+    # eq. 9 and its mode-2 / mode-3 analogues (eq. pdei, pdet)
+    krp = {0: _khatri_rao(A[2], A[1]), 1: _khatri_rao(A[2], A[0]), 2: _khatri_rao(A[1], A[0])}
+    for n in range(3):
+        want = _unfold(X, n) @ krp[n]
+        got = T.mttkrp(n, A)
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------- Gram-Hadamard and L -----
+
+def test_hadamard_of_grams_and_lipschitz(oracle_mod):
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 8, seed=42)
+    A = [m.factor(n) for n in range(3)]
+    m.sweep(0)
+    info = m.info(0)
+    H = (A[1].T @ A[1]) * (A[2].T @ A[2])  # eq. 10
+    np.testing.assert_allclose(info["H"], H, rtol=1e-13)
+    assert np.allclose(info["H"], info["H"].T)
+    assert info["H"].min() >= 0.0
+    assert np.linalg.eigvalsh(info["H"]).min() > -1e-9 * np.abs(H).max()
+    assert math.isclose(info["L"], np.linalg.norm(H, "fro"), rel_tol=1e-13)
+
+
+# ------------------------------------------------ step and importance -----
+
+def _sweep_quantities(O, dims, idx, vals, R, seed, mode):
+    """Gradient pieces of one mode at the initial state, from the oracle."""
+    T = O.Tensor(dims, idx, vals)
+    m = O.Model(T, R, seed=seed)
+    A = [m.factor(n) for n in range(3)]
+    m.sweep(mode)
+    return T, A, m.info(mode)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_step_is_brute_force_one_coordinate_minimiser(oracle_mod, seed):
+    dims, idx, vals = _tiny(seed, dims=(3, 4, 5), nnz=40)
+    X = _dense(dims, idx, vals)
+    R = 3
+    T, A, info = _sweep_quantities(oracle_mod, dims, idx, vals, R, seed, mode=1)
+    H, G0 = info["H"], info["G0"]
+    def f_at(q, r, t):
+        B = [x.copy() for x in A]
+        B[1][q, r] = t
+        return _dense_objective(X, B)
+
+    for (q, r) in [(0, 0), (1, 2), (3, 1), (2, 0)]:
+        a = A[1][q, r]
+        want = a + oracle_mod.cd_delta(a, G0[q, r], H[r, r])  # eq. 11-13
+        # f along one coordinate is an exact parabola: three dense evaluations
+        # fix it; its minimiser over t >= 0 is max(0, vertex).
+        y0, y1, y2 = f_at(q, r, 0.0), f_at(q, r, 1.0), f_at(q, r, 2.0)
+        curv = y0 - 2 * y1 + y2
+        assert curv > 0
+        vertex = 0.5 - (y1 - y0) / curv
+        tstar = max(0.0, vertex)
+        assert abs(tstar - want) <= 1e-9 * max(1.0, abs(want)), (q, r, tstar, want)
+        # and a brute-force neighbourhood scan agrees that `want` is minimal
+        for t in np.linspace(max(0.0, want - 1.0), want + 1.0, 201):
+            assert f_at(q, r, want) <= f_at(q, r, t) + 1e-9 * abs(y0)
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_importance_with_L_equal_h_is_exact_half_decrease(oracle_mod, seed):
+    """eq. 18 (importance with h_rr in place of L) equals the exact decrease
+    of f/2 for the one-coordinate move, f being eq. 6 (the paper's gradient
+    eq. 9 drops the factor 2 of f's derivative)."""
+    dims, idx, vals = _tiny(seed, dims=(4, 4, 3), nnz=30)
+    X = _dense(dims, idx, vals)
+    R = 2
+    T, A, info = _sweep_quantities(oracle_mod, dims, idx, vals, R, seed, mode=0)
+    H, G0 = info["H"], info["G0"]
+    f0 = _dense_objective(X, A)
+    for q in range(dims[0]):
+        for r in range(R):
+            a = A[0][q, r]
+            d = oracle_mod.cd_delta(a, G0[q, r], H[r, r])
+            z = oracle_mod.importance(G0[q, r], d, H[r, r])
+            B = [x.copy() for x in A]
+            B[0][q, r] = a + d
+            assert math.isclose(z, (f0 - _dense_objective(X, B)) / 2, rel_tol=1e-9,
+                                abs_tol=1e-9 * f0)
+
+
+def test_importance_and_selection_worked_examples(oracle_mod):
+    with open(os.path.join(GOLDEN, "selection_cases.json")) as fh:
+        g = json.load(fh)
+    for c in g["importance_cases"]:
+        d = oracle_mod.cd_delta(c["a"], c["g"], c["h"])
+        z = oracle_mod.importance(c["g"], d, c["L"])
+        assert d == c["delta"], c["name"]
+        assert z == c["z"], c["name"]
+        assert oracle_mod.select(c["k"], z, 0.0, False) == c["selected"], c["name"]
+    for c in g["selection_cases"]:
+        flip = c["ti"] > c["ti_prev"]
+        assert flip == c["flip"]
+        assert oracle_mod.select(c["k"], c["z"], c["zprev"], flip) == c["selected"], c
+
+
+# ------------------------------------------------------------- update -----
+
+def _micro_model(O, update):
+    with open(os.path.join(GOLDEN, "micro_gs_jacobi.json")) as fh:
+        g = json.load(fh)
+    dims = tuple(g["dims"])
+    idx = np.array([g["nonzero"]["coord"]], np.int32)
+    vals = np.array([1.0 / math.sqrt(0.9)], np.float32)
+    T = O.Tensor(dims, idx, vals)
+    m = O.Model(T, 3, seed=0, update=update)
+    V = np.vstack([math.sqrt(0.9) * np.ones((1, 3)), math.sqrt(0.1) * np.eye(3)])
+    m.set_factor(0, np.zeros((1, 3)))
+    m.set_factor(1, V)
+    m.set_factor(2, np.ones((1, 3)))
+    return g, T, m
+
+
+def _force_select_all(O, m, mode):
+    """State under which every finite importance is selected: k >= 2, no flip
+    (ti_prev huge) and Z^{k-1} below every z."""
+    I = m.t.dims[mode]
+    m.set_state(mode, np.full((I, m.R), -3.0e38, np.float32), 1e300, 1)
+
+
+def test_micro_example_gauss_seidel_and_jacobi(oracle_mod):
+    O = oracle_mod
+    for update, key in [(O.UPDATE_GS, "gauss_seidel"), (O.UPDATE_JACOBI, "jacobi")]:
+        g, T, m = _micro_model(O, update)
+        assert math.isclose(m.objective(), g["f0"], rel_tol=1e-6)
+        _force_select_all(O, m, 0)
+        m.sweep(0)
+        want = g["select_all"][key]
+        np.testing.assert_allclose(m.factor(0)[0], want["u"], rtol=1e-6, atol=1e-7)
+        info = m.info(0)
+        np.testing.assert_allclose(info["M"][0], g["m"], rtol=1e-6)
+        np.testing.assert_allclose(info["H"], 0.9 * np.ones((3, 3)) + 0.1 * np.eye(3), rtol=1e-6)
+        assert math.isclose(info["f"], want["f"], rel_tol=1e-5)
+        assert math.isclose(m.objective(), want["f"], rel_tol=1e-5)
+    # Jacobi raises the objective here; Gauss-Seidel lowers it
+    assert g["select_all"]["jacobi"]["f"] > g["f0"] > g["select_all"]["gauss_seidel"]["f"]
+
+
+def test_micro_example_first_sweep_selects_nothing(oracle_mod):
+    g, T, m = _micro_model(oracle_mod, oracle_mod.UPDATE_GS)
+    m.sweep(0)
+    info = m.info(0)
+    assert math.isclose(info["L"], g["first_sweep_literal"]["L"], rel_tol=1e-6)
+    np.testing.assert_allclose(info["z"], g["first_sweep_literal"]["z"], rtol=1e-6)
+    assert info["nsel"] == 0
+    np.testing.assert_array_equal(m.factor(0), 0.0)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_select_all_gauss_seidel_converges_to_nnls(oracle_mod, seed):
+    """Repeated select-all sweeps of one mode with the other factors fixed are
+    HALS row sweeps; each row converges to the nonnegative least squares
+    solution of min u'Hu - 2m'u (scipy NNLS on H = C'C)."""
+    from scipy.optimize import nnls
+    O = oracle_mod
+    dims, idx, vals = _tiny(seed, dims=(5, 6, 7), nnz=80)
+    T = O.Tensor(dims, idx, vals)
+    R = 3
+    m = O.Model(T, R, seed=seed)
+    for _ in range(400):
+        _force_select_all(O, m, 2)
+        m.sweep(2)
+    info = m.info(2)
+    H, M = info["H"], info["M"]
+    Lc = np.linalg.cholesky(H)
+    C = Lc.T
+    for q in range(dims[2]):
+        d = np.linalg.solve(Lc, M[q])
+        x, _ = nnls(C, d)
+        np.testing.assert_allclose(m.factor(2)[q], x, rtol=1e-8, atol=1e-9)
+
+
+def test_rank_one_closed_form(oracle_mod):
+    O = oracle_mod
+    dims, idx, vals = _tiny(9, dims=(6, 5, 4), nnz=40)
+    T = O.Tensor(dims, idx, vals)
+    m = O.Model(T, 1, seed=3)
+    A = [m.factor(n) for n in range(3)]
+    _force_select_all(O, m, 0)
+    m.sweep(0)
+    h = float(((A[1].T @ A[1]) * (A[2].T @ A[2]))[0, 0])
+    Mref = T.mttkrp(0, A)
+    np.testing.assert_allclose(m.factor(0)[:, 0], np.maximum(0.0, Mref[:, 0] / h), rtol=1e-12)
+
+
+# ---------------------------------------------------------- objective -----
+
+@pytest.mark.parametrize("seed", [10, 11])
+def test_objective_gram_formula_equals_dense(oracle_mod, seed):
+    dims, idx, vals = _tiny(seed, dims=(5, 4, 6), nnz=50)
+    X = _dense(dims, idx, vals)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 3, seed=seed)
+    A = [m.factor(n) for n in range(3)]
+    assert math.isclose(m.objective(), _dense_objective(X, A), rel_tol=1e-10)
+    m.sweep(0)
+    m.sweep(1)
+    A = [m.factor(n) for n in range(3)]
+    f_dense = _dense_objective(X, A)
+    assert math.isclose(m.info(1)["f"], f_dense, rel_tol=1e-10)
+    assert math.isclose(m.objective(), f_dense, rel_tol=1e-10)
+    fit, f = m.fit()
+    assert math.isclose(fit, 1 - math.sqrt(f_dense) / math.sqrt(np.sum(X ** 2)), rel_tol=1e-10)
+
+
+def test_objective_nonincreasing_and_factors_nonnegative(oracle_mod):
+    """Gauss-Seidel coordinate minimisation cannot raise f for any selected
+    set, and the projection keeps every factor nonnegative (eq. ntf)."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 8, seed=42)
+    f_prev = m.objective()
+    for it in range(12):
+        for n in range(3):
+            m.sweep(n)
+            f = m.info(n)["f"]
+            assert f <= f_prev * (1 + 1e-12) + 1e-12, (it, n, f, f_prev)
+            assert m.factor(n).min() >= 0.0
+            f_prev = f
+    assert math.isclose(f_prev, m.objective(), rel_tol=1e-10)
+
+
+def test_jacobi_can_raise_the_objective(oracle_mod):
+    g, T, m = _micro_model(oracle_mod, oracle_mod.UPDATE_JACOBI)
+    f0 = m.objective()
+    _force_select_all(oracle_mod, m, 0)
+    m.sweep(0)
+    assert m.objective() > f0
+
+
+def test_run_until_stops_on_relative_fit_change(oracle_mod):
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 8, seed=42)
+    it, fit, trace = m.run_until(1e-3, 200)
+    assert 2 <= it < 200
+    assert abs(trace[-1] - trace[-2]) < 1e-3 * abs(trace[-2])
+    for k in range(1, it - 1):
+        assert abs(trace[k] - trace[k - 1]) >= 1e-3 * abs(trace[k - 1])
+    assert fit == trace[-1]

@@ -1,0 +1,212 @@
+/*
+ * sacd.h -- C ABI of the MI355X (gfx950) implementation of Saturating
+ * Coordinate Descent (SaCD) for sparse nonnegative CP factorization of a
+ * 3-way tensor.
+ *
+ * Paper: Balasubramaniam, Nayak, Yuen, "Efficient Nonnegative Tensor
+ * Factorization via Saturating Coordinate Descent", ACM TKDD 2020
+ * (arXiv 2003.03572).  Problem (Sec. 3, eq. ntf): given a sparse tensor X of
+ * size I0 x I1 x I2 with observed set Omega, find nonnegative factors
+ * A0 (I0 x R), A1 (I1 x R), A2 (I2 x R) minimising ||X - [[A0, A1, A2]]||^2
+ * (eq. 6), unobserved cells counting as zeros.  The library runs Algorithm 1:
+ * for every outer iteration, one sweep of each mode 0, 1, 2.
+ *
+ * Conventions for every call
+ *   - Device pointers are plain HIP device addresses on the device that was
+ *     current when the tensor was created.  Host pointers are marked "host".
+ *   - Streams are hipStream_t values passed as void*.  NULL means "the
+ *     library creates its own non-blocking stream" (the null stream cannot be
+ *     captured into the graphs the library uses).
+ *   - Calls never throw; they return a sacd_status.  sacd_last_error()
+ *     returns a message for the last failing call on the calling thread.
+ *   - A tensor or model is used by one host thread at a time.  All GPU work
+ *     of a model is ordered on its stream; calls that return results to the
+ *     host synchronise that stream.
+ *   - Factors are FP32, row-major, R columns (unpadded) at the boundary.
+ */
+#ifndef SACD_H
+#define SACD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SACD_OK = 0,
+  SACD_ERR_INVALID_ARG = -1,  /* bad size, mode, rank, pointer or option */
+  SACD_ERR_OUT_OF_RANGE = -2, /* a coordinate is outside dims */
+  SACD_ERR_NO_MEMORY = -3,    /* device allocation failed */
+  SACD_ERR_BAD_STATE = -4,    /* call not valid in the object's state */
+  SACD_ERR_DEVICE = -5,       /* a HIP runtime call failed */
+  SACD_ERR_NUMERIC = -6       /* NaN/Inf input, or ||X|| = 0 where a fit is asked */
+} sacd_status;
+
+/* Arithmetic of the dense R x R products (Gram matrices and A_n * H).
+ * FP32: everything in FP32 (objective in FP64).  MIXED_BF16: Gram and A_n * H
+ * on BF16 MFMA with FP32 accumulation; MTTKRP and updates stay FP32. */
+typedef enum { SACD_PREC_FP32 = 0, SACD_PREC_MIXED_BF16 = 1 } sacd_precision;
+
+/* Update of the selected elements (eq. 13).  GS: each selected element takes
+ * the exact one-variable minimiser with the gradient refreshed for the
+ * elements of its row already moved in this sweep (the refresh of g_qr that
+ * Lemma 2 calls for).  JACOBI: every selected element moves by the step
+ * computed from the sweep's snapshot gradient. */
+typedef enum { SACD_UPDATE_GS = 0, SACD_UPDATE_JACOBI = 1 } sacd_update;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns a device pointer (256-byte aligned) or NULL; release frees it.
+ * When the pointer passed to sacd_create_tensor is NULL the library uses
+ * hipMalloc / hipFree. */
+typedef struct sacd_allocator {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*release)(void *ptr, void *user);
+  void *user;
+} sacd_allocator;
+
+typedef struct sacd_tensor sacd_tensor; /* opaque, library-owned */
+typedef struct sacd_model sacd_model;   /* opaque, library-owned */
+
+/* Per-sweep statistics of one mode (host struct). */
+typedef struct sacd_sweep_stats {
+  int64_t k;          /* sweeps of this mode done so far (Alg. 1 loop counter) */
+  double lipschitz;   /* L = ||H||_F of the last sweep (Alg. 1) */
+  double ti;          /* total importance of the last sweep (eq. 25) */
+  int32_t flip;       /* 1 if the last sweep used eq. 27 (ti grew) */
+  int64_t n_selected; /* |E|: elements selected in the last sweep */
+  double objective;   /* eq. 6 after the last sweep of this mode (FP64) */
+} sacd_sweep_stats;
+
+/* ------------------------------------------------------------------------ */
+/* Tensor                                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Ingest a sparse tensor (Sec. 3: observed set Omega and its slices
+ * Omega^U_q, Omega^V_p, Omega^W_s).
+ *   dims  host, 3 mode lengths, each in [1, 2^31 - 1]; the bit widths of
+ *         (I0 - 1, I1 - 1, I2 - 1) must sum to at most 64.
+ *   nnz   number of entries, in [0, 2^31 - 1].
+ *   idx   device, nnz x 3 int32, row-major, 0-based coordinates.
+ *   vals  device, nnz float32.
+ *   alloc optional device allocator (NULL: hipMalloc).
+ *   stream hipStream_t or NULL (see conventions).
+ *   out   host, receives the tensor handle.
+ * The library copies the data; the caller keeps ownership of idx / vals.
+ * Entries with equal coordinates are merged by FP32 addition in input order.
+ * For each mode n the entries are sorted by (i_n, i_a, i_b), a < b the other
+ * modes, and slice pointers are built.  Synchronises the stream once.
+ * Errors: INVALID_ARG (sizes, NULL pointers), OUT_OF_RANGE (a coordinate not
+ * in [0, dims)), NUMERIC (NaN/Inf value), NO_MEMORY, DEVICE. */
+sacd_status sacd_create_tensor(const int64_t dims[3], int64_t nnz, const int32_t *idx,
+                               const float *vals, const sacd_allocator *alloc, void *stream,
+                               sacd_tensor **out);
+
+/* dims (host, 3), nnz after merging, ||X||^2 (FP64) and the device bytes the
+ * tensor holds.  Any output pointer may be NULL. */
+sacd_status sacd_tensor_info(const sacd_tensor *t, int64_t dims[3], int64_t *nnz, double *norm2,
+                             int64_t *device_bytes);
+
+/* Export mode `mode`'s sorted entries: coords device nnz x 3 int32 holding
+ * (i_n, i_a, i_b); vals device nnz float32; ptr device (dims[mode] + 1)
+ * int64 slice offsets.  Any pointer may be NULL.  Synchronises. */
+sacd_status sacd_tensor_mode_coo(const sacd_tensor *t, int32_t mode, int32_t *coords, float *vals,
+                                 int64_t *ptr);
+
+void sacd_destroy_tensor(sacd_tensor *t);
+
+/* ------------------------------------------------------------------------ */
+/* Model                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Create a model of rank R in [1, 128] over tensor t (Alg. 1 inputs: tensor,
+ * randomly initialised factors, rank).  Factors A0, A1, A2 are filled in that
+ * order, row-major with R columns, from consecutive outputs of SplitMix64
+ * seeded with `seed`, each output x mapped to (x >> 40) * 2^-24 in [0, 1).
+ * Z = empty (no sweep done).  The tensor must outlive the model.
+ * Errors: INVALID_ARG, NO_MEMORY, DEVICE. */
+sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
+                              sacd_update update, sacd_model **out);
+
+/* Enqueue one SaCD sweep of mode `mode` in {0, 1, 2} (Alg. 1 body for one
+ * factor matrix: MTTKRP, H and L, gradient and importance eq. 14 / eq. 20,
+ * total importance eq. 25, selection eq. 24 / eq. 27, update eq. 11-13,
+ * Gram and objective).  Asynchronous.  Errors: INVALID_ARG, DEVICE. */
+sacd_status sacd_sweep(sacd_model *m, int32_t mode);
+
+/* Enqueue `n_iters` outer iterations (sweeps of modes 0, 1, 2 each) as
+ * replays of one captured HIP graph.  Asynchronous. */
+sacd_status sacd_iterate(sacd_model *m, int32_t n_iters);
+
+/* Objective eq. 6 after the most recent sweep (FP64) and fit
+ * 1 - sqrt(max(f, 0)) / ||X||.  Before any sweep, the objective of the
+ * initial factors.  Synchronises.  NUMERIC if ||X|| = 0 (f is still set). */
+sacd_status sacd_fit(sacd_model *m, double *fit, double *objective);
+
+/* Outer loop of Alg. 1: run iterations until, after iteration k >= 2 of
+ * this call, |fit_k - fit_{k-1}| < tol * |fit_{k-1}|, or max_iter
+ * iterations.  Per-mode sweep counters persist across calls.  Synchronises
+ * once per iteration.  Outputs may be NULL. */
+sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t *iters_done,
+                           double *final_fit);
+
+/* Copy factor `mode` out to / in from device memory (I_n x R row-major
+ * FP32).  set_factor rejects negative or non-finite values (NUMERIC) and
+ * recomputes that mode's Gram matrix.  Synchronises. */
+sacd_status sacd_get_factor(const sacd_model *m, int32_t mode, float *dst);
+sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src);
+
+/* Selection state of one mode, for checkpoint / resume: zprev device
+ * I_n x R FP32 (importance of the last sweep, Z^{k-1} of Alg. 1), ti_prev
+ * (host, eq. 26) and k (host, sweeps done; k = 0 means Z is empty).
+ * Synchronises.  Any pointer of get_state may be NULL. */
+sacd_status sacd_get_state(const sacd_model *m, int32_t mode, float *zprev, double *ti_prev,
+                           int64_t *k);
+sacd_status sacd_set_state(sacd_model *m, int32_t mode, const float *zprev, double ti_prev,
+                           int64_t k);
+
+/* Statistics of the last sweep of `mode` (host struct).  Synchronises. */
+sacd_status sacd_get_stats(const sacd_model *m, int32_t mode, sacd_sweep_stats *out);
+
+/* Diagnostics of the last sweep of `mode`, for parity tests:
+ *   mttkrp     device I_n x R FP32, the MTTKRP M of eq. 9;
+ *   selection  device I_n x R uint8, 1 where the element was selected
+ *              (recorded only while diagnostics are enabled, else zeros);
+ *   gram       host R x R FP64, A_n^T A_n after the sweep.
+ * Any pointer may be NULL.  Synchronises. */
+sacd_status sacd_get_diagnostics(const sacd_model *m, int32_t mode, float *mttkrp,
+                                 uint8_t *selection, double *gram);
+/* Enable (1) or disable (0) recording of the selection mask. */
+sacd_status sacd_set_diagnostics(sacd_model *m, int32_t enable);
+
+/* Time kernel `which` (0 = MTTKRP main kernel, 1 = selection/update kernel,
+ * 2 = importance kernel) of mode `mode` on the model's stream with HIP
+ * events: `reps` back-to-back launches on the current state; the average
+ * milliseconds per launch go to *avg_ms (host).  The kernels re-run on
+ * unchanged inputs, so the model state is not advanced by MTTKRP / importance
+ * timing; timing the update kernel does change the factors.  Synchronises. */
+sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t reps,
+                             float *avg_ms);
+
+/* Algorithmic HBM bytes of one launch of kernel `which` (as in
+ * sacd_time_kernel) for mode `mode` at the model's shapes (host). */
+sacd_status sacd_kernel_bytes(const sacd_model *m, int32_t which, int32_t mode, double *bytes);
+
+/* Device bytes held by the model (factors, importances, MTTKRP, scratch). */
+sacd_status sacd_model_bytes(const sacd_model *m, int64_t *bytes);
+
+void sacd_destroy_model(sacd_model *m);
+
+/* ------------------------------------------------------------------------ */
+/* Misc                                                                      */
+/* ------------------------------------------------------------------------ */
+const char *sacd_status_string(sacd_status s);
+const char *sacd_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char *sacd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SACD_H */

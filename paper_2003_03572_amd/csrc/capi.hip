@@ -1,0 +1,809 @@
+// capi.hip -- host runtime of libsacd: the C ABI declared in include/sacd.h.
+//
+// Owns the device buffers of tensors and models, orders all work on the
+// object's stream, captures one outer iteration (three mode sweeps) as a HIP
+// graph for replay, and turns every failure into a sacd_status plus a
+// thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sacd.h"
+#include "common.hpp"
+
+using namespace sacd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+sacd_status fail(sacd_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t _e = (expr);                                                              \
+    if (_e != hipSuccess)                                                                \
+      return fail(_e == hipErrorOutOfMemory ? SACD_ERR_NO_MEMORY : SACD_ERR_DEVICE,      \
+                  "%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e), __FILE__, __LINE__); \
+  } while (0)
+
+#define SACD_TRY(expr)                 \
+  do {                                 \
+    sacd_status _s = (expr);           \
+    if (_s != SACD_OK) return _s;      \
+  } while (0)
+
+int bits_for(int64_t n) {  // bits needed to hold the values 0 .. n-1
+  int b = 0;
+  while (b < 63 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+void other_modes(int n, int *a, int *b) {
+  *a = (n == 0) ? 1 : 0;
+  *b = (n == 2) ? 1 : 2;
+}
+
+// Device memory owner: caller's allocator if given, else hipMalloc.
+struct DevAlloc {
+  sacd_allocator alloc{};
+  bool custom = false;
+  std::vector<void *> blocks;
+  int64_t bytes = 0;
+
+  sacd_status get(size_t n, void **out) {
+    if (n == 0) n = 16;
+    n = (n + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if (custom) {
+      p = alloc.alloc(n, alloc.user);
+      if (!p) return fail(SACD_ERR_NO_MEMORY, "allocator returned NULL for %zu bytes", n);
+    } else {
+      hipError_t e = hipMalloc(&p, n);
+      if (e != hipSuccess) return fail(SACD_ERR_NO_MEMORY, "hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+    }
+    blocks.push_back(p);
+    bytes += (int64_t)n;
+    *out = p;
+    return SACD_OK;
+  }
+  template <typename T>
+  sacd_status get_t(size_t count, T **out) {
+    void *p = nullptr;
+    SACD_TRY(get(count * sizeof(T), &p));
+    *out = (T *)p;
+    return SACD_OK;
+  }
+  void release(void *p) {
+    for (size_t i = 0; i < blocks.size(); ++i)
+      if (blocks[i] == p) {
+        if (custom) alloc.release(p, alloc.user);
+        else (void)hipFree(p);
+        blocks.erase(blocks.begin() + i);
+        return;
+      }
+  }
+  void release_all() {
+    for (void *p : blocks) {
+      if (custom) alloc.release(p, alloc.user);
+      else (void)hipFree(p);
+    }
+    blocks.clear();
+  }
+};
+
+}  // namespace
+
+struct sacd_tensor {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevAlloc mem;
+  int64_t dims[3] = {0, 0, 0};
+  long long nnz = 0;
+  KeyLayout lay[3];
+  unsigned long long *keys[3] = {nullptr, nullptr, nullptr};
+  float *vals[3] = {nullptr, nullptr, nullptr};
+  int *ptr[3] = {nullptr, nullptr, nullptr};
+  double norm2 = 0.0;
+  int nmodels = 0;
+};
+
+struct sacd_model {
+  sacd_tensor *t = nullptr;
+  hipStream_t s = nullptr;
+  DevAlloc mem;
+  int R = 0, RP = 0;
+  sacd_precision prec = SACD_PREC_FP32;
+  sacd_update upd = SACD_UPDATE_GS;
+  bool diag = false;
+  float *A[3] = {}, *Z[3] = {}, *M[3] = {}, *H[3] = {};
+  double *G64[3] = {};
+  HInfo *hinfo[3] = {};
+  ModeState *st = nullptr;  // 3 entries
+  long long *colcnt[3] = {};
+  uint8_t *selmask[3] = {};
+  float *carry = nullptr, *gpart = nullptr;
+  double *ti_part = nullptr, *inner_part = nullptr;
+  int *cnt_part = nullptr, *flag = nullptr;
+  double *full_part = nullptr, *full_out = nullptr;
+  unsigned *full_cnt = nullptr;
+  int full_nparts = 0;
+  MttkrpPlan plan[3];
+  int nparts[3] = {0, 0, 0};
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  double *h_pinned = nullptr;
+  int last_mode = -1;  // mode of the most recent sweep, -1: objective must be recomputed
+  bool dirty = true;   // factors changed outside a sweep
+};
+
+namespace {
+
+sacd_status enter(int dev) {
+  HIP_TRY(hipSetDevice(dev));
+  return SACD_OK;
+}
+
+sacd_status make_stream(void *stream, hipStream_t *out, bool *own) {
+  if (stream) {
+    *out = (hipStream_t)stream;
+    *own = false;
+  } else {
+    HIP_TRY(hipStreamCreateWithFlags(out, hipStreamNonBlocking));
+    *own = true;
+  }
+  return SACD_OK;
+}
+
+// ---------------------------------------------------------------- sweep ----
+
+sacd_status enqueue_sweep(sacd_model *m, int n) {
+  sacd_tensor *t = m->t;
+  int a, b;
+  other_modes(n, &a, &b);
+  const int I = (int)t->dims[n];
+  hipStream_t s = m->s;
+  HIP_TRY(launch_mttkrp(m->RP, m->plan[n], t->keys[n], t->vals[n], t->lay[n], m->A[a], m->A[b], m->M[n],
+                        m->carry, s));
+  HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[n], t->keys[n], t->lay[n].sh_n, t->ptr[n], I, m->carry,
+                            m->M[n], m->G64[a], m->G64[b], m->H[n], m->hinfo[n], m->st + n, s));
+  HIP_TRY(launch_importance(m->RP, I, m->A[n], m->M[n], m->H[n], m->hinfo[n], m->ti_part, m->st + n, s));
+  HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[n], m->M[n], m->Z[n], m->H[n],
+                               m->hinfo[n], m->st + n, m->gpart, m->inner_part, m->cnt_part,
+                               m->selmask[n], s));
+  HIP_TRY(launch_gram_final(m->RP, m->nparts[n], m->gpart, m->G64[n], m->G64[0], m->G64[1], m->G64[2],
+                            m->inner_part, m->cnt_part, m->colcnt[n], t->norm2, 1, m->st + n, s));
+  return SACD_OK;
+}
+
+sacd_status recompute_gram(sacd_model *m, int n) {
+  const int I = (int)m->t->dims[n];
+  HIP_TRY(launch_gram_partial(m->RP, I, m->A[n], m->gpart, m->s));
+  HIP_TRY(launch_gram_final(m->RP, m->nparts[n], m->gpart, m->G64[n], m->G64[0], m->G64[1], m->G64[2],
+                            nullptr, nullptr, nullptr, 0.0, 0, m->st + n, m->s));
+  return SACD_OK;
+}
+
+void drop_graph(sacd_model *m) {
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->gexec = nullptr;
+  m->graph = nullptr;
+}
+
+sacd_status ensure_graph(sacd_model *m) {
+  if (m->gexec) return SACD_OK;
+  HIP_TRY(hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal));
+  sacd_status st = SACD_OK;
+  for (int n = 0; n < 3 && st == SACD_OK; ++n) st = enqueue_sweep(m, n);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(m->s, &g);
+  if (st != SACD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SACD_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ge = nullptr;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(SACD_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  m->graph = g;
+  m->gexec = ge;
+  return SACD_OK;
+}
+
+sacd_status read_state(const sacd_model *m, int n, ModeState *out) {
+  HIP_TRY(hipMemcpyAsync(out, m->st + n, sizeof(ModeState), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+// Objective of the current factors from scratch (no sweep information).
+sacd_status objective_full(sacd_model *m, double *f) {
+  sacd_tensor *t = m->t;
+  const int RP = m->RP;
+  HIP_TRY(launch_inner_full(t->keys[0], t->vals[0], t->nnz, t->lay[0], RP, m->A[0], m->A[1], m->A[2],
+                            m->full_part, m->full_nparts, m->full_out, m->full_cnt, m->s));
+  std::vector<double> G((size_t)3 * RP * RP);
+  double inner = 0.0;
+  for (int n = 0; n < 3; ++n)
+    HIP_TRY(hipMemcpyAsync(G.data() + (size_t)n * RP * RP, m->G64[n], sizeof(double) * RP * RP,
+                           hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipMemcpyAsync(&inner, m->full_out, sizeof(double), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  double model = 0.0;
+  for (int i = 0; i < RP * RP; ++i)
+    model += G[i] * G[(size_t)RP * RP + i] * G[(size_t)2 * RP * RP + i];
+  *f = t->norm2 - 2.0 * inner + model;
+  return SACD_OK;
+}
+
+sacd_status check_mode(const sacd_model *m, int32_t mode) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (mode < 0 || mode > 2) return fail(SACD_ERR_INVALID_ARG, "mode %d not in {0, 1, 2}", mode);
+  return SACD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sacd_version(void) { return "0.1.0"; }
+
+const char *sacd_last_error(void) { return g_err; }
+
+const char *sacd_status_string(sacd_status s) {
+  switch (s) {
+    case SACD_OK: return "ok";
+    case SACD_ERR_INVALID_ARG: return "invalid argument";
+    case SACD_ERR_OUT_OF_RANGE: return "index out of range";
+    case SACD_ERR_NO_MEMORY: return "out of device memory";
+    case SACD_ERR_BAD_STATE: return "bad state";
+    case SACD_ERR_DEVICE: return "device error";
+    case SACD_ERR_NUMERIC: return "non-finite or degenerate value";
+  }
+  return "unknown status";
+}
+
+// ------------------------------------------------------------------ tensor --
+
+static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int64_t nnz,
+                                      const int32_t *idx, const float *vals) {
+  const hipStream_t s = t->stream;
+  int bits[3];
+  for (int n = 0; n < 3; ++n) bits[n] = bits_for(dims[n]);
+  for (int n = 0; n < 3; ++n) {
+    int a, b;
+    other_modes(n, &a, &b);
+    t->lay[n].sh_n = bits[a] + bits[b];
+    t->lay[n].sh_a = bits[b];
+    t->lay[n].mask_a = (bits[a] == 0) ? 0ull : ((1ull << bits[a]) - 1ull);
+    t->lay[n].mask_b = (bits[b] == 0) ? 0ull : ((1ull << bits[b]) - 1ull);
+  }
+  const int total_bits = bits[0] + bits[1] + bits[2];
+  const long long n = nnz;
+  DevAlloc tmp;
+  unsigned long long *k0 = nullptr, *k1 = nullptr;
+  float *v0 = nullptr, *v1 = nullptr;
+  int *err = nullptr, *cnt = nullptr;
+  void *temp = nullptr;
+  size_t tb = radix_sort_temp_bytes(n);
+  if (dedup_temp_bytes(n) > tb) tb = dedup_temp_bytes(n);
+  for (int m = 0; m < 3; ++m)
+    if (build_ptr_temp_bytes(n, (int)dims[m]) > tb) tb = build_ptr_temp_bytes(n, (int)dims[m]);
+  if (tb < 8192) tb = 8192;  // also holds the 512 + 1 doubles of the norm reduction
+  sacd_status rs = SACD_OK;
+  auto cleanup = [&]() { tmp.release_all(); };
+#define TMP_TRY(expr)                 \
+  do {                                \
+    rs = (expr);                      \
+    if (rs != SACD_OK) {              \
+      cleanup();                      \
+      return rs;                      \
+    }                                 \
+  } while (0)
+#define TMP_HIP(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t _e = (expr);                                                                    \
+    if (_e != hipSuccess) {                                                                    \
+      cleanup();                                                                               \
+      return fail(SACD_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));            \
+    }                                                                                          \
+  } while (0)
+  TMP_TRY(tmp.get_t(n > 0 ? n : 1, &k0));
+  TMP_TRY(tmp.get_t(n > 0 ? n : 1, &k1));
+  TMP_TRY(tmp.get_t(n > 0 ? n : 1, &v0));
+  TMP_TRY(tmp.get_t(n > 0 ? n : 1, &v1));
+  TMP_TRY(tmp.get_t(4, &err));
+  TMP_TRY(tmp.get_t(4, &cnt));
+  TMP_TRY(tmp.get(tb, &temp));
+  TMP_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+  TMP_HIP(launch_make_keys0(idx, vals, n, dims, t->lay[0], k0, v0, err, s));
+  int herr = 0;
+  TMP_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  TMP_HIP(hipStreamSynchronize(s));
+  if (herr & 1) {
+    cleanup();
+    return fail(SACD_ERR_OUT_OF_RANGE, "a coordinate is outside dims (%lld, %lld, %lld)",
+                (long long)dims[0], (long long)dims[1], (long long)dims[2]);
+  }
+  if (herr & 2) {
+    cleanup();
+    return fail(SACD_ERR_NUMERIC, "a value is NaN or Inf");
+  }
+  // mode 0: stable sort by the full key, then merge duplicates
+  bool in_alt = false;
+  TMP_HIP(radix_sort_pairs(k0, v0, k1, v1, n, 0, total_bits, temp, s, &in_alt));
+  unsigned long long *ks = in_alt ? k1 : k0;
+  float *vs = in_alt ? v1 : v0;
+  unsigned long long *kd = in_alt ? k0 : k1;  // free pair of buffers
+  float *vd = in_alt ? v0 : v1;
+  TMP_HIP(dedup_sorted(ks, vs, n, kd, vd, cnt, temp, s));
+  int hcnt = 0;
+  TMP_HIP(hipMemcpyAsync(&hcnt, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+  TMP_HIP(hipStreamSynchronize(s));
+  const long long u = hcnt;
+  t->nnz = u;
+  for (int m = 0; m < 3; ++m) {
+    TMP_TRY(t->mem.get_t(u > 0 ? u : 1, &t->keys[m]));
+    TMP_TRY(t->mem.get_t(u > 0 ? u : 1, &t->vals[m]));
+    TMP_TRY(t->mem.get_t((size_t)dims[m] + 1, &t->ptr[m]));
+  }
+  if (u > 0) {
+    TMP_HIP(hipMemcpyAsync(t->keys[0], kd, sizeof(unsigned long long) * u, hipMemcpyDeviceToDevice, s));
+    TMP_HIP(hipMemcpyAsync(t->vals[0], vd, sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+  }
+  // modes 1, 2: the mode-0 order sorted stably by i_n alone is (i_n, i_a, i_b) order
+  for (int m = 1; m < 3; ++m) {
+    TMP_HIP(launch_rekey(t->keys[0], u, t->lay[0], m, t->lay[m], k0, s));
+    if (u > 0)
+      TMP_HIP(hipMemcpyAsync(v0, t->vals[0], sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+    bool alt = false;
+    TMP_HIP(radix_sort_pairs(k0, v0, k1, v1, u, t->lay[m].sh_n, t->lay[m].sh_n + bits[m], temp, s, &alt));
+    if (u > 0) {
+      TMP_HIP(hipMemcpyAsync(t->keys[m], alt ? k1 : k0, sizeof(unsigned long long) * u,
+                             hipMemcpyDeviceToDevice, s));
+      TMP_HIP(hipMemcpyAsync(t->vals[m], alt ? v1 : v0, sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  for (int m = 0; m < 3; ++m)
+    TMP_HIP(build_ptr(t->keys[m], u, t->lay[m].sh_n, (int)dims[m], t->ptr[m], temp, s));
+  // ||X||^2
+  {
+    const int nparts = 512;
+    double *part = (double *)temp;  // temp holds at least 512 doubles
+    double *out = part + nparts;
+    TMP_HIP(launch_norm2(t->vals[0], u, part, nparts, out, s));
+    TMP_HIP(hipMemcpyAsync(&t->norm2, out, sizeof(double), hipMemcpyDeviceToHost, s));
+    TMP_HIP(hipStreamSynchronize(s));
+  }
+  cleanup();
+  return SACD_OK;
+#undef TMP_TRY
+#undef TMP_HIP
+}
+
+sacd_status sacd_create_tensor(const int64_t dims[3], int64_t nnz, const int32_t *idx, const float *vals,
+                               const sacd_allocator *alloc, void *stream, sacd_tensor **out) {
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!dims) return fail(SACD_ERR_INVALID_ARG, "dims is NULL");
+  for (int n = 0; n < 3; ++n)
+    if (dims[n] < 1 || dims[n] > 2147483647LL)
+      return fail(SACD_ERR_INVALID_ARG, "dims[%d] = %lld not in [1, 2^31 - 1]", n, (long long)dims[n]);
+  if (nnz < 0 || nnz > 2147483647LL) return fail(SACD_ERR_INVALID_ARG, "nnz = %lld not in [0, 2^31 - 1]", (long long)nnz);
+  if (nnz > 0 && (!idx || !vals)) return fail(SACD_ERR_INVALID_ARG, "idx / vals is NULL");
+  if (alloc && (!alloc->alloc || !alloc->release)) return fail(SACD_ERR_INVALID_ARG, "allocator callbacks are NULL");
+  if (bits_for(dims[0]) + bits_for(dims[1]) + bits_for(dims[2]) > 64)
+    return fail(SACD_ERR_INVALID_ARG, "mode lengths need more than 64 key bits");
+  sacd_tensor *t = new (std::nothrow) sacd_tensor();
+  if (!t) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    delete t;
+    return fail(SACD_ERR_DEVICE, "no HIP device");
+  }
+  t->dev = dev;
+  for (int n = 0; n < 3; ++n) t->dims[n] = dims[n];
+  if (alloc) {
+    t->mem.alloc = *alloc;
+    t->mem.custom = true;
+  }
+  sacd_status st = make_stream(stream, &t->stream, &t->own_stream);
+  if (st == SACD_OK) st = create_tensor_impl(t, dims, nnz, idx, vals);
+  if (st != SACD_OK) {
+    sacd_destroy_tensor(t);
+    return st;
+  }
+  *out = t;
+  return SACD_OK;
+}
+
+sacd_status sacd_tensor_info(const sacd_tensor *t, int64_t dims[3], int64_t *nnz, double *norm2,
+                             int64_t *device_bytes) {
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (dims)
+    for (int n = 0; n < 3; ++n) dims[n] = t->dims[n];
+  if (nnz) *nnz = t->nnz;
+  if (norm2) *norm2 = t->norm2;
+  if (device_bytes) *device_bytes = t->mem.bytes;
+  return SACD_OK;
+}
+
+sacd_status sacd_tensor_mode_coo(const sacd_tensor *t, int32_t mode, int32_t *coords, float *vals,
+                                 int64_t *ptr) {
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (mode < 0 || mode > 2) return fail(SACD_ERR_INVALID_ARG, "mode %d not in {0, 1, 2}", mode);
+  SACD_TRY(enter(t->dev));
+  HIP_TRY(launch_export_coo(t->keys[mode], t->vals[mode], t->nnz, t->lay[mode], coords, vals,
+                            t->ptr[mode], (int)t->dims[mode], ptr, t->stream));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  return SACD_OK;
+}
+
+void sacd_destroy_tensor(sacd_tensor *t) {
+  if (!t) return;
+  (void)hipSetDevice(t->dev);
+  if (t->stream) (void)hipStreamSynchronize(t->stream);
+  t->mem.release_all();
+  if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
+  delete t;
+}
+
+// ------------------------------------------------------------------- model --
+
+static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
+  sacd_tensor *t = m->t;
+  const int RP = m->RP;
+  DevAlloc &A = m->mem;
+  int maxI = 0;
+  long long maxchunks = 1;
+  for (int n = 0; n < 3; ++n) {
+    const int I = (int)t->dims[n];
+    if (I > maxI) maxI = I;
+    m->plan[n] = mttkrp_plan(RP, t->nnz);
+    if (m->plan[n].nchunks > maxchunks) maxchunks = m->plan[n].nchunks;
+    m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
+    SACD_TRY(A.get_t((size_t)I * RP, &m->A[n]));
+    SACD_TRY(A.get_t((size_t)I * RP, &m->Z[n]));
+    SACD_TRY(A.get_t((size_t)I * RP, &m->M[n]));
+    SACD_TRY(A.get_t((size_t)RP * RP, &m->H[n]));
+    SACD_TRY(A.get_t((size_t)RP * RP, &m->G64[n]));
+    SACD_TRY(A.get_t(1, &m->hinfo[n]));
+    SACD_TRY(A.get_t((size_t)RP, &m->colcnt[n]));
+    SACD_TRY(A.get_t((size_t)I * RP, &m->selmask[n]));
+  }
+  const int maxparts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
+  SACD_TRY(A.get_t(3, &m->st));
+  SACD_TRY(A.get_t((size_t)maxchunks * 2 * RP, &m->carry));
+  SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart));
+  SACD_TRY(A.get_t((size_t)maxparts, &m->ti_part));
+  SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
+  SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
+  SACD_TRY(A.get_t(4, &m->flag));
+  m->full_nparts = 1024;
+  SACD_TRY(A.get_t((size_t)m->full_nparts, &m->full_part));
+  SACD_TRY(A.get_t(1, &m->full_out));
+  SACD_TRY(A.get_t(4, &m->full_cnt));
+  HIP_TRY(hipHostMalloc((void **)&m->h_pinned, 64, hipHostMallocDefault));
+  hipStream_t s = m->s;
+  HIP_TRY(hipMemsetAsync(m->st, 0, 3 * sizeof(ModeState), s));
+  HIP_TRY(hipMemsetAsync(m->full_cnt, 0, 16, s));
+  unsigned long long off = 0;
+  for (int n = 0; n < 3; ++n) {
+    const int I = (int)t->dims[n];
+    HIP_TRY(launch_init_factor(m->A[n], I, m->R, RP, seed, off, s));
+    off += (unsigned long long)I * m->R;
+    HIP_TRY(hipMemsetAsync(m->Z[n], 0, sizeof(float) * I * RP, s));
+    HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * I * RP, s));
+    HIP_TRY(hipMemsetAsync(m->selmask[n], 0, (size_t)I * RP, s));
+    HIP_TRY(hipMemsetAsync(m->colcnt[n], 0, sizeof(long long) * RP, s));
+  }
+  for (int n = 0; n < 3; ++n) SACD_TRY(recompute_gram(m, n));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SACD_OK;
+}
+
+sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
+                              sacd_update update, sacd_model **out) {
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "rank %d not in [1, %d]", R, kMaxRP);
+  if (prec != SACD_PREC_FP32 && prec != SACD_PREC_MIXED_BF16)
+    return fail(SACD_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
+  if (prec == SACD_PREC_MIXED_BF16)
+    return fail(SACD_ERR_INVALID_ARG, "the mixed BF16 form is not built in this library");
+  if (update != SACD_UPDATE_GS && update != SACD_UPDATE_JACOBI)
+    return fail(SACD_ERR_INVALID_ARG, "unknown update rule %d", (int)update);
+  SACD_TRY(enter(t->dev));
+  sacd_model *m = new (std::nothrow) sacd_model();
+  if (!m) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
+  m->t = t;
+  m->s = t->stream;
+  m->mem.alloc = t->mem.alloc;
+  m->mem.custom = t->mem.custom;
+  m->R = R;
+  m->RP = R <= 16 ? 16 : R <= 32 ? 32 : R <= 64 ? 64 : 128;
+  m->prec = prec;
+  m->upd = update;
+  sacd_status st = init_model_impl(m, seed);
+  if (st != SACD_OK) {
+    sacd_destroy_model(m);
+    return st;
+  }
+  t->nmodels++;
+  m->last_mode = -1;
+  m->dirty = true;
+  *out = m;
+  return SACD_OK;
+}
+
+sacd_status sacd_sweep(sacd_model *m, int32_t mode) {
+  SACD_TRY(check_mode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(enqueue_sweep(m, mode));
+  m->last_mode = mode;
+  m->dirty = false;
+  return SACD_OK;
+}
+
+sacd_status sacd_iterate(sacd_model *m, int32_t n_iters) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (n_iters < 0) return fail(SACD_ERR_INVALID_ARG, "n_iters < 0");
+  if (n_iters == 0) return SACD_OK;
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(ensure_graph(m));
+  for (int i = 0; i < n_iters; ++i) HIP_TRY(hipGraphLaunch(m->gexec, m->s));
+  m->last_mode = 2;
+  m->dirty = false;
+  return SACD_OK;
+}
+
+sacd_status sacd_fit(sacd_model *m, double *fit, double *objective) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  SACD_TRY(enter(m->t->dev));
+  double f = 0.0;
+  if (m->last_mode < 0 || m->dirty) {
+    SACD_TRY(objective_full(m, &f));
+  } else {
+    ModeState s;
+    SACD_TRY(read_state(m, m->last_mode, &s));
+    f = s.f;
+  }
+  if (objective) *objective = f;
+  if (!(m->t->norm2 > 0.0)) return fail(SACD_ERR_NUMERIC, "||X|| = 0: the fit is undefined");
+  if (fit) *fit = 1.0 - std::sqrt(f > 0.0 ? f : 0.0) / std::sqrt(m->t->norm2);
+  return SACD_OK;
+}
+
+sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t *iters_done,
+                           double *final_fit) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (max_iter < 1 || !(tol >= 0.0)) return fail(SACD_ERR_INVALID_ARG, "max_iter < 1 or tol < 0");
+  if (!(m->t->norm2 > 0.0)) return fail(SACD_ERR_NUMERIC, "||X|| = 0: the fit is undefined");
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(ensure_graph(m));
+  const double nx = std::sqrt(m->t->norm2);
+  double prev = 0.0, fit = 0.0;
+  int it;
+  for (it = 1; it <= max_iter; ++it) {
+    HIP_TRY(hipGraphLaunch(m->gexec, m->s));
+    HIP_TRY(hipMemcpyAsync(m->h_pinned, &m->st[2].f, sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    m->last_mode = 2;
+    m->dirty = false;
+    const double f = m->h_pinned[0];
+    fit = 1.0 - std::sqrt(f > 0.0 ? f : 0.0) / nx;
+    if (it >= 2 && std::fabs(fit - prev) < tol * std::fabs(prev)) break;
+    prev = fit;
+  }
+  if (it > max_iter) it = max_iter;
+  if (iters_done) *iters_done = it;
+  if (final_fit) *final_fit = fit;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_factor(const sacd_model *m, int32_t mode, float *dst) {
+  SACD_TRY(check_mode(m, mode));
+  if (!dst) return fail(SACD_ERR_INVALID_ARG, "dst is NULL");
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  HIP_TRY(launch_copy_rows(m->A[mode], m->RP, dst, m->R, I, m->R, m->R, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src) {
+  SACD_TRY(check_mode(m, mode));
+  if (!src) return fail(SACD_ERR_INVALID_ARG, "src is NULL");
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  HIP_TRY(hipMemsetAsync(m->flag, 0, sizeof(int), m->s));
+  HIP_TRY(launch_check_factor(src, (long long)I * m->R, m->flag, m->s));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  if (hflag) return fail(SACD_ERR_NUMERIC, "factor has negative or non-finite entries");
+  HIP_TRY(launch_copy_rows(src, m->R, m->A[mode], m->RP, I, m->R, m->RP, m->s));
+  SACD_TRY(recompute_gram(m, mode));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  m->dirty = true;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_state(const sacd_model *m, int32_t mode, float *zprev, double *ti_prev, int64_t *k) {
+  SACD_TRY(check_mode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  if (zprev) HIP_TRY(launch_copy_rows(m->Z[mode], m->RP, zprev, m->R, I, m->R, m->R, m->s));
+  ModeState s;
+  SACD_TRY(read_state(m, mode, &s));
+  if (ti_prev) *ti_prev = s.ti_prev;
+  if (k) *k = s.k;
+  return SACD_OK;
+}
+
+sacd_status sacd_set_state(sacd_model *m, int32_t mode, const float *zprev, double ti_prev, int64_t k) {
+  SACD_TRY(check_mode(m, mode));
+  if (k < 0) return fail(SACD_ERR_INVALID_ARG, "k < 0");
+  if (k > 0 && !zprev) return fail(SACD_ERR_INVALID_ARG, "zprev is NULL with k > 0");
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  if (zprev) HIP_TRY(launch_copy_rows(zprev, m->R, m->Z[mode], m->RP, I, m->R, m->RP, m->s));
+  ModeState s;
+  SACD_TRY(read_state(m, mode, &s));
+  s.k = k;
+  s.ti_prev = ti_prev;
+  HIP_TRY(hipMemcpyAsync(m->st + mode, &s, sizeof(ModeState), hipMemcpyHostToDevice, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_get_stats(const sacd_model *m, int32_t mode, sacd_sweep_stats *out) {
+  SACD_TRY(check_mode(m, mode));
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  SACD_TRY(enter(m->t->dev));
+  ModeState s;
+  SACD_TRY(read_state(m, mode, &s));
+  out->k = s.k;
+  out->lipschitz = s.L;
+  out->ti = s.ti;
+  out->flip = s.flip;
+  out->n_selected = s.nsel;
+  out->objective = s.f;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_diagnostics(const sacd_model *m, int32_t mode, float *mttkrp, uint8_t *selection,
+                                 double *gram) {
+  SACD_TRY(check_mode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  const int R = m->R, RP = m->RP;
+  if (mttkrp) HIP_TRY(launch_copy_rows(m->M[mode], RP, mttkrp, R, I, R, R, m->s));
+  if (selection) {
+    HIP_TRY(hipMemcpy2DAsync(selection, (size_t)R, m->selmask[mode], (size_t)RP, (size_t)R, (size_t)I,
+                             hipMemcpyDeviceToDevice, m->s));
+  }
+  if (gram) {
+    std::vector<double> G((size_t)RP * RP);
+    HIP_TRY(hipMemcpyAsync(G.data(), m->G64[mode], sizeof(double) * RP * RP, hipMemcpyDeviceToHost, m->s));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < R; ++j) gram[i * R + j] = G[(size_t)i * RP + j];
+  }
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_set_diagnostics(sacd_model *m, int32_t enable) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  const bool d = enable != 0;
+  if (d != m->diag) {
+    SACD_TRY(enter(m->t->dev));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    drop_graph(m);
+    m->diag = d;
+  }
+  return SACD_OK;
+}
+
+sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t reps, float *avg_ms) {
+  SACD_TRY(check_mode(m, mode));
+  if (which < 0 || which > 2 || reps < 1 || !avg_ms) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  SACD_TRY(enter(m->t->dev));
+  sacd_tensor *t = m->t;
+  int a, b;
+  other_modes(mode, &a, &b);
+  const int I = (int)t->dims[mode];
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  // a save of the mode's selection state, so that timing does not advance it
+  ModeState saved;
+  SACD_TRY(read_state(m, mode, &saved));
+  HIP_TRY(hipEventRecord(e0, m->s));
+  for (int i = 0; i < reps; ++i) {
+    if (which == 0)
+      HIP_TRY(launch_mttkrp(m->RP, m->plan[mode], t->keys[mode], t->vals[mode], t->lay[mode], m->A[a],
+                            m->A[b], m->M[mode], m->carry, m->s));
+    else if (which == 1)
+      HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[mode], m->M[mode], m->Z[mode],
+                                   m->H[mode], m->hinfo[mode], m->st + mode, m->gpart, m->inner_part,
+                                   m->cnt_part, m->selmask[mode], m->s));
+    else
+      HIP_TRY(launch_importance(m->RP, I, m->A[mode], m->M[mode], m->H[mode], m->hinfo[mode],
+                                m->ti_part, m->st + mode, m->s));
+  }
+  HIP_TRY(hipEventRecord(e1, m->s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  if (which == 0) {
+    // restore the complete MTTKRP (spanning slices) for later sweeps' diagnostics
+    HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[mode], t->keys[mode], t->lay[mode].sh_n, t->ptr[mode], I,
+                              m->carry, m->M[mode], m->G64[a], m->G64[b], m->H[mode], m->hinfo[mode],
+                              m->st + mode, m->s));
+  }
+  HIP_TRY(hipMemcpyAsync(m->st + mode, &saved, sizeof(ModeState), hipMemcpyHostToDevice, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_kernel_bytes(const sacd_model *m, int32_t which, int32_t mode, double *bytes) {
+  SACD_TRY(check_mode(m, mode));
+  if (!bytes || which < 0 || which > 2) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  const sacd_tensor *t = m->t;
+  int a, b;
+  other_modes(mode, &a, &b);
+  const double R = m->R, I = (double)t->dims[mode];
+  if (which == 0) {
+    // stream 12 B per entry (8 B key, 4 B value); each factor row of A_a, A_b
+    // read once; M written once
+    *bytes = 12.0 * (double)t->nnz + 4.0 * R * ((double)t->dims[a] + (double)t->dims[b]) + 4.0 * R * I;
+  } else if (which == 1) {
+    // read A, M, Z; write A, Z
+    *bytes = 20.0 * R * I;
+  } else {
+    // read A, M
+    *bytes = 8.0 * R * I;
+  }
+  return SACD_OK;
+}
+
+sacd_status sacd_model_bytes(const sacd_model *m, int64_t *bytes) {
+  if (!m || !bytes) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  *bytes = m->mem.bytes;
+  return SACD_OK;
+}
+
+void sacd_destroy_model(sacd_model *m) {
+  if (!m) return;
+  (void)hipSetDevice(m->t->dev);
+  if (m->s) (void)hipStreamSynchronize(m->s);
+  drop_graph(m);
+  m->mem.release_all();
+  if (m->h_pinned) (void)hipHostFree(m->h_pinned);
+  if (m->t && m->t->nmodels > 0) m->t->nmodels--;
+  delete m;
+}
+
+}  // extern "C"

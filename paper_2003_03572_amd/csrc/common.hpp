@@ -1,0 +1,149 @@
+// common.hpp -- internal declarations shared by the HIP sources of libsacd.
+//
+// Device data layout (one tensor, one model):
+//   tensor, per mode n:  keys[n]  nnz x uint64  bit-packed (i_n, i_a, i_b), i_n in
+//                                 the high bits, sorted ascending (so entries of a
+//                                 slice are contiguous, fibres (i_n, i_a) too)
+//                        vals[n]  nnz x f32
+//                        ptr[n]   (I_n + 1) x int32 slice offsets
+//   model, per mode n:   A[n]     I_n x RP f32 factor, row stride RP (R padded to
+//                                 16/32/64/128 with zero columns)
+//                        Z[n]     I_n x RP f32 importance of the last sweep
+//                        M[n]     I_n x RP f32 MTTKRP of the last sweep
+//                        G64[n]   RP x RP f64 Gram matrix A_n^T A_n
+//   Padded columns are exactly zero in A, so their Gram rows/columns, H rows/
+//   columns and MTTKRP columns are zero: h_rr = 0 columns take no step and add
+//   nothing to any sum, which leaves every result of the real columns unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sacd {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kMaxRP = 128;
+
+// Per-mode selection / sweep state, resident in device memory so that a whole
+// iteration can be replayed as a HIP graph without host decisions.
+struct ModeState {
+  long long k;          // sweeps of this mode done
+  double ti_prev;       // total importance of the previous sweep (eq. 26)
+  double ti;            // total importance of the current sweep (eq. 25)
+  double f;             // objective after the last sweep of this mode (eq. 6)
+  double L;             // Lipschitz constant ||H||_F of the last sweep
+  double inner;         // <M_n, A_n> after the last sweep
+  long long nsel;       // elements selected in the last sweep
+  int flip;             // eq. 27 branch taken in the current sweep
+  int first;            // current sweep is the first of this mode (k == 1)
+  unsigned cnt_imp;     // arrival counters of the "last block" reductions
+  unsigned cnt_gram;
+  unsigned cnt_inner;
+  unsigned pad;
+};
+
+// H = Gram_a * Gram_b of the current sweep and what the element kernels need.
+struct HInfo {
+  float halfL;            // L / 2 in FP32
+  float L32;
+  double L64;
+  float hdiag[kMaxRP];    // h_rr
+  int nearzero[kMaxRP];   // h_rr < 1e-6 max_s h_ss: divide in FP64
+};
+
+// Key layout of one mode.
+struct KeyLayout {
+  int sh_n;       // shift of i_n
+  int sh_a;       // shift of i_a (= bits of i_b)
+  unsigned long long mask_a;
+  unsigned long long mask_b;
+};
+
+__device__ __forceinline__ int key_row(unsigned long long k, int sh_n) { return (int)(k >> sh_n); }
+
+// Importance of one element (eq. 20) from the MTTKRP entry m, the entry ah of
+// A_n H, the current value a, h = h_rr and L / 2.  Explicitly rounded FP32
+// operations: the importance and the update kernels recompute the same z
+// bit for bit.  Returns z; *step receives the projected step (eq. 11-12).
+__device__ __forceinline__ float element_importance(float ah, float m, float a, float h,
+                                                    int nearzero, float halfL, float *step) {
+  const float g = __fsub_rn(ah, m);  // eq. 14: g = -M + (A H)
+  float d = 0.0f;
+  if (h > 0.0f) {
+    const float q = nearzero ? (float)((double)g / (double)h) : __fdiv_rn(g, h);  // eq. 11
+    const float u = __fsub_rn(a, q);
+    d = __fsub_rn(fmaxf(u, 0.0f), a);  // eq. 12
+  }
+  *step = d;
+  return __fsub_rn(-__fmul_rn(g, d), __fmul_rn(__fmul_rn(halfL, d), d));  // eq. 20
+}
+
+// --------------------------------------------------------------------------
+// Launchers (host functions defined in the .hip files)
+// --------------------------------------------------------------------------
+
+// ingest.hip
+hipError_t launch_make_keys0(const int32_t *idx, const float *vals, long long nnz, const int64_t *dims,
+                             KeyLayout lay0, unsigned long long *keys, float *vout, int *err_flags,
+                             hipStream_t s);
+size_t radix_sort_temp_bytes(long long n);
+hipError_t radix_sort_pairs(unsigned long long *keys, float *vals, unsigned long long *keys_alt,
+                            float *vals_alt, long long n, int lo_bit, int hi_bit, void *temp,
+                            hipStream_t s, bool *result_in_alt);
+size_t dedup_temp_bytes(long long n);
+hipError_t dedup_sorted(const unsigned long long *keys, const float *vals, long long n,
+                        unsigned long long *ukeys, float *uvals, int *d_count, void *temp,
+                        hipStream_t s);
+hipError_t launch_rekey(const unsigned long long *keys0, long long n, KeyLayout lay0, int mode,
+                        KeyLayout layn, unsigned long long *keysn, hipStream_t s);
+hipError_t build_ptr(const unsigned long long *keys, long long n, int sh_n, int I, int *ptr,
+                     void *temp, hipStream_t s);
+size_t build_ptr_temp_bytes(long long n, int I);
+hipError_t launch_norm2(const float *vals, long long n, double *partials, int nparts, double *out,
+                        hipStream_t s);
+hipError_t launch_export_coo(const unsigned long long *keys, const float *vals, long long n,
+                             KeyLayout lay, int32_t *coords, float *vout, const int *ptr, int I,
+                             int64_t *ptr64, hipStream_t s);
+
+// mttkrp.hip
+struct MttkrpPlan {
+  long long nnz;
+  int S;          // entries per lane group
+  long long C;    // entries per wave chunk
+  int nchunks;    // wave chunks
+  int blocks;     // blocks of the main kernel (4 waves each)
+};
+MttkrpPlan mttkrp_plan(int RP, long long nnz);
+hipError_t launch_mttkrp(int RP, const MttkrpPlan &p, const unsigned long long *keys, const float *vals,
+                         KeyLayout lay, const float *Aa, const float *Ab, float *M, float *carry,
+                         hipStream_t s);
+hipError_t launch_mttkrp_fix(int RP, const MttkrpPlan &p, const unsigned long long *keys, int sh_n,
+                             const int *ptr, int I, const float *carry, float *M, const double *Ga,
+                             const double *Gb, float *H, HInfo *hinfo, ModeState *st, hipStream_t s);
+
+// sweep.hip
+int rows_per_block(int RP);
+hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long seed,
+                              unsigned long long offset, hipStream_t s);
+hipError_t launch_importance(int RP, int I, const float *A, const float *M, const float *H,
+                             const HInfo *hinfo, double *ti_part, ModeState *st, hipStream_t s);
+hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, const float *M,
+                                float *Z, const float *H, const HInfo *hinfo, const ModeState *st,
+                                float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
+                                hipStream_t s);
+hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s);
+hipError_t launch_gram_final(int RP, int nparts, const float *gpart, double *Gn, const double *G0,
+                             const double *G1, const double *G2, const double *inner_part,
+                             const int *cnt_part, long long *colcnt, double normX2, int with_f,
+                             ModeState *st, hipStream_t s);
+hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,
+                             KeyLayout lay0, int RP, const float *A0, const float *A1,
+                             const float *A2, double *partials, int nparts, double *out,
+                             unsigned *counter, hipStream_t s);
+hipError_t launch_copy_rows(const float *src, int src_stride, float *dst, int dst_stride, int I,
+                            int ncols, int zero_cols_to, hipStream_t s);
+hipError_t launch_check_factor(const float *src, long long n, int *flag, hipStream_t s);
+
+}  // namespace sacd

@@ -1,0 +1,614 @@
+// sweep.hip -- the dense part of one SaCD sweep of mode n (Alg. 1):
+//
+//   k_importance     A_n H on MFMA (16x16x4 FP32), gradient G0 = -M + A_n H
+//                    (eq. 9, eq. 14), projected step (eq. 11-12), Lipschitz
+//                    importance z (eq. 20); per-block partial sums of z in
+//                    FP64; the last block to finish forms the total importance
+//                    (eq. 25) in a fixed order and decides the eq. 27 branch.
+//   k_select_update  recomputes z bit for bit, selects (Alg. 1, eq. 24 / 27),
+//                    stores z as the next Z^{k-1}, updates the selected
+//                    elements of each row (eq. 13; Gauss-Seidel refresh of the
+//                    row's gradient, or Jacobi), and emits per-block partials
+//                    of the new Gram matrix (MFMA), of <M, A_n> (FP64) and of
+//                    the per-column selection counts.
+//   k_gram_final     reduces the Gram partials in FP64 in a fixed order; the
+//                    last block forms the objective eq. 6 in FP64.
+//
+// Rows are split into blocks of RB rows; a block keeps its rows of A_n in LDS
+// (row stride RP + 1 floats: conflict-free for the lane-per-row update).
+#include "common.hpp"
+
+namespace sacd {
+
+namespace {
+
+template <int RP>
+struct UCfg {
+  static constexpr int RB = RP <= 32 ? 256 : (RP == 64 ? 128 : 64);  // rows per block
+  static constexpr int STR = RP + 1;                                   // LDS row stride (floats)
+  static constexpr int SST = RP + 4;                                   // LDS row stride (bytes) of sel
+  static constexpr int TC = RP / 16;                                   // 16-column tiles
+  static constexpr int NT = (RB / 16) * TC;                            // 16x16 tiles per block
+  static constexpr int NTW = NT / 4;                                   // tiles per wave
+};
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Load that observes stores made by other blocks of the same grid after the
+// arrival counter has been read (device-scope coherent).
+template <typename T>
+__device__ __forceinline__ T ld_coherent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int RP>
+__device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
+  using Cf = UCfg<RP>;
+  for (int i = threadIdx.x; i < Cf::RB * RP; i += kThreads) {
+    const int r = i / RP, c = i % RP;
+    sA[r * Cf::STR + c] = (row0 + r < I) ? A[(long long)(row0 + r) * RP + c] : 0.0f;
+  }
+}
+
+// C tile (16 x 16) of the block's rows times H: rows tr*16.., columns tc*16..
+template <int RP>
+__device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *__restrict__ H, int tr, int tc,
+                                         int lane) {
+  using Cf = UCfg<RP>;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kk = 0; kk < RP / 4; ++kk) {
+    const float a = sA[(tr * 16 + (lane & 15)) * Cf::STR + kk * 4 + (lane >> 4)];
+    const float b = H[(kk * 4 + (lane >> 4)) * RP + tc * 16 + (lane & 15)];
+    acc = mfma4(a, b, acc);
+  }
+  return acc;
+}
+
+// Block-wide FP64 sum in a fixed tree order (all threads call; result in red[0]).
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__restrict__ A,
+                                                         const float *__restrict__ M,
+                                                         const float *__restrict__ H,
+                                                         const HInfo *__restrict__ hi,
+                                                         double *__restrict__ ti_part, ModeState *st) {
+  using Cf = UCfg<RP>;
+  __shared__ float sA[Cf::RB * Cf::STR];
+  __shared__ double red[kThreads];
+  __shared__ int s_last;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row0 = blockIdx.x * Cf::RB;
+  load_rows<RP>(sA, A, row0, I);
+  __syncthreads();
+  const float halfL = hi->halfL;
+  double zs = 0.0;
+  for (int t = wv; t < Cf::NT; t += 4) {
+    const int tr = t / Cf::TC, tc = t % Cf::TC;
+    const f32x4 ah = tile_AH<RP>(sA, H, tr, tc, lane);
+    const int cc = tc * 16 + (lane & 15);
+    const float h = hi->hdiag[cc];
+    const int nz = hi->nearzero[cc];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = tr * 16 + 4 * (lane >> 4) + v;
+      const long long q = row0 + rr;
+      if (q < I) {
+        float d;
+        const float z = element_importance(ah[v], M[q * RP + cc], sA[rr * Cf::STR + cc], h, nz,
+                                           halfL, &d);
+        zs += (double)z;
+      }
+    }
+  }
+  const double bs = block_sum(zs, red);
+  if (tid == 0) {
+    ti_part[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->cnt_imp, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double s = 0.0;
+  for (int i = tid; i < (int)gridDim.x; i += kThreads) s += ld_coherent(&ti_part[i]);
+  const double ti = block_sum(s, red);
+  if (tid == 0) {
+    const long long k = st->k + 1;
+    const int first = (k == 1);
+    st->flip = (!first && ti > st->ti_prev) ? 1 : 0;  // eq. 27 condition: "more than"
+    st->first = first;
+    st->k = k;
+    st->ti = ti;
+    st->ti_prev = ti;  // becomes ti^{k-1} of the next sweep (eq. 26)
+    st->cnt_imp = 0;
+  }
+}
+
+// Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
+template <int RP, int UPD>
+__device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, const uint8_t *s_l,
+                                               const float *__restrict__ H,
+                                               const HInfo *__restrict__ hi) {
+  float a[RP], g[RP];
+  unsigned long long sel = 0;
+#pragma unroll
+  for (int c = 0; c < RP; ++c) {
+    a[c] = a_l[c];
+    g[c] = g_l[c];
+    sel |= (unsigned long long)(s_l[c] != 0) << c;
+  }
+  if (sel == 0) return;
+#pragma unroll
+  for (int r = 0; r < RP; ++r) {
+    if ((sel >> r) & 1ull) {
+      const float h = hi->hdiag[r];
+      if (h > 0.0f) {
+        const float q = hi->nearzero[r] ? (float)((double)g[r] / (double)h) : __fdiv_rn(g[r], h);
+        const float an = fmaxf(__fsub_rn(a[r], q), 0.0f);  // eq. 11-13
+        const float d = __fsub_rn(an, a[r]);
+        a[r] = an;
+        if (UPD == 0 && d != 0.0f) {
+          // refresh the gradient of the row's later elements: g_s += d * H_rs
+#pragma unroll
+          for (int s = r + 1; s < RP; ++s) g[s] = __fmaf_rn(d, H[r * RP + s], g[s]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < RP; ++c) a_l[c] = a[c];
+}
+
+// Same update with the row kept in LDS (RP = 128).
+template <int RP, int UPD>
+__device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const uint8_t *s_l,
+                                               const float *__restrict__ H,
+                                               const HInfo *__restrict__ hi) {
+  for (int r = 0; r < RP; ++r) {
+    if (!s_l[r]) continue;
+    const float h = hi->hdiag[r];
+    if (!(h > 0.0f)) continue;
+    const float gr = g_l[r], ar = a_l[r];
+    const float q = hi->nearzero[r] ? (float)((double)gr / (double)h) : __fdiv_rn(gr, h);
+    const float an = fmaxf(__fsub_rn(ar, q), 0.0f);
+    const float d = __fsub_rn(an, ar);
+    a_l[r] = an;
+    if (UPD == 0 && d != 0.0f) {
+      for (int s = r + 1; s < RP; ++s) g_l[s] = __fmaf_rn(d, H[r * RP + s], g_l[s]);
+    }
+  }
+}
+
+template <int RP, int UPD, bool DIAG>
+__global__ __launch_bounds__(kThreads) void k_select_update(
+    int I, float *__restrict__ A, const float *__restrict__ M, float *__restrict__ Z,
+    const float *__restrict__ H, const HInfo *__restrict__ hi, const ModeState *__restrict__ st,
+    float *__restrict__ gpart, double *__restrict__ inner_part, int *__restrict__ cnt_part,
+    uint8_t *__restrict__ selmask) {
+  using Cf = UCfg<RP>;
+  __shared__ float sA[Cf::RB * Cf::STR];
+  __shared__ float sG[Cf::RB * Cf::STR];
+  __shared__ uint8_t sSel[Cf::RB * Cf::SST];
+  __shared__ double red[kThreads];
+  __shared__ int sCnt[RP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int row0 = blockIdx.x * Cf::RB;
+  load_rows<RP>(sA, A, row0, I);
+  for (int c = tid; c < RP; c += kThreads) sCnt[c] = 0;
+  __syncthreads();
+  const int first = st->first, flip = st->flip;
+  const float halfL = hi->halfL;
+  float mreg[Cf::NTW][4];
+#pragma unroll
+  for (int ti = 0; ti < Cf::NTW; ++ti) {
+    const int t = wv + 4 * ti;
+    const int tr = t / Cf::TC, tc = t % Cf::TC;
+    const f32x4 ah = tile_AH<RP>(sA, H, tr, tc, lane);
+    const int cc = tc * 16 + (lane & 15);
+    const float h = hi->hdiag[cc];
+    const int nz = hi->nearzero[cc];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = tr * 16 + 4 * (lane >> 4) + v;
+      const long long q = row0 + rr;
+      mreg[ti][v] = 0.0f;
+      uint8_t sl = 0;
+      float gv = 0.0f;
+      if (q < I) {
+        const float m = M[q * RP + cc];
+        float d;
+        const float z = element_importance(ah[v], m, sA[rr * Cf::STR + cc], h, nz, halfL, &d);
+        const float zp = Z[q * RP + cc];
+        // Alg. 1: first sweep z > 0; later sp = z - zprev (eq. 24) or zprev - z (eq. 27) > 0
+        const bool s = first ? (z > 0.0f) : (flip ? (z < zp) : (z > zp));
+        Z[q * RP + cc] = z;
+        gv = __fsub_rn(ah[v], m);
+        sl = s ? 1 : 0;
+        mreg[ti][v] = m;
+        if (DIAG) selmask[q * RP + cc] = sl;
+        if (s) atomicAdd(&sCnt[cc], 1);
+      }
+      sG[rr * Cf::STR + cc] = gv;
+      sSel[rr * Cf::SST + cc] = sl;
+    }
+  }
+  __syncthreads();
+  if (tid < Cf::RB && row0 + tid < I) {
+    if constexpr (RP <= 64)
+      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, H, hi);
+    else
+      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, H, hi);
+  }
+  __syncthreads();
+  for (int i = tid; i < Cf::RB * RP; i += kThreads) {
+    const int r = i / RP, c = i % RP;
+    if (row0 + r < I) A[(long long)(row0 + r) * RP + c] = sA[r * Cf::STR + c];
+  }
+  // <M, A_n> over the block, FP64
+  double inner = 0.0;
+#pragma unroll
+  for (int ti = 0; ti < Cf::NTW; ++ti) {
+    const int t = wv + 4 * ti;
+    const int tr = t / Cf::TC, tc = t % Cf::TC;
+    const int cc = tc * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = tr * 16 + 4 * (lane >> 4) + v;
+      inner += (double)mreg[ti][v] * (double)sA[rr * Cf::STR + cc];
+    }
+  }
+  const double bs = block_sum(inner, red);
+  if (tid == 0) inner_part[blockIdx.x] = bs;
+  for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blockIdx.x * RP + c] = sCnt[c];
+  // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
+  constexpr int n16 = RP / 16;
+  float *gp = gpart + (long long)blockIdx.x * RP * RP;
+  for (int t = wv; t < n16 * n16; t += 4) {
+    const int ti_ = t / n16, tj = t % n16;
+    if (ti_ > tj) continue;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Cf::RB; k0 += 4) {
+      const float a = sA[(k0 + (lane >> 4)) * Cf::STR + ti_ * 16 + (lane & 15)];
+      const float b = sA[(k0 + (lane >> 4)) * Cf::STR + tj * 16 + (lane & 15)];
+      acc = mfma4(a, b, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = acc[v];
+  }
+}
+
+// Gram partials of an arbitrary factor (initialisation, set_factor).
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *__restrict__ A,
+                                                           float *__restrict__ gpart) {
+  using Cf = UCfg<RP>;
+  __shared__ float sA[Cf::RB * Cf::STR];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  load_rows<RP>(sA, A, blockIdx.x * Cf::RB, I);
+  __syncthreads();
+  constexpr int n16 = RP / 16;
+  float *gp = gpart + (long long)blockIdx.x * RP * RP;
+  for (int t = wv; t < n16 * n16; t += 4) {
+    const int ti_ = t / n16, tj = t % n16;
+    if (ti_ > tj) continue;
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Cf::RB; k0 += 4) {
+      const float a = sA[(k0 + (lane >> 4)) * Cf::STR + ti_ * 16 + (lane & 15)];
+      const float b = sA[(k0 + (lane >> 4)) * Cf::STR + tj * 16 + (lane & 15)];
+      acc = mfma4(a, b, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = acc[v];
+  }
+}
+
+// Gram reduction: 64 entries (i <= j) per block, 4 threads per entry, FP64.
+// The last block to arrive forms the objective
+//   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
+// and the selection counts.
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_gram_final(int nparts, const float *__restrict__ gpart,
+                                                         double *Gn, const double *G0, const double *G1,
+                                                         const double *G2,
+                                                         const double *__restrict__ inner_part,
+                                                         const int *__restrict__ cnt_part,
+                                                         long long *__restrict__ colcnt, double normX2,
+                                                         int with_f, ModeState *st) {
+  __shared__ double red[kThreads];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  const int e = blockIdx.x * 64 + tid / 4, part = tid % 4;
+  const int i = e / RP, j = e % RP;
+  const bool act = e < RP * RP && i <= j;
+  double s = 0.0;
+  if (act)
+    for (int b = part; b < nparts; b += 4) s += (double)gpart[(long long)b * RP * RP + i * RP + j];
+  red[tid] = s;
+  __syncthreads();
+  if (part == 0 && act) {
+    const double tot = (red[tid] + red[tid + 1]) + (red[tid + 2] + red[tid + 3]);
+    Gn[i * RP + j] = tot;
+    Gn[j * RP + i] = tot;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->cnt_gram, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (with_f) {
+    double mn = 0.0;
+    for (int x = tid; x < RP * RP; x += kThreads)
+      mn += ld_coherent(&G0[x]) * ld_coherent(&G1[x]) * ld_coherent(&G2[x]);
+    const double model = block_sum(mn, red);
+    double in = 0.0;
+    for (int b = tid; b < nparts; b += kThreads) in += inner_part[b];
+    const double inner = block_sum(in, red);
+    if (tid == 0) {
+      st->inner = inner;
+      st->f = normX2 - 2.0 * inner + model;
+    }
+  }
+  if (cnt_part) {
+    long long tot = 0;
+    for (int c = tid; c < RP; c += kThreads) {
+      long long cnt = 0;
+      for (int b = 0; b < nparts; ++b) cnt += cnt_part[(long long)b * RP + c];
+      colcnt[c] = cnt;
+      tot += cnt;
+    }
+    const double all = block_sum((double)tot, red);
+    if (tid == 0) st->nsel = (long long)all;
+  }
+  if (tid == 0) st->cnt_gram = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_factor(float *__restrict__ A, int I, int R, int RP,
+                                                          unsigned long long seed,
+                                                          unsigned long long offset) {
+  const long long n = (long long)I * RP;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (long long)gridDim.x * blockDim.x) {
+    const long long q = x / RP;
+    const int c = (int)(x % RP);
+    float v = 0.0f;
+    if (c < R) {
+      // output number e of SplitMix64(seed): mix(seed + (e + 1) * golden gamma)
+      const unsigned long long e = offset + (unsigned long long)q * R + c;
+      unsigned long long z = seed + (e + 1ull) * 0x9E3779B97F4A7C15ull;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      v = (float)(z >> 40) * (1.0f / 16777216.0f);
+    }
+    A[x] = v;
+  }
+}
+
+// <X, Xhat> = sum over Omega of x * sum_r A0[i0,r] A1[i1,r] A2[i2,r] (eq. 8),
+// FP64; the last block reduces the block partials in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_inner_full(const unsigned long long *__restrict__ keys,
+                                                         const float *__restrict__ vals, long long nnz,
+                                                         KeyLayout lay, int RP,
+                                                         const float *__restrict__ A0,
+                                                         const float *__restrict__ A1,
+                                                         const float *__restrict__ A2,
+                                                         double *__restrict__ part, double *out,
+                                                         unsigned *counter) {
+  __shared__ double red[kThreads];
+  __shared__ int s_last;
+  double s = 0.0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nnz;
+       p += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long k = keys[p];
+    const long long i0 = (long long)(k >> lay.sh_n), i1 = (long long)((k >> lay.sh_a) & lay.mask_a),
+                    i2 = (long long)(k & lay.mask_b);
+    double xh = 0.0;
+    for (int r = 0; r < RP; ++r)
+      xh += (double)A0[i0 * RP + r] * (double)A1[i1 * RP + r] * (double)A2[i2 * RP + r];
+    s += (double)vals[p] * xh;
+  }
+  const double bs = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) t += ld_coherent(&part[i]);
+  const double tot = block_sum(t, red);
+  if (threadIdx.x == 0) {
+    *out = tot;
+    *counter = 0;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_rows(const float *__restrict__ src, int ss,
+                                                        float *__restrict__ dst, int ds, int I,
+                                                        int ncols, int zero_to) {
+  const long long n = (long long)I * zero_to;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (long long)gridDim.x * blockDim.x) {
+    const long long q = x / zero_to;
+    const int c = (int)(x % zero_to);
+    dst[q * ds + c] = (c < ncols) ? src[q * ss + c] : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_check_factor(const float *__restrict__ a, long long n,
+                                                           int *flag) {
+  int bad = 0;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+       x += (long long)gridDim.x * blockDim.x) {
+    const float v = a[x];
+    if (!isfinite(v)) bad |= 2;
+    else if (v < 0.0f) bad |= 1;
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+inline int grid_for(long long n, int per_block = kThreads * 4, int cap = 65535 * 4) {
+  long long g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+int rows_per_block(int RP) {
+  switch (RP) {
+    case 16: return UCfg<16>::RB;
+    case 32: return UCfg<32>::RB;
+    case 64: return UCfg<64>::RB;
+    case 128: return UCfg<128>::RB;
+    default: return 0;
+  }
+}
+
+hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long seed,
+                              unsigned long long offset, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_factor, dim3(grid_for((long long)I * RP)), dim3(kThreads), 0, s, A, I, R,
+                     RP, seed, offset);
+  return hipGetLastError();
+}
+
+template <int RP>
+static hipError_t imp_t(int I, const float *A, const float *M, const float *H, const HInfo *hinfo,
+                        double *ti_part, ModeState *st, hipStream_t s) {
+  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
+  hipLaunchKernelGGL(k_importance<RP>, dim3(nb), dim3(kThreads), 0, s, I, A, M, H, hinfo, ti_part, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_importance(int RP, int I, const float *A, const float *M, const float *H,
+                             const HInfo *hinfo, double *ti_part, ModeState *st, hipStream_t s) {
+  switch (RP) {
+    case 16: return imp_t<16>(I, A, M, H, hinfo, ti_part, st, s);
+    case 32: return imp_t<32>(I, A, M, H, hinfo, ti_part, st, s);
+    case 64: return imp_t<64>(I, A, M, H, hinfo, ti_part, st, s);
+    case 128: return imp_t<128>(I, A, M, H, hinfo, ti_part, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RP, int UPD, bool DIAG>
+static hipError_t upd_t3(int I, float *A, const float *M, float *Z, const float *H, const HInfo *hinfo,
+                         const ModeState *st, float *gpart, double *inner_part, int *cnt_part,
+                         uint8_t *selmask, hipStream_t s) {
+  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
+  hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG>), dim3(nb), dim3(kThreads), 0, s, I, A, M, Z, H,
+                     hinfo, st, gpart, inner_part, cnt_part, selmask);
+  return hipGetLastError();
+}
+
+template <int RP>
+static hipError_t upd_t(int update, bool diag, int I, float *A, const float *M, float *Z, const float *H,
+                        const HInfo *hinfo, const ModeState *st, float *gpart, double *inner_part,
+                        int *cnt_part, uint8_t *selmask, hipStream_t s) {
+  if (update == 0)
+    return diag ? upd_t3<RP, 0, true>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s)
+                : upd_t3<RP, 0, false>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+  return diag ? upd_t3<RP, 1, true>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s)
+              : upd_t3<RP, 1, false>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+}
+
+hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, const float *M,
+                                float *Z, const float *H, const HInfo *hinfo, const ModeState *st,
+                                float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
+                                hipStream_t s) {
+  switch (RP) {
+    case 16: return upd_t<16>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+    case 32: return upd_t<32>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+    case 64: return upd_t<64>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+    case 128: return upd_t<128>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RP>
+static hipError_t gp_t(int I, const float *A, float *gpart, hipStream_t s) {
+  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
+  hipLaunchKernelGGL(k_gram_partial<RP>, dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s) {
+  switch (RP) {
+    case 16: return gp_t<16>(I, A, gpart, s);
+    case 32: return gp_t<32>(I, A, gpart, s);
+    case 64: return gp_t<64>(I, A, gpart, s);
+    case 128: return gp_t<128>(I, A, gpart, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RP>
+static hipError_t gf_t(int nparts, const float *gpart, double *Gn, const double *G0, const double *G1,
+                       const double *G2, const double *inner_part, const int *cnt_part, long long *colcnt,
+                       double normX2, int with_f, ModeState *st, hipStream_t s) {
+  const int nb = (RP * RP + 63) / 64;
+  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb), dim3(kThreads), 0, s, nparts, gpart, Gn, G0, G1, G2,
+                     inner_part, cnt_part, colcnt, normX2, with_f, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_final(int RP, int nparts, const float *gpart, double *Gn, const double *G0,
+                             const double *G1, const double *G2, const double *inner_part,
+                             const int *cnt_part, long long *colcnt, double normX2, int with_f,
+                             ModeState *st, hipStream_t s) {
+  switch (RP) {
+    case 16: return gf_t<16>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 32: return gf_t<32>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 64: return gf_t<64>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 128: return gf_t<128>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,
+                             KeyLayout lay0, int RP, const float *A0, const float *A1, const float *A2,
+                             double *partials, int nparts, double *out, unsigned *counter,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_inner_full, dim3(nparts), dim3(kThreads), 0, s, keys0, vals0, nnz, lay0, RP, A0,
+                     A1, A2, partials, out, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const float *src, int src_stride, float *dst, int dst_stride, int I,
+                            int ncols, int zero_cols_to, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((long long)I * zero_cols_to)), dim3(kThreads), 0, s, src,
+                     src_stride, dst, dst_stride, I, ncols, zero_cols_to);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_factor(const float *src, long long n, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_factor, dim3(grid_for(n)), dim3(kThreads), 0, s, src, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace sacd

@@ -60,21 +60,32 @@ def zipf_indices(rng: np.random.Generator, n: int, length: int, alpha: float) ->
 
 def _draw_distinct(rng, dims, nnz, draw_coords, max_rounds: int = 64):
     """Draw coordinates with ``draw_coords(n)`` until ``nnz`` distinct ones
-    exist (top-up rounds), keeping first draws in draw order."""
-    idx = np.empty((0, 3), np.int32)
+    exist, keeping first draws in draw order.  Each top-up round draws
+    enough for the acceptance rate seen in the previous round."""
+    parts = []
+    seen = np.empty(0, np.int64)  # sorted keys accepted so far
     need = nnz
+    rate = 1.0
     rounds = 0
-    while need > 0:
-        if rounds >= max_rounds:
-            break
-        # over-draw a little to limit the number of top-up rounds
-        batch = draw_coords(max(need + need // 8, 16))
-        idx = np.concatenate([idx, batch])
-        keep = _dedup_keep_first(idx, dims)
-        idx = idx[keep]
-        need = nnz - idx.shape[0]
+    while need > 0 and rounds < max_rounds:
+        n_draw = int(min(max(need / max(rate, 1e-3) * 1.1 + 16, need), 4 * nnz + 16))
+        batch = draw_coords(n_draw)
+        k = _linear(batch, dims)
+        _, first = np.unique(k, return_index=True)
+        first.sort()
+        batch, k = batch[first], k[first]
+        if seen.size:
+            pos = np.searchsorted(seen, k)
+            hit = seen[np.minimum(pos, seen.size - 1)] == k
+            batch, k = batch[~hit], k[~hit]
+        rate = max(k.size / n_draw, 1e-3)
+        batch, k = batch[:need], k[:need]
+        parts.append(batch)
+        seen = np.sort(np.concatenate([seen, k]))
+        need -= batch.shape[0]
         rounds += 1
-    return idx[:nnz], rounds
+    idx = np.concatenate(parts) if parts else np.empty((0, 3), np.int32)
+    return idx, rounds
 
 
 def uniform_distinct_linear(dims, nnz: int, seed: int, values: str = "int1to5") -> TensorCOO:

@@ -1,0 +1,307 @@
+"""Thin Python binding of libsacd (include/sacd.h).
+
+Argument marshalling only: every step of SaCD runs in the HIP library.
+PyTorch provides device memory (through the allocator callback) and the HIP
+stream the library orders its work on.  The library must be built
+(``python -m paper_2003_03572_amd.build``); loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libsacd.so")
+
+PREC_FP32 = 0
+PREC_MIXED_BF16 = 1
+UPDATE_GS = 0
+UPDATE_JACOBI = 1
+
+KERNEL_MTTKRP = 0
+KERNEL_UPDATE = 1
+KERNEL_IMPORTANCE = 2
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "index out of range", -3: "out of device memory",
+           -4: "bad state", -5: "device error", -6: "non-finite or degenerate value"}
+
+
+class SacdError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__(f"{what}: {_STATUS.get(status, status)} ({detail})")
+        self.status = status
+
+
+class _Stats(C.Structure):
+    _fields_ = [("k", C.c_int64), ("lipschitz", C.c_double), ("ti", C.c_double),
+                ("flip", C.c_int32), ("n_selected", C.c_int64), ("objective", C.c_double)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("release", _RELEASE_FN), ("user", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsacd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libsacd.so is not built ({LIB_PATH}); run "
+                               "python -m paper_2003_03572_amd.build")
+        L = C.CDLL(LIB_PATH)
+        p, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "sacd_create_tensor": [p, i64, p, p, p, p, C.POINTER(p)],
+            "sacd_tensor_info": [p, p, p, p, p],
+            "sacd_tensor_mode_coo": [p, i32, p, p, p],
+            "sacd_init_factors": [p, i32, C.c_uint64, C.c_int, C.c_int, C.POINTER(p)],
+            "sacd_sweep": [p, i32],
+            "sacd_iterate": [p, i32],
+            "sacd_fit": [p, p, p],
+            "sacd_run_until": [p, dbl, i32, p, p],
+            "sacd_get_factor": [p, i32, p],
+            "sacd_set_factor": [p, i32, p],
+            "sacd_get_state": [p, i32, p, p, p],
+            "sacd_set_state": [p, i32, p, dbl, i64],
+            "sacd_get_stats": [p, i32, p],
+            "sacd_get_diagnostics": [p, i32, p, p, p],
+            "sacd_set_diagnostics": [p, i32],
+            "sacd_time_kernel": [p, i32, i32, i32, p],
+            "sacd_kernel_bytes": [p, i32, i32, p],
+            "sacd_model_bytes": [p, p],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.sacd_destroy_tensor.argtypes = [p]
+        L.sacd_destroy_tensor.restype = None
+        L.sacd_destroy_model.argtypes = [p]
+        L.sacd_destroy_model.restype = None
+        L.sacd_last_error.restype = C.c_char_p
+        L.sacd_status_string.restype = C.c_char_p
+        L.sacd_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise SacdError(rc, what, lib().sacd_last_error().decode(errors="replace"))
+
+
+def _dptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class TorchAllocator:
+    """Device allocator backed by torch's caching allocator."""
+
+    def __init__(self, device: torch.device):
+        self.device = device
+        self.live = {}
+        self._alloc = _ALLOC_FN(self._do_alloc)
+        self._release = _RELEASE_FN(self._do_release)
+        self.struct = _Allocator(self._alloc, self._release, None)
+
+    def _do_alloc(self, nbytes, user):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: the library reports SACD_ERR_NO_MEMORY
+            return None
+        ptr = t.data_ptr()
+        self.live[ptr] = t
+        return ptr
+
+    def _do_release(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+class Tensor:
+    """A sparse 3-way tensor resident on the GPU (sacd_create_tensor)."""
+
+    def __init__(self, dims: Sequence[int], idx: torch.Tensor, vals: torch.Tensor,
+                 stream: Optional[torch.cuda.Stream] = None, torch_allocator: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the SaCD library runs on the GPU only")
+        self.device = idx.device if idx.is_cuda else torch.device("cuda", torch.cuda.current_device())
+        idx = idx.to(self.device, torch.int32).contiguous().view(-1, 3)
+        vals = vals.to(self.device, torch.float32).contiguous().view(-1)
+        if idx.shape[0] != vals.shape[0]:
+            raise ValueError("idx and vals disagree on nnz")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.alloc = TorchAllocator(self.device) if torch_allocator else None
+        d = (C.c_int64 * 3)(*[int(x) for x in dims])
+        h = C.c_void_p()
+        # the input must be complete before the library's stream reads it
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().sacd_create_tensor(d, idx.shape[0], _dptr(idx), _dptr(vals),
+                                        C.byref(self.alloc.struct) if self.alloc else None,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+               "sacd_create_tensor")
+        self._h = h
+        self._models = 0
+
+    @classmethod
+    def from_numpy(cls, dims, idx: np.ndarray, vals: np.ndarray, **kw) -> "Tensor":
+        dev = torch.device("cuda", torch.cuda.current_device())
+        return cls(dims, torch.from_numpy(np.ascontiguousarray(idx, np.int32)).to(dev),
+                   torch.from_numpy(np.ascontiguousarray(vals, np.float32)).to(dev), **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sacd_destroy_tensor(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        d = (C.c_int64 * 3)()
+        nnz, n2, by = C.c_int64(), C.c_double(), C.c_int64()
+        _check(lib().sacd_tensor_info(self._h, d, C.byref(nnz), C.byref(n2), C.byref(by)),
+               "sacd_tensor_info")
+        return dict(dims=tuple(d), nnz=nnz.value, norm2=n2.value, device_bytes=by.value)
+
+    @property
+    def dims(self) -> Tuple[int, int, int]:
+        return self.info()["dims"]
+
+    @property
+    def nnz(self) -> int:
+        return self.info()["nnz"]
+
+    @property
+    def norm2(self) -> float:
+        return self.info()["norm2"]
+
+    def mode_coo(self, mode: int):
+        info = self.info()
+        nnz = info["nnz"]
+        coords = torch.empty((max(nnz, 1), 3), dtype=torch.int32, device=self.device)
+        vals = torch.empty(max(nnz, 1), dtype=torch.float32, device=self.device)
+        ptr = torch.empty(info["dims"][mode] + 1, dtype=torch.int64, device=self.device)
+        _check(lib().sacd_tensor_mode_coo(self._h, mode, _dptr(coords), _dptr(vals), _dptr(ptr)),
+               "sacd_tensor_mode_coo")
+        return coords[:nnz], vals[:nnz], ptr
+
+
+class Model:
+    """SaCD model of rank R over a Tensor (sacd_init_factors)."""
+
+    def __init__(self, tensor: Tensor, rank: int, seed: int, precision: int = PREC_FP32,
+                 update: int = UPDATE_GS):
+        self.t = tensor
+        self.R = int(rank)
+        h = C.c_void_p()
+        _check(lib().sacd_init_factors(tensor._h, self.R, C.c_uint64(seed), precision, update,
+                                       C.byref(h)), "sacd_init_factors")
+        self._h = h
+        self.dims = tensor.dims
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sacd_destroy_model(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, mode: int):
+        _check(lib().sacd_sweep(self._h, mode), "sacd_sweep")
+
+    def iterate(self, n: int = 1):
+        _check(lib().sacd_iterate(self._h, n), "sacd_iterate")
+
+    def fit(self) -> Tuple[float, float]:
+        fit, f = C.c_double(), C.c_double()
+        _check(lib().sacd_fit(self._h, C.byref(fit), C.byref(f)), "sacd_fit")
+        return fit.value, f.value
+
+    def run_until(self, tol: float, max_iter: int) -> Tuple[int, float]:
+        it, fit = C.c_int32(), C.c_double()
+        _check(lib().sacd_run_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit)),
+               "sacd_run_until")
+        return it.value, fit.value
+
+    def factor(self, mode: int) -> torch.Tensor:
+        out = torch.empty((self.dims[mode], self.R), dtype=torch.float32, device=self.t.device)
+        _check(lib().sacd_get_factor(self._h, mode, _dptr(out)), "sacd_get_factor")
+        return out
+
+    def set_factor(self, mode: int, A: torch.Tensor):
+        A = A.to(self.t.device, torch.float32).contiguous()
+        if tuple(A.shape) != (self.dims[mode], self.R):
+            raise ValueError("factor shape mismatch")
+        torch.cuda.current_stream(self.t.device).synchronize()
+        _check(lib().sacd_set_factor(self._h, mode, _dptr(A)), "sacd_set_factor")
+
+    def state(self, mode: int):
+        zp = torch.empty((self.dims[mode], self.R), dtype=torch.float32, device=self.t.device)
+        ti, k = C.c_double(), C.c_int64()
+        _check(lib().sacd_get_state(self._h, mode, _dptr(zp), C.byref(ti), C.byref(k)),
+               "sacd_get_state")
+        return zp, ti.value, k.value
+
+    def set_state(self, mode: int, zprev: torch.Tensor, ti_prev: float, k: int):
+        zp = zprev.to(self.t.device, torch.float32).contiguous()
+        if tuple(zp.shape) != (self.dims[mode], self.R):
+            raise ValueError("zprev shape mismatch")
+        torch.cuda.current_stream(self.t.device).synchronize()
+        _check(lib().sacd_set_state(self._h, mode, _dptr(zp), float(ti_prev), int(k)),
+               "sacd_set_state")
+
+    def stats(self, mode: int) -> dict:
+        s = _Stats()
+        _check(lib().sacd_get_stats(self._h, mode, C.byref(s)), "sacd_get_stats")
+        return dict(k=s.k, L=s.lipschitz, ti=s.ti, flip=bool(s.flip), nsel=s.n_selected,
+                    f=s.objective)
+
+    def set_diagnostics(self, on: bool):
+        _check(lib().sacd_set_diagnostics(self._h, int(bool(on))), "sacd_set_diagnostics")
+
+    def diagnostics(self, mode: int):
+        I = self.dims[mode]
+        M = torch.empty((I, self.R), dtype=torch.float32, device=self.t.device)
+        sel = torch.empty((I, self.R), dtype=torch.uint8, device=self.t.device)
+        G = np.empty((self.R, self.R), np.float64)
+        _check(lib().sacd_get_diagnostics(self._h, mode, _dptr(M), _dptr(sel),
+                                          G.ctypes.data_as(C.c_void_p)), "sacd_get_diagnostics")
+        return M, sel.bool(), G
+
+    def time_kernel(self, which: int, mode: int, reps: int) -> float:
+        ms = C.c_float()
+        _check(lib().sacd_time_kernel(self._h, which, mode, reps, C.byref(ms)), "sacd_time_kernel")
+        return ms.value
+
+    def kernel_bytes(self, which: int, mode: int) -> float:
+        b = C.c_double()
+        _check(lib().sacd_kernel_bytes(self._h, which, mode, C.byref(b)), "sacd_kernel_bytes")
+        return b.value
+
+    def device_bytes(self) -> int:
+        b = C.c_int64()
+        _check(lib().sacd_model_bytes(self._h, C.byref(b)), "sacd_model_bytes")
+        return b.value
+
+    def synchronize(self):
+        self.t.stream.synchronize()

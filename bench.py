@@ -72,7 +72,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--data-cache", default="",
+                    help="directory to keep the generated tensor in (reused when present)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
@@ -87,7 +101,17 @@ def main():
     sacd.lib()
     w = getattr(gen, WORKLOADS[args.workload])
     t0 = time.perf_counter()
-    dims, idx, vals = gen.make(w)
+    cache = os.path.join(args.data_cache, w.name + ".npz") if args.data_cache else None
+    if cache and os.path.exists(cache):
+        import numpy as np
+        z = np.load(cache)
+        dims, idx, vals = tuple(int(d) for d in z["dims"]), z["idx"], z["vals"]
+    else:
+        dims, idx, vals = gen.make(w)
+        if cache:
+            import numpy as np
+            os.makedirs(args.data_cache, exist_ok=True)
+            np.savez(cache, dims=np.array(dims), idx=idx, vals=vals)
     log(f"[bench] generated {w.name}: dims {dims}, nnz {idx.shape[0]} in {time.perf_counter() - t0:.1f} s")
 
     t0 = time.perf_counter()

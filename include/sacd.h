@@ -114,6 +114,8 @@ sacd_status sacd_tensor_info(const sacd_tensor *t, int64_t dims[3], int64_t *nnz
 sacd_status sacd_tensor_mode_coo(const sacd_tensor *t, int32_t mode, int32_t *coords, float *vals,
                                  int64_t *ptr);
 
+/* Release the tensor.  While models built on it are alive, the release is
+ * deferred until the last of them is destroyed. */
 void sacd_destroy_tensor(sacd_tensor *t);
 
 /* ------------------------------------------------------------------------ */

@@ -74,6 +74,7 @@ def lib():
         L.ora_model_set_tie_tol.restype = None
         L.ora_sweep.argtypes = [p, i32]
         L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p, p]
+        L.ora_sweep_alternatives.argtypes = [p, i32, p, p, p, p, p, p]
         L.ora_objective.argtypes = [p]
         L.ora_objective.restype = dbl
         L.ora_fit.argtypes = [p, p, p]
@@ -219,12 +220,39 @@ class Model:
         sel = np.empty((I, R), np.uint8)
         tie = np.empty((I, R), np.uint8)
         H = np.empty((R, R), np.float64)
-        sc = np.empty(6, np.float64)
+        sc = np.empty(8, np.float64)
         _check(lib().ora_sweep_info(self._h, mode, _ptr(M), _ptr(G0), _ptr(z), _ptr(sel),
                                     _ptr(tie), _ptr(H), _ptr(sc)), "sweep_info")
         return dict(M=M, G0=G0, z=z, sel=sel.astype(bool), tie=tie.astype(bool), H=H,
                     L=sc[0], ti=sc[1], flip=bool(sc[2]), tie_global=bool(sc[3]), f=sc[4],
-                    nsel=int(sc[5]))
+                    nsel=int(sc[5]), inner=sc[6], model=sc[7])
+
+    def alternatives(self, mode: int) -> dict:
+        """Valid outcomes of the rows holding tie elements in the last sweep
+        of `mode`: {row: (tie_cols, outcomes)} with outcomes an array of
+        shape (2^t, R); outcome c takes decision (c >> j) & 1 for tie_cols[j].
+        Rows with more than 6 tie elements map to (tie_cols, None)."""
+        nr, ne = C.c_int64(), C.c_int64()
+        _check(lib().ora_sweep_alternatives(self._h, mode, C.byref(nr), C.byref(ne), None, None,
+                                            None, None), "alternatives")
+        nr, ne = nr.value, ne.value
+        if nr == 0:
+            return {}
+        rows = np.empty(nr, np.int64)
+        ntie = np.empty(nr, np.int32)
+        cols = np.empty((nr, 6), np.int32)
+        vals = np.empty((max(ne, 1), self.R), np.float64)
+        _check(lib().ora_sweep_alternatives(self._h, mode, None, None, _ptr(rows), _ptr(ntie),
+                                            _ptr(cols), _ptr(vals)), "alternatives")
+        out, off = {}, 0
+        for k in range(nr):
+            t = int(ntie[k])
+            if t < 0:
+                out[int(rows[k])] = (None, None)
+                continue
+            out[int(rows[k])] = (cols[k, :t].copy(), vals[off:off + (1 << t)].copy())
+            off += 1 << t
+        return out
 
     def objective(self) -> float:
         return float(lib().ora_objective(self._h))

@@ -254,8 +254,16 @@ struct ora_model {
   float *z[3];
   uint8_t *sel[3], *tie[3];
   double *H[3];
-  double info[3][6];
+  double info[3][8];
+  /* valid outcomes of the rows holding tie elements (last sweep per mode) */
+  int64_t alt_nrows[3], alt_nent[3];
+  int64_t *alt_row[3];
+  int32_t *alt_ntie[3];
+  int32_t *alt_cols[3]; /* alt_nrows x ORA_MAX_TIE */
+  double *alt_vals[3];  /* alt_nent x R */
 };
+
+#define ORA_MAX_TIE 6
 
 void ora_model_destroy(ora_model *m) {
   if (!m) return;
@@ -263,6 +271,7 @@ void ora_model_destroy(ora_model *m) {
     free(m->A[n]); free(m->G[n]); free(m->zprev[n]);
     free(m->M[n]); free(m->G0[n]); free(m->z[n]);
     free(m->sel[n]); free(m->tie[n]); free(m->H[n]);
+    free(m->alt_row[n]); free(m->alt_ntie[n]); free(m->alt_cols[n]); free(m->alt_vals[n]);
   }
   free(m);
 }
@@ -382,6 +391,26 @@ int ora_fit(const ora_model *m, double *fit, double *f) {
   return ORA_OK;
 }
 
+/* Update of one row's selected elements (step 9 below).  a: the row (R
+ * values, updated in place); sel: decisions; M, delta: the row's MTTKRP and
+ * snapshot steps; H: R x R. */
+static void update_row(double *a, const uint8_t *sel, const double *M, const double *delta,
+                       const double *H, int R, int rule) {
+  if (rule == ORA_UPDATE_GS) {
+    for (int r = 0; r < R; ++r) {
+      const double h = H[r * R + r];
+      if (!sel[r] || !(h > 0.0)) continue;
+      double g = -M[r];
+      for (int s = 0; s < R; ++s) g += a[s] * H[s * R + r];
+      const double u = a[r] - g / h;
+      a[r] = u > 0.0 ? u : 0.0;
+    }
+  } else {
+    for (int r = 0; r < R; ++r)
+      if (sel[r]) a[r] += delta[r];
+  }
+}
+
 /*
  * One sweep of mode n: the body of Alg. 1 for one factor matrix.
  *
@@ -488,23 +517,61 @@ int ora_sweep(ora_model *m, int mode) {
   memcpy(zprev, z, (size_t)I * R * sizeof(float));
   m->ti_prev[mode] = ti;
 
-  /* 9 */
-  if (m->update_rule == ORA_UPDATE_GS) {
-    for (int64_t q = 0; q < I; ++q) {
-      for (int r = 0; r < R; ++r) {
-        const int64_t e = q * R + r;
-        const double h = H[r * R + r];
-        if (!sel[e] || !(h > 0.0)) continue;
-        double g = -M[e];
-        for (int s = 0; s < R; ++s) g += A[q * R + s] * H[s * R + r];
-        const double u = A[e] - g / h;
-        A[e] = u > 0.0 ? u : 0.0;
-      }
+  /* Valid outcomes of rows with tie elements: a decision inside the tie
+   * band may go either way, and rows are independent in step 9, so each such
+   * row's outcome is computed for every combination of its tie decisions. */
+  free(m->alt_row[mode]); free(m->alt_ntie[mode]); free(m->alt_cols[mode]); free(m->alt_vals[mode]);
+  m->alt_row[mode] = NULL; m->alt_ntie[mode] = NULL; m->alt_cols[mode] = NULL; m->alt_vals[mode] = NULL;
+  int64_t nrows = 0, nent = 0;
+  for (int64_t q = 0; q < I; ++q) {
+    int t = 0;
+    for (int r = 0; r < R; ++r) t += tie[q * R + r];
+    if (t > 0) {
+      ++nrows;
+      if (t <= ORA_MAX_TIE) nent += (int64_t)1 << t;
     }
-  } else {
-    for (int64_t e = 0; e < I * R; ++e)
-      if (sel[e]) A[e] += delta[e];
   }
+  m->alt_nrows[mode] = nrows;
+  m->alt_nent[mode] = nent;
+  if (nrows > 0) {
+    m->alt_row[mode] = (int64_t *)malloc((size_t)nrows * sizeof(int64_t));
+    m->alt_ntie[mode] = (int32_t *)malloc((size_t)nrows * sizeof(int32_t));
+    m->alt_cols[mode] = (int32_t *)malloc((size_t)nrows * ORA_MAX_TIE * sizeof(int32_t));
+    m->alt_vals[mode] = (double *)malloc((size_t)(nent > 0 ? nent : 1) * R * sizeof(double));
+    uint8_t *sel2 = (uint8_t *)malloc((size_t)R);
+    if (!m->alt_row[mode] || !m->alt_ntie[mode] || !m->alt_cols[mode] || !m->alt_vals[mode] || !sel2) {
+      free(sel2); free(delta); free(scale); return ORA_ENOMEM;
+    }
+    int64_t k_row = 0, k_ent = 0;
+    for (int64_t q = 0; q < I; ++q) {
+      int t = 0;
+      int32_t *cols = m->alt_cols[mode] + k_row * ORA_MAX_TIE;
+      for (int r = 0; r < R; ++r)
+        if (tie[q * R + r]) {
+          if (t < ORA_MAX_TIE) cols[t] = r;
+          ++t;
+        }
+      if (t == 0) continue;
+      m->alt_row[mode][k_row] = q;
+      m->alt_ntie[mode][k_row] = (t <= ORA_MAX_TIE) ? t : -t;
+      if (t <= ORA_MAX_TIE) {
+        for (int64_t c = 0; c < ((int64_t)1 << t); ++c) {
+          double *out = m->alt_vals[mode] + k_ent * R;
+          memcpy(sel2, sel + q * R, (size_t)R);
+          for (int j = 0; j < t; ++j) sel2[cols[j]] = (uint8_t)((c >> j) & 1);
+          memcpy(out, A + q * R, (size_t)R * sizeof(double));
+          update_row(out, sel2, M + q * R, delta + q * R, H, R, m->update_rule);
+          ++k_ent;
+        }
+      }
+      ++k_row;
+    }
+    free(sel2);
+  }
+
+  /* 9 */
+  for (int64_t q = 0; q < I; ++q)
+    update_row(A + q * R, sel + q * R, M + q * R, delta + q * R, H, R, m->update_rule);
   free(delta);
   free(scale);
 
@@ -524,6 +591,22 @@ int ora_sweep(ora_model *m, int mode) {
   m->info[mode][3] = (double)tie_global;
   m->info[mode][4] = f;
   m->info[mode][5] = (double)nsel;
+  m->info[mode][6] = inner;
+  m->info[mode][7] = model;
+  return ORA_OK;
+}
+
+int ora_sweep_alternatives(const ora_model *m, int mode, int64_t *n_rows, int64_t *n_entries,
+                           int64_t *rows, int32_t *ntie, int32_t *cols, double *vals) {
+  if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
+  if (n_rows) *n_rows = m->alt_nrows[mode];
+  if (n_entries) *n_entries = m->alt_nent[mode];
+  const int64_t nr = m->alt_nrows[mode], ne = m->alt_nent[mode];
+  if (nr == 0) return ORA_OK;
+  if (rows) memcpy(rows, m->alt_row[mode], (size_t)nr * sizeof(int64_t));
+  if (ntie) memcpy(ntie, m->alt_ntie[mode], (size_t)nr * sizeof(int32_t));
+  if (cols) memcpy(cols, m->alt_cols[mode], (size_t)nr * ORA_MAX_TIE * sizeof(int32_t));
+  if (vals && ne > 0) memcpy(vals, m->alt_vals[mode], (size_t)ne * m->R * sizeof(double));
   return ORA_OK;
 }
 

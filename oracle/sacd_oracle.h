@@ -85,7 +85,16 @@ int ora_sweep(ora_model *m, int mode);
  * the sweep), nsel. */
 int ora_sweep_info(const ora_model *m, int mode, double *M, double *G0,
                    float *z, uint8_t *sel, uint8_t *tie, double *H,
-                   double *scalars /* [L, ti, flip, tie_global, f, nsel] */);
+                   double *scalars /* [L, ti, flip, tie_global, f, nsel, inner, model] */);
+
+/* Valid outcomes of the last sweep's rows that hold tie elements.  For row
+ * rows[k] with ntie[k] = t tie elements at columns cols[k*6 .. k*6+t-1]
+ * (t <= 6; a negative ntie means more than 6, outcomes not enumerated), the
+ * 2^t rows of vals (R values each, consecutive over k) are the updated row
+ * for decision combination c = 0 .. 2^t - 1 (bit j: decision of tie j).
+ * Call first with NULL arrays to get n_rows / n_entries. */
+int ora_sweep_alternatives(const ora_model *m, int mode, int64_t *n_rows, int64_t *n_entries,
+                           int64_t *rows, int32_t *ntie, int32_t *cols, double *vals);
 
 /* Objective eq. 6 (full-tensor least squares) and fit 1 - sqrt(f)/||X||. */
 double ora_objective(const ora_model *m);

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -116,8 +117,10 @@ struct sacd_tensor {
   unsigned long long *keys[3] = {nullptr, nullptr, nullptr};
   float *vals[3] = {nullptr, nullptr, nullptr};
   int *ptr[3] = {nullptr, nullptr, nullptr};
+  std::vector<int> hptr[3];  // host copy of the slice pointers
   double norm2 = 0.0;
-  int nmodels = 0;
+  int nmodels = 0;              // live models built on this tensor
+  bool destroy_pending = false;  // destroyed by the caller while models were live
 };
 
 struct sacd_model {
@@ -134,17 +137,21 @@ struct sacd_model {
   ModeState *st = nullptr;  // 3 entries
   long long *colcnt[3] = {};
   uint8_t *selmask[3] = {};
-  float *carry = nullptr, *gpart = nullptr;
+  float *part = nullptr, *gpart = nullptr;
+  double *g2 = nullptr, *inner2 = nullptr;
+  long long *cnt2 = nullptr;
+  unsigned *ec_counter = nullptr;
   double *ti_part = nullptr, *inner_part = nullptr;
   int *cnt_part = nullptr, *flag = nullptr;
   double *full_part = nullptr, *full_out = nullptr;
   unsigned *full_cnt = nullptr;
   int full_nparts = 0;
-  MttkrpPlan plan[3];
   int nparts[3] = {0, 0, 0};
+  MttkrpPlan plan[3];
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   double *h_pinned = nullptr;
+  bool counted = false;  // included in t->nmodels
   int last_mode = -1;  // mode of the most recent sweep, -1: objective must be recomputed
   bool dirty = true;   // factors changed outside a sweep
 };
@@ -152,6 +159,7 @@ struct sacd_model {
 namespace {
 
 sacd_status enter(int dev) {
+  (void)hipGetLastError();  // drop an error left by an unrelated earlier call
   HIP_TRY(hipSetDevice(dev));
   return SACD_OK;
 }
@@ -169,6 +177,17 @@ sacd_status make_stream(void *stream, hipStream_t *out, bool *own) {
 
 // ---------------------------------------------------------------- sweep ----
 
+GramReduce gram_reduce(const sacd_model *m, int n) {
+  GramReduce g;
+  g.nparts = m->nparts[n];
+  g.gpart = m->gpart;
+  g.g2 = m->g2;
+  g.cnt2 = m->cnt2;
+  g.inner2 = m->inner2;
+  g.ec_counter = m->ec_counter;
+  return g;
+}
+
 sacd_status enqueue_sweep(sacd_model *m, int n) {
   sacd_tensor *t = m->t;
   int a, b;
@@ -176,14 +195,14 @@ sacd_status enqueue_sweep(sacd_model *m, int n) {
   const int I = (int)t->dims[n];
   hipStream_t s = m->s;
   HIP_TRY(launch_mttkrp(m->RP, m->plan[n], t->keys[n], t->vals[n], t->lay[n], m->A[a], m->A[b], m->M[n],
-                        m->carry, s));
-  HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[n], t->keys[n], t->lay[n].sh_n, t->ptr[n], I, m->carry,
-                            m->M[n], m->G64[a], m->G64[b], m->H[n], m->hinfo[n], m->st + n, s));
+                        m->part, s));
+  HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[n], t->ptr[n], I, m->part, m->M[n], m->G64[a], m->G64[b],
+                            m->H[n], m->hinfo[n], m->st + n, s));
   HIP_TRY(launch_importance(m->RP, I, m->A[n], m->M[n], m->H[n], m->hinfo[n], m->ti_part, m->st + n, s));
   HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[n], m->M[n], m->Z[n], m->H[n],
                                m->hinfo[n], m->st + n, m->gpart, m->inner_part, m->cnt_part,
                                m->selmask[n], s));
-  HIP_TRY(launch_gram_final(m->RP, m->nparts[n], m->gpart, m->G64[n], m->G64[0], m->G64[1], m->G64[2],
+  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[0], m->G64[1], m->G64[2],
                             m->inner_part, m->cnt_part, m->colcnt[n], t->norm2, 1, m->st + n, s));
   return SACD_OK;
 }
@@ -191,7 +210,7 @@ sacd_status enqueue_sweep(sacd_model *m, int n) {
 sacd_status recompute_gram(sacd_model *m, int n) {
   const int I = (int)m->t->dims[n];
   HIP_TRY(launch_gram_partial(m->RP, I, m->A[n], m->gpart, m->s));
-  HIP_TRY(launch_gram_final(m->RP, m->nparts[n], m->gpart, m->G64[n], m->G64[0], m->G64[1], m->G64[2],
+  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[0], m->G64[1], m->G64[2],
                             nullptr, nullptr, nullptr, 0.0, 0, m->st + n, m->s));
   return SACD_OK;
 }
@@ -280,6 +299,126 @@ const char *sacd_status_string(sacd_status s) {
 }
 
 // ------------------------------------------------------------------ tensor --
+
+// Work plan of mode m for the MTTKRP kernels: each slice cut into segments
+// of at most kSegment entries, ordered by length (longest first, stable);
+// unit u runs in block u / upb.  Segments of a split slice that sit next to
+// each other in one block form a run that shares one partial slot; the slots
+// of a slice are numbered consecutively.
+static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &mem, MttkrpPlan *out) {
+  const std::vector<int> &ptr = t->hptr[m];
+  const int I = (int)t->dims[m];
+  std::vector<int4> units;
+  std::vector<char> split;
+  for (int r = 0; r < I; ++r) {
+    const int len = ptr[r + 1] - ptr[r];
+    if (len == 0) continue;
+    if (len <= kSegment) {
+      units.push_back(make_int4(r, ptr[r], len, -1));
+      continue;
+    }
+    const int nseg = (len + kSegment - 1) / kSegment;
+    for (int q = 0; q < nseg; ++q) {
+      const int b = ptr[r] + q * kSegment;
+      const int l = (q == nseg - 1) ? ptr[r + 1] - b : kSegment;
+      units.push_back(make_int4(r, b, l, -2));  // -2: segment of a split slice
+    }
+  }
+  // Full-length segments first, ordered by the range of A_a rows they gather
+  // (kGatherBuckets coarse buckets of i_a; within a bucket by slice and
+  // position), so the work in flight together reuses a small part of A_a from
+  // cache; then every shorter unit, longest first.
+  {
+    std::vector<int> pos;
+    for (const int4 &u : units)
+      if (u.z == kSegment) pos.push_back(u.y);
+    std::vector<unsigned long long> first_key(pos.size());
+    if (!pos.empty()) {
+      int *dpos = nullptr;
+      unsigned long long *dkey = nullptr;
+      DevAlloc tmp;
+      tmp.alloc = mem.alloc;
+      tmp.custom = mem.custom;
+      SACD_TRY(tmp.get_t(pos.size(), &dpos));
+      SACD_TRY(tmp.get_t(pos.size(), &dkey));
+      HIP_TRY(hipMemcpyAsync(dpos, pos.data(), sizeof(int) * pos.size(), hipMemcpyHostToDevice, t->stream));
+      HIP_TRY(launch_gather_keys(t->keys[m], dpos, (int)pos.size(), dkey, t->stream));
+      HIP_TRY(hipMemcpyAsync(first_key.data(), dkey, sizeof(unsigned long long) * pos.size(),
+                             hipMemcpyDeviceToHost, t->stream));
+      HIP_TRY(hipStreamSynchronize(t->stream));
+      tmp.release_all();
+    }
+    int a, b;
+    other_modes(m, &a, &b);
+    const long long Ia = t->dims[a];
+    std::vector<std::pair<long long, int4>> full;
+    std::vector<int4> rest;
+    size_t k = 0;
+    for (const int4 &u : units) {
+      if (u.z == kSegment) {
+        const long long ia = (long long)((first_key[k++] >> t->lay[m].sh_a) & t->lay[m].mask_a);
+        full.push_back({ia * kGatherBuckets / Ia, u});
+      } else {
+        rest.push_back(u);
+      }
+    }
+    std::stable_sort(full.begin(), full.end(), [](const std::pair<long long, int4> &x,
+                                                  const std::pair<long long, int4> &y) {
+      if (x.first != y.first) return x.first < y.first;
+      if (x.second.x != y.second.x) return x.second.x < y.second.x;
+      return x.second.y < y.second.y;
+    });
+    std::stable_sort(rest.begin(), rest.end(), [](const int4 &x, const int4 &y) { return x.z > y.z; });
+    units.clear();
+    for (const auto &f : full) units.push_back(f.second);
+    for (const int4 &u : rest) units.push_back(u);
+  }
+  // runs: consecutive units of one split slice inside one block
+  std::vector<int> run_of(units.size(), -1);
+  std::vector<int> run_slice;
+  for (size_t u = 0; u < units.size(); ++u) {
+    if (units[u].w != -2) continue;
+    const bool cont = u > 0 && units[u - 1].w == -2 && units[u - 1].x == units[u].x &&
+                      (u - 1) / upb == u / upb;
+    if (cont) {
+      run_of[u] = run_of[u - 1];
+    } else {
+      run_of[u] = (int)run_slice.size();
+      run_slice.push_back(units[u].x);
+    }
+  }
+  // number the runs slice by slice
+  std::vector<int> order(run_slice.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return run_slice[a] < run_slice[b]; });
+  std::vector<int> slot_of(run_slice.size());
+  std::vector<int4> longs;
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int r = run_slice[order[k]];
+    slot_of[order[k]] = (int)k;
+    if (longs.empty() || longs.back().x != r) longs.push_back(make_int4(r, (int)k, 0, 0));
+    longs.back().z += 1;
+  }
+  for (size_t u = 0; u < units.size(); ++u)
+    if (units[u].w == -2) units[u].w = slot_of[run_of[u]];
+  MttkrpPlan p;
+  p.nnz = t->nnz;
+  p.nunits = (int)units.size();
+  p.nlong = (int)longs.size();
+  p.nslots = (int)run_slice.size();
+  int4 *du = nullptr, *dl = nullptr;
+  SACD_TRY(mem.get_t(units.size() + 1, &du));
+  SACD_TRY(mem.get_t(longs.size() + 1, &dl));
+  if (!units.empty())
+    HIP_TRY(hipMemcpyAsync(du, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, t->stream));
+  if (!longs.empty())
+    HIP_TRY(hipMemcpyAsync(dl, longs.data(), sizeof(int4) * longs.size(), hipMemcpyHostToDevice, t->stream));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  p.units = du;
+  p.longs = dl;
+  *out = p;
+  return SACD_OK;
+}
 
 static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int64_t nnz,
                                       const int32_t *idx, const float *vals) {
@@ -382,6 +521,12 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
   }
   for (int m = 0; m < 3; ++m)
     TMP_HIP(build_ptr(t->keys[m], u, t->lay[m].sh_n, (int)dims[m], t->ptr[m], temp, s));
+  for (int m = 0; m < 3; ++m) {
+    t->hptr[m].resize((size_t)dims[m] + 1);
+    TMP_HIP(hipMemcpyAsync(t->hptr[m].data(), t->ptr[m], sizeof(int) * ((size_t)dims[m] + 1),
+                           hipMemcpyDeviceToHost, s));
+  }
+  TMP_HIP(hipStreamSynchronize(s));
   // ||X||^2
   {
     const int nparts = 512;
@@ -402,6 +547,7 @@ sacd_status sacd_create_tensor(const int64_t dims[3], int64_t nnz, const int32_t
   if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!dims) return fail(SACD_ERR_INVALID_ARG, "dims is NULL");
+  (void)hipGetLastError();
   for (int n = 0; n < 3; ++n)
     if (dims[n] < 1 || dims[n] > 2147483647LL)
       return fail(SACD_ERR_INVALID_ARG, "dims[%d] = %lld not in [1, 2^31 - 1]", n, (long long)dims[n]);
@@ -455,13 +601,21 @@ sacd_status sacd_tensor_mode_coo(const sacd_tensor *t, int32_t mode, int32_t *co
   return SACD_OK;
 }
 
-void sacd_destroy_tensor(sacd_tensor *t) {
-  if (!t) return;
+static void release_tensor(sacd_tensor *t) {
   (void)hipSetDevice(t->dev);
   if (t->stream) (void)hipStreamSynchronize(t->stream);
   t->mem.release_all();
   if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
   delete t;
+}
+
+void sacd_destroy_tensor(sacd_tensor *t) {
+  if (!t) return;
+  if (t->nmodels > 0) {
+    t->destroy_pending = true;  // released with its last model
+    return;
+  }
+  release_tensor(t);
 }
 
 // ------------------------------------------------------------------- model --
@@ -471,12 +625,12 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   const int RP = m->RP;
   DevAlloc &A = m->mem;
   int maxI = 0;
-  long long maxchunks = 1;
+  long long maxslots = 1;
   for (int n = 0; n < 3; ++n) {
     const int I = (int)t->dims[n];
     if (I > maxI) maxI = I;
-    m->plan[n] = mttkrp_plan(RP, t->nnz);
-    if (m->plan[n].nchunks > maxchunks) maxchunks = m->plan[n].nchunks;
+    SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n]));
+    if (m->plan[n].nslots > maxslots) maxslots = m->plan[n].nslots;
     m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
     SACD_TRY(A.get_t((size_t)I * RP, &m->A[n]));
     SACD_TRY(A.get_t((size_t)I * RP, &m->Z[n]));
@@ -489,11 +643,16 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   }
   const int maxparts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
   SACD_TRY(A.get_t(3, &m->st));
-  SACD_TRY(A.get_t((size_t)maxchunks * 2 * RP, &m->carry));
+  SACD_TRY(A.get_t((size_t)maxslots * RP, &m->part));
   SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart));
   SACD_TRY(A.get_t((size_t)maxparts, &m->ti_part));
   SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
   SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
+  const int nb2 = gram_level2_blocks(maxparts);
+  SACD_TRY(A.get_t((size_t)nb2 * RP * RP, &m->g2));
+  SACD_TRY(A.get_t((size_t)nb2 * RP, &m->cnt2));
+  SACD_TRY(A.get_t((size_t)nb2, &m->inner2));
+  SACD_TRY(A.get_t(16, &m->ec_counter));
   SACD_TRY(A.get_t(4, &m->flag));
   m->full_nparts = 1024;
   SACD_TRY(A.get_t((size_t)m->full_nparts, &m->full_part));
@@ -503,6 +662,7 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   hipStream_t s = m->s;
   HIP_TRY(hipMemsetAsync(m->st, 0, 3 * sizeof(ModeState), s));
   HIP_TRY(hipMemsetAsync(m->full_cnt, 0, 16, s));
+  HIP_TRY(hipMemsetAsync(m->ec_counter, 0, 16 * sizeof(unsigned), s));
   unsigned long long off = 0;
   for (int n = 0; n < 3; ++n) {
     const int I = (int)t->dims[n];
@@ -547,6 +707,7 @@ sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_pre
     return st;
   }
   t->nmodels++;
+  m->counted = true;
   m->last_mode = -1;
   m->dirty = true;
   *out = m;
@@ -741,7 +902,7 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   for (int i = 0; i < reps; ++i) {
     if (which == 0)
       HIP_TRY(launch_mttkrp(m->RP, m->plan[mode], t->keys[mode], t->vals[mode], t->lay[mode], m->A[a],
-                            m->A[b], m->M[mode], m->carry, m->s));
+                            m->A[b], m->M[mode], m->part, m->s));
     else if (which == 1)
       HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[mode], m->M[mode], m->Z[mode],
                                    m->H[mode], m->hinfo[mode], m->st + mode, m->gpart, m->inner_part,
@@ -759,8 +920,8 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   *avg_ms = ms / reps;
   if (which == 0) {
     // restore the complete MTTKRP (spanning slices) for later sweeps' diagnostics
-    HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[mode], t->keys[mode], t->lay[mode].sh_n, t->ptr[mode], I,
-                              m->carry, m->M[mode], m->G64[a], m->G64[b], m->H[mode], m->hinfo[mode],
+    HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[mode], t->ptr[mode], I, m->part, m->M[mode], m->G64[a],
+                              m->G64[b], m->H[mode], m->hinfo[mode],
                               m->st + mode, m->s));
   }
   HIP_TRY(hipMemcpyAsync(m->st + mode, &saved, sizeof(ModeState), hipMemcpyHostToDevice, m->s));
@@ -797,13 +958,16 @@ sacd_status sacd_model_bytes(const sacd_model *m, int64_t *bytes) {
 
 void sacd_destroy_model(sacd_model *m) {
   if (!m) return;
-  (void)hipSetDevice(m->t->dev);
+  sacd_tensor *t = m->t;
+  (void)hipSetDevice(t->dev);
   if (m->s) (void)hipStreamSynchronize(m->s);
   drop_graph(m);
   m->mem.release_all();
   if (m->h_pinned) (void)hipHostFree(m->h_pinned);
-  if (m->t && m->t->nmodels > 0) m->t->nmodels--;
+  const bool counted = m->counted;
   delete m;
+  if (counted && t->nmodels > 0) t->nmodels--;
+  if (t->destroy_pending && t->nmodels == 0) release_tensor(t);
 }
 
 }  // extern "C"

@@ -101,6 +101,8 @@ hipError_t launch_rekey(const unsigned long long *keys0, long long n, KeyLayout 
 hipError_t build_ptr(const unsigned long long *keys, long long n, int sh_n, int I, int *ptr,
                      void *temp, hipStream_t s);
 size_t build_ptr_temp_bytes(long long n, int I);
+hipError_t launch_gather_keys(const unsigned long long *keys, const int *pos, int n,
+                              unsigned long long *out, hipStream_t s);
 hipError_t launch_norm2(const float *vals, long long n, double *partials, int nparts, double *out,
                         hipStream_t s);
 hipError_t launch_export_coo(const unsigned long long *keys, const float *vals, long long n,
@@ -108,20 +110,25 @@ hipError_t launch_export_coo(const unsigned long long *keys, const float *vals, 
                              int64_t *ptr64, hipStream_t s);
 
 // mttkrp.hip
+// Static work plan of one mode (built once per tensor from the slice
+// pointers): every slice cut into segments of at most kSegment entries.
+constexpr int kSegment = 256;
+constexpr int kGatherBuckets = 64;  // i_a ranges that order the full-length segments
 struct MttkrpPlan {
   long long nnz;
-  int S;          // entries per lane group
-  long long C;    // entries per wave chunk
-  int nchunks;    // wave chunks
-  int blocks;     // blocks of the main kernel (4 waves each)
+  int nunits;         // work units, longest first
+  const int4 *units;  // device: (slice, first entry, entries, partial slot or -1)
+  int nlong;          // slices split over several units
+  const int4 *longs;  // device: (slice, first partial slot, slots, 0)
+  int nslots;         // partial slots
 };
-MttkrpPlan mttkrp_plan(int RP, long long nnz);
+int mttkrp_units_per_block(int RP);
 hipError_t launch_mttkrp(int RP, const MttkrpPlan &p, const unsigned long long *keys, const float *vals,
-                         KeyLayout lay, const float *Aa, const float *Ab, float *M, float *carry,
+                         KeyLayout lay, const float *Aa, const float *Ab, float *M, float *part,
                          hipStream_t s);
-hipError_t launch_mttkrp_fix(int RP, const MttkrpPlan &p, const unsigned long long *keys, int sh_n,
-                             const int *ptr, int I, const float *carry, float *M, const double *Ga,
-                             const double *Gb, float *H, HInfo *hinfo, ModeState *st, hipStream_t s);
+hipError_t launch_mttkrp_fix(int RP, const MttkrpPlan &p, const int *ptr, int I, const float *part,
+                             float *M, const double *Ga, const double *Gb, float *H, HInfo *hinfo,
+                             ModeState *st, hipStream_t s);
 
 // sweep.hip
 int rows_per_block(int RP);
@@ -134,10 +141,21 @@ hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, 
                                 float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
                                 hipStream_t s);
 hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s);
-hipError_t launch_gram_final(int RP, int nparts, const float *gpart, double *Gn, const double *G0,
-                             const double *G1, const double *G2, const double *inner_part,
-                             const int *cnt_part, long long *colcnt, double normX2, int with_f,
-                             ModeState *st, hipStream_t s);
+// Two-level Gram reduction buffers (see k_gram_final).
+struct GramReduce {
+  int nparts;           // per-block partials written by the update / Gram kernel
+  const float *gpart;   // nparts x RP x RP
+  double *g2;           // level-2 partials, gram_level2_blocks(nparts) x RP x RP
+  long long *cnt2;      // level-2 selection counts, gram_level2_blocks(nparts) x RP
+  double *inner2;       // level-2 <M, A> partials
+  unsigned *ec_counter; // 16 arrival counters (zero between launches)
+};
+int gram_pb(int nparts);
+int gram_level2_blocks(int nparts);
+hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *G0, const double *G1,
+                             const double *G2, const double *inner_part, const int *cnt_part,
+                             long long *colcnt, double normX2, int with_f, ModeState *st,
+                             hipStream_t s);
 hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,
                              KeyLayout lay0, int RP, const float *A0, const float *A1,
                              const float *A2, double *partials, int nparts, double *out,

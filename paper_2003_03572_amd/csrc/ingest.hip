@@ -239,11 +239,18 @@ __global__ __launch_bounds__(kThreads) void k_rekey(const unsigned long long *__
 
 // ---------------------------------------------------------------- ptr ----
 
-__global__ __launch_bounds__(kThreads) void k_count_rows(const unsigned long long *__restrict__ keys,
-                                                         long long n, int sh_n, int *__restrict__ counts) {
+// Slice pointers from sorted keys: position p is the start of every row in
+// (row(p-1), row(p)], with row(-1) = -1 and row(n) = I.  Each pointer is
+// written exactly once; no atomics.
+__global__ __launch_bounds__(kThreads) void k_row_bounds(const unsigned long long *__restrict__ keys,
+                                                         long long n, int sh_n, int I,
+                                                         int *__restrict__ ptr) {
   const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
-    atomicAdd(&counts[(int)(keys[p] >> sh_n)], 1);
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p <= n; p += stride) {
+    const int prev = (p == 0) ? -1 : (int)(keys[p - 1] >> sh_n);
+    const int cur = (p == n) ? I : (int)(keys[p] >> sh_n);
+    for (int r = prev + 1; r <= cur; ++r) ptr[r] = (int)p;
+  }
 }
 
 // --------------------------------------------------------------- norm ----
@@ -377,17 +384,16 @@ hipError_t launch_rekey(const unsigned long long *keys0, long long n, KeyLayout 
 
 size_t build_ptr_temp_bytes(long long n, int I) {
   (void)n;
-  return (size_t)(scan_temp_ints((long long)I + 1) + 16) * sizeof(int);
+  (void)I;
+  return 16;
 }
 
 hipError_t build_ptr(const unsigned long long *keys, long long n, int sh_n, int I, int *ptr, void *temp,
                      hipStream_t s) {
-  hipError_t e = hipMemsetAsync(ptr, 0, ((size_t)I + 1) * sizeof(int), s);
-  if (e != hipSuccess) return e;
-  if (n > 0)
-    hipLaunchKernelGGL(k_count_rows, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, keys, n,
-                       sh_n, ptr);
-  return scan_exclusive(ptr, ptr, (long long)I + 1, (int *)temp, s);
+  (void)temp;
+  hipLaunchKernelGGL(k_row_bounds, dim3(grid_for(n + 1, kThreads * 4)), dim3(kThreads), 0, s, keys, n,
+                     sh_n, I, ptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_norm2(const float *vals, long long n, double *partials, int nparts, double *out,
@@ -406,6 +412,27 @@ hipError_t launch_export_coo(const unsigned long long *keys, const float *vals, 
   if (ptr64)
     hipLaunchKernelGGL(k_ptr_widen, dim3(grid_for((long long)I + 1, kThreads)), dim3(kThreads), 0, s,
                        ptr, I + 1, ptr64);
+  return hipGetLastError();
+}
+
+}  // namespace sacd
+
+namespace sacd {
+
+namespace {
+__global__ __launch_bounds__(kThreads) void k_gather_keys(const unsigned long long *__restrict__ keys,
+                                                          const int *__restrict__ pos, int n,
+                                                          unsigned long long *__restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    out[i] = keys[pos[i]];
+}
+}  // namespace
+
+hipError_t launch_gather_keys(const unsigned long long *keys, const int *pos, int n,
+                              unsigned long long *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_keys, dim3((n + kThreads - 1) / kThreads < 4096 ? (n + kThreads - 1) / kThreads : 4096),
+                     dim3(kThreads), 0, s, keys, pos, n, out);
   return hipGetLastError();
 }
 

@@ -36,11 +36,15 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Load that observes stores made by other blocks of the same grid after the
-// arrival counter has been read (device-scope coherent).
+// Load of data stored by other blocks of the same grid.  Every block stores,
+// then issues a device-scope fence (release) before it increments the
+// arrival counter; the last block issues a device-scope fence (acquire) after
+// reading the counter, which invalidates its caches, so plain loads that
+// follow observe the other blocks' stores.  Plain loads can be pipelined,
+// unlike atomic ones.
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
 }
 
 template <int RP>
@@ -65,6 +69,52 @@ __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *__restric
     acc = mfma4(a, b, acc);
   }
   return acc;
+}
+
+// Partial Gram matrix of the block's rows (the upper 16x16 tiles of
+// sA^T sA), written to gp.  Four independent MFMA accumulation chains over
+// interleaved row groups, added in a fixed order at the end.
+template <int RP>
+__device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, int lane) {
+  using Cf = UCfg<RP>;
+  constexpr int n16 = RP / 16;
+  for (int t = wv; t < n16 * n16; t += 4) {
+    const int ti_ = t / n16, tj = t % n16;
+    if (ti_ > tj) continue;
+    f32x4 acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < Cf::RB; k0 += 16) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int row = k0 + 4 * c + (lane >> 4);
+        const float a = sA[row * Cf::STR + ti_ * 16 + (lane & 15)];
+        const float b = sA[row * Cf::STR + tj * 16 + (lane & 15)];
+        acc[c] = mfma4(a, b, acc[c]);
+      }
+    }
+    const f32x4 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = tot[v];
+  }
+}
+
+// Sequential sum of n values base[0], base[stride], ... in index order,
+// loads issued eight at a time so their latencies overlap.
+template <typename Acc, typename T>
+__device__ __forceinline__ Acc sum_strided(const T *base, long long stride, int n) {
+  Acc s = 0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    T v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = base[(long long)(i + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += (Acc)v[k];
+  }
+  for (; i < n; ++i) s += (Acc)base[(long long)i * stride];
+  return s;
 }
 
 // Block-wide FP64 sum in a fixed tree order (all threads call; result in red[0]).
@@ -92,11 +142,27 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blockIdx.x * Cf::RB;
+  // this thread's MTTKRP entries for all its tiles, fetched before anything
+  // waits on them
+  float mv[Cf::NTW][4];
+#pragma unroll
+  for (int ti = 0; ti < Cf::NTW; ++ti) {
+    const int t = wv + 4 * ti;
+    const int tr = t / Cf::TC, tc = t % Cf::TC;
+    const int cc = tc * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long long q = row0 + tr * 16 + 4 * (lane >> 4) + v;
+      mv[ti][v] = (q < I) ? M[q * RP + cc] : 0.0f;
+    }
+  }
   load_rows<RP>(sA, A, row0, I);
   __syncthreads();
   const float halfL = hi->halfL;
   double zs = 0.0;
-  for (int t = wv; t < Cf::NT; t += 4) {
+#pragma unroll
+  for (int ti = 0; ti < Cf::NTW; ++ti) {
+    const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const f32x4 ah = tile_AH<RP>(sA, H, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
@@ -105,11 +171,9 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rr = tr * 16 + 4 * (lane >> 4) + v;
-      const long long q = row0 + rr;
-      if (q < I) {
+      if (row0 + rr < I) {
         float d;
-        const float z = element_importance(ah[v], M[q * RP + cc], sA[rr * Cf::STR + cc], h, nz,
-                                           halfL, &d);
+        const float z = element_importance(ah[v], mv[ti][v], sA[rr * Cf::STR + cc], h, nz, halfL, &d);
         zs += (double)z;
       }
     }
@@ -208,12 +272,26 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   __shared__ int sCnt[RP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blockIdx.x * Cf::RB;
+  // this thread's MTTKRP and previous-importance entries for all its tiles,
+  // fetched before anything waits on them
+  float mreg[Cf::NTW][4], zpreg[Cf::NTW][4];
+#pragma unroll
+  for (int ti = 0; ti < Cf::NTW; ++ti) {
+    const int t = wv + 4 * ti;
+    const int tr = t / Cf::TC, tc = t % Cf::TC;
+    const int cc = tc * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long long q = row0 + tr * 16 + 4 * (lane >> 4) + v;
+      mreg[ti][v] = (q < I) ? M[q * RP + cc] : 0.0f;
+      zpreg[ti][v] = (q < I) ? Z[q * RP + cc] : 0.0f;
+    }
+  }
   load_rows<RP>(sA, A, row0, I);
   for (int c = tid; c < RP; c += kThreads) sCnt[c] = 0;
   __syncthreads();
   const int first = st->first, flip = st->flip;
   const float halfL = hi->halfL;
-  float mreg[Cf::NTW][4];
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
@@ -226,20 +304,18 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
     for (int v = 0; v < 4; ++v) {
       const int rr = tr * 16 + 4 * (lane >> 4) + v;
       const long long q = row0 + rr;
-      mreg[ti][v] = 0.0f;
       uint8_t sl = 0;
       float gv = 0.0f;
       if (q < I) {
-        const float m = M[q * RP + cc];
+        const float m = mreg[ti][v];
         float d;
         const float z = element_importance(ah[v], m, sA[rr * Cf::STR + cc], h, nz, halfL, &d);
-        const float zp = Z[q * RP + cc];
+        const float zp = zpreg[ti][v];
         // Alg. 1: first sweep z > 0; later sp = z - zprev (eq. 24) or zprev - z (eq. 27) > 0
         const bool s = first ? (z > 0.0f) : (flip ? (z < zp) : (z > zp));
         Z[q * RP + cc] = z;
         gv = __fsub_rn(ah[v], m);
         sl = s ? 1 : 0;
-        mreg[ti][v] = m;
         if (DIAG) selmask[q * RP + cc] = sl;
         if (s) atomicAdd(&sCnt[cc], 1);
       }
@@ -276,21 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   if (tid == 0) inner_part[blockIdx.x] = bs;
   for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blockIdx.x * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
-  constexpr int n16 = RP / 16;
-  float *gp = gpart + (long long)blockIdx.x * RP * RP;
-  for (int t = wv; t < n16 * n16; t += 4) {
-    const int ti_ = t / n16, tj = t % n16;
-    if (ti_ > tj) continue;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Cf::RB; k0 += 4) {
-      const float a = sA[(k0 + (lane >> 4)) * Cf::STR + ti_ * 16 + (lane & 15)];
-      const float b = sA[(k0 + (lane >> 4)) * Cf::STR + tj * 16 + (lane & 15)];
-      acc = mfma4(a, b, acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = acc[v];
-  }
+  gram_tiles<RP>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
 // Gram partials of an arbitrary factor (initialisation, set_factor).
@@ -302,67 +364,86 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *_
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   load_rows<RP>(sA, A, blockIdx.x * Cf::RB, I);
   __syncthreads();
-  constexpr int n16 = RP / 16;
-  float *gp = gpart + (long long)blockIdx.x * RP * RP;
-  for (int t = wv; t < n16 * n16; t += 4) {
-    const int ti_ = t / n16, tj = t % n16;
-    if (ti_ > tj) continue;
-    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Cf::RB; k0 += 4) {
-      const float a = sA[(k0 + (lane >> 4)) * Cf::STR + ti_ * 16 + (lane & 15)];
-      const float b = sA[(k0 + (lane >> 4)) * Cf::STR + tj * 16 + (lane & 15)];
-      acc = mfma4(a, b, acc);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = acc[v];
-  }
+  gram_tiles<RP>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
-// Gram reduction: 64 entries (i <= j) per block, 4 threads per entry, FP64.
-// The last block to arrive forms the objective
+// Gram reduction in FP64, fixed order, two levels.  Block (ec, b) sums the
+// partials [b*PB, (b+1)*PB) of the entries [ec*EC, (ec+1)*EC) of the
+// row-major R x R matrix (upper 16x16 tiles only; the lower ones are not
+// formed); the last block of element chunk ec to arrive sums the level-2
+// partials in order and writes Gram_n (mirrored from i <= j); the last of
+// those forms the objective
 //   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
 // and the selection counts.
 template <int RP>
-__global__ __launch_bounds__(kThreads) void k_gram_final(int nparts, const float *__restrict__ gpart,
-                                                         double *Gn, const double *G0, const double *G1,
-                                                         const double *G2,
-                                                         const double *__restrict__ inner_part,
-                                                         const int *__restrict__ cnt_part,
-                                                         long long *__restrict__ colcnt, double normX2,
-                                                         int with_f, ModeState *st) {
+__global__ __launch_bounds__(kThreads) void k_gram_final(
+    int nparts, int PB, const float *__restrict__ gpart, double *__restrict__ g2,
+    long long *__restrict__ cnt2, double *__restrict__ inner2, double *Gn, const double *G0,
+    const double *G1, const double *G2, const double *__restrict__ inner_part,
+    const int *__restrict__ cnt_part, long long *__restrict__ colcnt, double normX2, int with_f,
+    unsigned *ec_counter, ModeState *st) {
+  constexpr int RR = RP * RP;
+  constexpr int EC = RR < 1024 ? RR : 1024;
+  constexpr int NEC = RR / EC;
+  constexpr int EPT = (EC + kThreads - 1) / kThreads;
   __shared__ double red[kThreads];
   __shared__ int s_last;
   const int tid = threadIdx.x;
-  const int e = blockIdx.x * 64 + tid / 4, part = tid % 4;
-  const int i = e / RP, j = e % RP;
-  const bool act = e < RP * RP && i <= j;
-  double s = 0.0;
-  if (act)
-    for (int b = part; b < nparts; b += 4) s += (double)gpart[(long long)b * RP * RP + i * RP + j];
-  red[tid] = s;
-  __syncthreads();
-  if (part == 0 && act) {
-    const double tot = (red[tid] + red[tid + 1]) + (red[tid + 2] + red[tid + 3]);
-    Gn[i * RP + j] = tot;
-    Gn[j * RP + i] = tot;
+  const int ec = blockIdx.x % NEC, b = blockIdx.x / NEC;
+  const int NB2 = gridDim.x / NEC;
+  const int p0 = b * PB, p1 = (p0 + PB < nparts) ? p0 + PB : nparts;
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = ec * EC + tid + k * kThreads;
+    if (tid + k * kThreads < EC && (e / RP) / 16 <= (e % RP) / 16) {
+      g2[(long long)b * RR + e] = sum_strided<double>(gpart + (long long)p0 * RR + e, RR, p1 - p0);
+    }
+  }
+  if (ec == 0) {
+    if (cnt_part)
+      for (int c = tid; c < RP; c += kThreads) {
+        cnt2[(long long)b * RP + c] = sum_strided<long long>(cnt_part + (long long)p0 * RP + c, RP, p1 - p0);
+      }
+    if (inner_part && tid == 0) {
+      inner2[b] = sum_strided<double>(inner_part + p0, 1, p1 - p0);
+    }
   }
   __syncthreads();
   if (tid == 0) {
     __threadfence();
+    const unsigned prev = atomicAdd(&ec_counter[ec], 1u);
+    s_last = (prev == (unsigned)NB2 - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+#pragma unroll
+  for (int k = 0; k < EPT; ++k) {
+    const int e = ec * EC + tid + k * kThreads;
+    const int i = e / RP, j = e % RP;
+    if (tid + k * kThreads < EC && i <= j) {
+      const double s = sum_strided<double>(g2 + e, RR, NB2);
+      Gn[i * RP + j] = s;
+      Gn[j * RP + i] = s;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    ec_counter[ec] = 0;
+    __threadfence();
     const unsigned prev = atomicAdd(&st->cnt_gram, 1u);
-    s_last = (prev == gridDim.x - 1);
+    s_last = (prev == (unsigned)NEC - 1);
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   if (with_f) {
     double mn = 0.0;
-    for (int x = tid; x < RP * RP; x += kThreads)
+    for (int x = tid; x < RR; x += kThreads)
       mn += ld_coherent(&G0[x]) * ld_coherent(&G1[x]) * ld_coherent(&G2[x]);
     const double model = block_sum(mn, red);
     double in = 0.0;
-    for (int b = tid; b < nparts; b += kThreads) in += inner_part[b];
+    for (int q = tid; q < NB2; q += kThreads) in += ld_coherent(&inner2[q]);
     const double inner = block_sum(in, red);
     if (tid == 0) {
       st->inner = inner;
@@ -372,8 +453,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(int nparts, const float
   if (cnt_part) {
     long long tot = 0;
     for (int c = tid; c < RP; c += kThreads) {
-      long long cnt = 0;
-      for (int b = 0; b < nparts; ++b) cnt += cnt_part[(long long)b * RP + c];
+      const long long cnt = sum_strided<long long>(cnt2 + c, RP, NB2);
       colcnt[c] = cnt;
       tot += cnt;
     }
@@ -567,25 +647,39 @@ hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipS
   }
 }
 
+int gram_level2_blocks(int nparts) {
+  const int PB = gram_pb(nparts);
+  return (nparts + PB - 1) / PB;
+}
+
+int gram_pb(int nparts) {
+  int pb = (nparts + 31) / 32;
+  return pb < 8 ? 8 : pb;
+}
+
 template <int RP>
-static hipError_t gf_t(int nparts, const float *gpart, double *Gn, const double *G0, const double *G1,
-                       const double *G2, const double *inner_part, const int *cnt_part, long long *colcnt,
-                       double normX2, int with_f, ModeState *st, hipStream_t s) {
-  const int nb = (RP * RP + 63) / 64;
-  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb), dim3(kThreads), 0, s, nparts, gpart, Gn, G0, G1, G2,
-                     inner_part, cnt_part, colcnt, normX2, with_f, st);
+static hipError_t gf_t(const GramReduce &g, double *Gn, const double *G0, const double *G1,
+                       const double *G2, const double *inner_part, const int *cnt_part,
+                       long long *colcnt, double normX2, int with_f, ModeState *st, hipStream_t s) {
+  constexpr int RR = RP * RP;
+  constexpr int NEC = RR < 1024 ? 1 : RR / 1024;
+  const int PB = gram_pb(g.nparts);
+  const int nb2 = (g.nparts + PB - 1) / PB;
+  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb2 * NEC), dim3(kThreads), 0, s, g.nparts, PB, g.gpart,
+                     g.g2, g.cnt2, g.inner2, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2,
+                     with_f, g.ec_counter, st);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_final(int RP, int nparts, const float *gpart, double *Gn, const double *G0,
-                             const double *G1, const double *G2, const double *inner_part,
-                             const int *cnt_part, long long *colcnt, double normX2, int with_f,
-                             ModeState *st, hipStream_t s) {
+hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *G0, const double *G1,
+                             const double *G2, const double *inner_part, const int *cnt_part,
+                             long long *colcnt, double normX2, int with_f, ModeState *st,
+                             hipStream_t s) {
   switch (RP) {
-    case 16: return gf_t<16>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 32: return gf_t<32>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 64: return gf_t<64>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 128: return gf_t<128>(nparts, gpart, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 16: return gf_t<16>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 32: return gf_t<32>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 64: return gf_t<64>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 128: return gf_t<128>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
     default: return hipErrorInvalidValue;
   }
 }

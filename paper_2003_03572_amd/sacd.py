@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libsacd.so")
+LIB_PATH = os.environ.get("SACD_LIB") or os.path.join(_HERE, "lib", "libsacd.so")
 
 PREC_FP32 = 0
 PREC_MIXED_BF16 = 1

@@ -6,8 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2003_03572_amd import gen
-from tests.gpu_helpers import (compare_sweep, gpu_tensor, load_oracle_state_into_gpu, step_parity,
-                               to_np)
+from tests.gpu_helpers import gpu_tensor, load_oracle_state_into_gpu, step_parity, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -112,21 +111,20 @@ def _step_parity_run(sacd, oracle_mod, w, R, n_iter, scale=1.0, seed=42):
 def test_step_parity_small_uniform_20_iterations(sacd, oracle_mod):
     rep = _step_parity_run(sacd, oracle_mod, gen.SMALL_UNIFORM, 8, 20)
     ties = sum(r["ties"] for r in rep)
-    skipped = sum(r["rows_skipped"] for r in rep)
-    print(f"ties {ties}, rows skipped {skipped} over {len(rep)} sweeps")
-    assert skipped <= 0.01 * 200 * len(rep)
+    other = sum(r["tie_rows_other_outcome"] for r in rep)
+    print(f"ties {ties}, tie rows with the other valid outcome {other} over {len(rep)} sweeps")
 
 
 @pytest.mark.parametrize("R", [32, 20])
 def test_step_parity_zipf_scaled(sacd, oracle_mod, R):
     rep = _step_parity_run(sacd, oracle_mod, gen.ZIPF_UIT, R, 3, scale=0.01)
-    print([(r["ties"], r["rows_skipped"]) for r in rep])
+    print([(r["ties"], r["tie_rows_other_outcome"]) for r in rep])
 
 
 @pytest.mark.parametrize("R", [64, 128, 100])
 def test_step_parity_uniform_scaled(sacd, oracle_mod, R):
     rep = _step_parity_run(sacd, oracle_mod, gen.UNIFORM_20M_R64, R, 2, scale=0.004)
-    print([(r["ties"], r["rows_skipped"]) for r in rep])
+    print([(r["ties"], r["tie_rows_other_outcome"]) for r in rep])
 
 
 def test_jacobi_flag_step_parity(sacd, oracle_mod):

@@ -50,22 +50,59 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
 template <int RP>
 __device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
   using Cf = UCfg<RP>;
-  for (int i = threadIdx.x; i < Cf::RB * RP; i += kThreads) {
-    const int r = i / RP, c = i % RP;
-    sA[r * Cf::STR + c] = (row0 + r < I) ? A[(long long)(row0 + r) * RP + c] : 0.0f;
+  // all loads of the tile are issued before the first LDS store waits on one
+  constexpr int N4 = Cf::RB * RP / 4 / kThreads;  // float4 per thread
+  f32x4 v[N4];
+#pragma unroll
+  for (int k = 0; k < N4; ++k) {
+    const int i = (threadIdx.x + k * kThreads) * 4;
+    const int r = i / RP;
+    v[k] = (row0 + r < I) ? *(const f32x4 *)(A + (long long)(row0 + r) * RP + i % RP)
+                          : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int k = 0; k < N4; ++k) {
+    const int i = (threadIdx.x + k * kThreads) * 4;
+    float *d = sA + (i / RP) * Cf::STR + i % RP;
+    d[0] = v[k][0];
+    d[1] = v[k][1];
+    d[2] = v[k][2];
+    d[3] = v[k][3];
+  }
+}
+
+// Stage H (RP x RP, row stride RP + 1) in LDS.
+template <int RP>
+__device__ __forceinline__ void load_h(float *sH, const float *__restrict__ H) {
+  constexpr int N4 = (RP * RP / 4 + kThreads - 1) / kThreads;
+  f32x4 v[N4];
+#pragma unroll
+  for (int k = 0; k < N4; ++k) {
+    const int i = (threadIdx.x + k * kThreads) * 4;
+    v[k] = (i < RP * RP) ? *(const f32x4 *)(H + i) : f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll
+  for (int k = 0; k < N4; ++k) {
+    const int i = (threadIdx.x + k * kThreads) * 4;
+    if (i < RP * RP) {
+      float *d = sH + (i / RP) * (RP + 1) + i % RP;
+      d[0] = v[k][0];
+      d[1] = v[k][1];
+      d[2] = v[k][2];
+      d[3] = v[k][3];
+    }
   }
 }
 
 // C tile (16 x 16) of the block's rows times H: rows tr*16.., columns tc*16..
 template <int RP>
-__device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *__restrict__ H, int tr, int tc,
-                                         int lane) {
+__device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int tr, int tc, int lane) {
   using Cf = UCfg<RP>;
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int kk = 0; kk < RP / 4; ++kk) {
     const float a = sA[(tr * 16 + (lane & 15)) * Cf::STR + kk * 4 + (lane >> 4)];
-    const float b = H[(kk * 4 + (lane >> 4)) * RP + tc * 16 + (lane & 15)];
+    const float b = sH[(kk * 4 + (lane >> 4)) * (RP + 1) + tc * 16 + (lane & 15)];
     acc = mfma4(a, b, acc);
   }
   return acc;
@@ -138,6 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
                                                          double *__restrict__ ti_part, ModeState *st) {
   using Cf = UCfg<RP>;
   __shared__ float sA[Cf::RB * Cf::STR];
+  __shared__ float sH[RP * (RP + 1)];
   __shared__ double red[kThreads];
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -157,6 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
     }
   }
   load_rows<RP>(sA, A, row0, I);
+  load_h<RP>(sH, H);
   __syncthreads();
   const float halfL = hi->halfL;
   double zs = 0.0;
@@ -164,7 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP>(sA, H, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -206,8 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
 // Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
 template <int RP, int UPD>
 __device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, const uint8_t *s_l,
-                                               const float *__restrict__ H,
-                                               const HInfo *__restrict__ hi) {
+                                               const float *sH, const HInfo *__restrict__ hi) {
   float a[RP], g[RP];
   unsigned long long sel = 0;
 #pragma unroll
@@ -229,7 +267,7 @@ __device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, con
         if (UPD == 0 && d != 0.0f) {
           // refresh the gradient of the row's later elements: g_s += d * H_rs
 #pragma unroll
-          for (int s = r + 1; s < RP; ++s) g[s] = __fmaf_rn(d, H[r * RP + s], g[s]);
+          for (int s = r + 1; s < RP; ++s) g[s] = __fmaf_rn(d, sH[r * (RP + 1) + s], g[s]);
         }
       }
     }
@@ -241,8 +279,7 @@ __device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, con
 // Same update with the row kept in LDS (RP = 128).
 template <int RP, int UPD>
 __device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const uint8_t *s_l,
-                                               const float *__restrict__ H,
-                                               const HInfo *__restrict__ hi) {
+                                               const float *sH, const HInfo *__restrict__ hi) {
   for (int r = 0; r < RP; ++r) {
     if (!s_l[r]) continue;
     const float h = hi->hdiag[r];
@@ -253,7 +290,7 @@ __device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const uin
     const float d = __fsub_rn(an, ar);
     a_l[r] = an;
     if (UPD == 0 && d != 0.0f) {
-      for (int s = r + 1; s < RP; ++s) g_l[s] = __fmaf_rn(d, H[r * RP + s], g_l[s]);
+      for (int s = r + 1; s < RP; ++s) g_l[s] = __fmaf_rn(d, sH[r * (RP + 1) + s], g_l[s]);
     }
   }
 }
@@ -267,6 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   using Cf = UCfg<RP>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
+  __shared__ float sH[RP * (RP + 1)];
   __shared__ uint8_t sSel[Cf::RB * Cf::SST];
   __shared__ double red[kThreads];
   __shared__ int sCnt[RP];
@@ -288,6 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
     }
   }
   load_rows<RP>(sA, A, row0, I);
+  load_h<RP>(sH, H);
   for (int c = tid; c < RP; c += kThreads) sCnt[c] = 0;
   __syncthreads();
   const int first = st->first, flip = st->flip;
@@ -296,7 +335,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP>(sA, H, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -326,9 +365,9 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   __syncthreads();
   if (tid < Cf::RB && row0 + tid < I) {
     if constexpr (RP <= 64)
-      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, H, hi);
+      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, sH, hi);
     else
-      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, H, hi);
+      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, sH, hi);
   }
   __syncthreads();
   for (int i = tid; i < Cf::RB * RP; i += kThreads) {
@@ -438,9 +477,22 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(
   if (!s_last) return;
   __threadfence();
   if (with_f) {
+    // model norm: sum of the Hadamard product of the three Gram matrices;
+    // four elements per thread in flight at a time
     double mn = 0.0;
-    for (int x = tid; x < RR; x += kThreads)
-      mn += ld_coherent(&G0[x]) * ld_coherent(&G1[x]) * ld_coherent(&G2[x]);
+    for (int x0 = tid; x0 < RR; x0 += 4 * kThreads) {
+      double v0[4], v1[4], v2[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = x0 + k * kThreads;
+        const bool ok = x < RR;
+        v0[k] = ok ? ld_coherent(&G0[x]) : 0.0;
+        v1[k] = ok ? ld_coherent(&G1[x]) : 0.0;
+        v2[k] = ok ? ld_coherent(&G2[x]) : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) mn += v0[k] * v1[k] * v2[k];
+    }
     const double model = block_sum(mn, red);
     double in = 0.0;
     for (int q = tid; q < NB2; q += kThreads) in += ld_coherent(&inner2[q]);

@@ -138,9 +138,8 @@ struct sacd_model {
   long long *colcnt[3] = {};
   uint8_t *selmask[3] = {};
   float *part = nullptr, *gpart = nullptr;
-  double *g2 = nullptr, *inner2 = nullptr;
-  long long *cnt2 = nullptr;
-  unsigned *ec_counter = nullptr;
+  double *mpart = nullptr;
+  unsigned *gcounter = nullptr;
   double *ti_part = nullptr, *inner_part = nullptr;
   int *cnt_part = nullptr, *flag = nullptr;
   double *full_part = nullptr, *full_out = nullptr;
@@ -181,10 +180,8 @@ GramReduce gram_reduce(const sacd_model *m, int n) {
   GramReduce g;
   g.nparts = m->nparts[n];
   g.gpart = m->gpart;
-  g.g2 = m->g2;
-  g.cnt2 = m->cnt2;
-  g.inner2 = m->inner2;
-  g.ec_counter = m->ec_counter;
+  g.mpart = m->mpart;
+  g.counter = m->gcounter;
   return g;
 }
 
@@ -202,16 +199,16 @@ sacd_status enqueue_sweep(sacd_model *m, int n) {
   HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[n], m->M[n], m->Z[n], m->H[n],
                                m->hinfo[n], m->st + n, m->gpart, m->inner_part, m->cnt_part,
                                m->selmask[n], s));
-  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[0], m->G64[1], m->G64[2],
-                            m->inner_part, m->cnt_part, m->colcnt[n], t->norm2, 1, m->st + n, s));
+  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[a], m->G64[b], m->inner_part,
+                            m->cnt_part, m->colcnt[n], t->norm2, 1, m->st + n, s));
   return SACD_OK;
 }
 
 sacd_status recompute_gram(sacd_model *m, int n) {
   const int I = (int)m->t->dims[n];
   HIP_TRY(launch_gram_partial(m->RP, I, m->A[n], m->gpart, m->s));
-  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[0], m->G64[1], m->G64[2],
-                            nullptr, nullptr, nullptr, 0.0, 0, m->st + n, m->s));
+  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], nullptr, nullptr, nullptr, nullptr,
+                            nullptr, 0.0, 0, m->st + n, m->s));
   return SACD_OK;
 }
 
@@ -648,11 +645,8 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   SACD_TRY(A.get_t((size_t)maxparts, &m->ti_part));
   SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
   SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
-  const int nb2 = gram_level2_blocks(maxparts);
-  SACD_TRY(A.get_t((size_t)nb2 * RP * RP, &m->g2));
-  SACD_TRY(A.get_t((size_t)nb2 * RP, &m->cnt2));
-  SACD_TRY(A.get_t((size_t)nb2, &m->inner2));
-  SACD_TRY(A.get_t(16, &m->ec_counter));
+  SACD_TRY(A.get_t((size_t)gram_model_parts(RP), &m->mpart));
+  SACD_TRY(A.get_t(1, &m->gcounter));
   SACD_TRY(A.get_t(4, &m->flag));
   m->full_nparts = 1024;
   SACD_TRY(A.get_t((size_t)m->full_nparts, &m->full_part));
@@ -662,7 +656,7 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   hipStream_t s = m->s;
   HIP_TRY(hipMemsetAsync(m->st, 0, 3 * sizeof(ModeState), s));
   HIP_TRY(hipMemsetAsync(m->full_cnt, 0, 16, s));
-  HIP_TRY(hipMemsetAsync(m->ec_counter, 0, 16 * sizeof(unsigned), s));
+  HIP_TRY(hipMemsetAsync(m->gcounter, 0, sizeof(unsigned), s));
   unsigned long long off = 0;
   for (int n = 0; n < 3; ++n) {
     const int I = (int)t->dims[n];

@@ -141,21 +141,17 @@ hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, 
                                 float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
                                 hipStream_t s);
 hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s);
-// Two-level Gram reduction buffers (see k_gram_final).
+// Gram reduction buffers (see k_gram_final).
 struct GramReduce {
   int nparts;           // per-block partials written by the update / Gram kernel
   const float *gpart;   // nparts x RP x RP
-  double *g2;           // level-2 partials, gram_level2_blocks(nparts) x RP x RP
-  long long *cnt2;      // level-2 selection counts, gram_level2_blocks(nparts) x RP
-  double *inner2;       // level-2 <M, A> partials
-  unsigned *ec_counter; // 16 arrival counters (zero between launches)
+  double *mpart;        // gram_model_parts(RP) model-norm partials
+  unsigned *counter;    // arrival counter (zero between launches)
 };
-int gram_pb(int nparts);
-int gram_level2_blocks(int nparts);
-hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *G0, const double *G1,
-                             const double *G2, const double *inner_part, const int *cnt_part,
-                             long long *colcnt, double normX2, int with_f, ModeState *st,
-                             hipStream_t s);
+int gram_model_parts(int RP);
+hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
+                             const double *inner_part, const int *cnt_part, long long *colcnt,
+                             double normX2, int with_f, ModeState *st, hipStream_t s);
 hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,
                              KeyLayout lay0, int RP, const float *A0, const float *A1,
                              const float *A2, double *partials, int nparts, double *out,

@@ -26,7 +26,6 @@ template <int RP>
 struct UCfg {
   static constexpr int RB = RP <= 32 ? 256 : (RP == 64 ? 128 : 64);  // rows per block
   static constexpr int STR = RP + 1;                                   // LDS row stride (floats)
-  static constexpr int SST = RP + 4;                                   // LDS row stride (bytes) of sel
   static constexpr int TC = RP / 16;                                   // 16-column tiles
   static constexpr int NT = (RB / 16) * TC;                            // 16x16 tiles per block
   static constexpr int NTW = NT / 4;                                   // tiles per wave
@@ -244,15 +243,16 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
 
 // Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
 template <int RP, int UPD>
-__device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, const uint8_t *s_l,
+__device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, const unsigned short *s_l,
                                                const float *sH, const HInfo *__restrict__ hi) {
   float a[RP], g[RP];
   unsigned long long sel = 0;
 #pragma unroll
+  for (int w = 0; w < RP / 16; ++w) sel |= (unsigned long long)s_l[w] << (16 * w);
+#pragma unroll
   for (int c = 0; c < RP; ++c) {
     a[c] = a_l[c];
     g[c] = g_l[c];
-    sel |= (unsigned long long)(s_l[c] != 0) << c;
   }
   if (sel == 0) return;
 #pragma unroll
@@ -278,10 +278,10 @@ __device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, con
 
 // Same update with the row kept in LDS (RP = 128).
 template <int RP, int UPD>
-__device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const uint8_t *s_l,
+__device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const unsigned short *s_l,
                                                const float *sH, const HInfo *__restrict__ hi) {
   for (int r = 0; r < RP; ++r) {
-    if (!s_l[r]) continue;
+    if (!((s_l[r >> 4] >> (r & 15)) & 1)) continue;
     const float h = hi->hdiag[r];
     if (!(h > 0.0f)) continue;
     const float gr = g_l[r], ar = a_l[r];
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
-  __shared__ uint8_t sSel[Cf::RB * Cf::SST];
+  __shared__ unsigned short sSel[Cf::RB * (RP / 16)];  // selection bits, 16 columns a word
   __shared__ double red[kThreads];
   __shared__ int sCnt[RP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -339,11 +339,12 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
+    int cnt = 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rr = tr * 16 + 4 * (lane >> 4) + v;
       const long long q = row0 + rr;
-      uint8_t sl = 0;
+      bool sl = false;
       float gv = 0.0f;
       if (q < I) {
         const float m = mreg[ti][v];
@@ -351,23 +352,25 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
         const float z = element_importance(ah[v], m, sA[rr * Cf::STR + cc], h, nz, halfL, &d);
         const float zp = zpreg[ti][v];
         // Alg. 1: first sweep z > 0; later sp = z - zprev (eq. 24) or zprev - z (eq. 27) > 0
-        const bool s = first ? (z > 0.0f) : (flip ? (z < zp) : (z > zp));
+        sl = first ? (z > 0.0f) : (flip ? (z < zp) : (z > zp));
         Z[q * RP + cc] = z;
         gv = __fsub_rn(ah[v], m);
-        sl = s ? 1 : 0;
-        if (DIAG) selmask[q * RP + cc] = sl;
-        if (s) atomicAdd(&sCnt[cc], 1);
+        if (DIAG) selmask[q * RP + cc] = sl ? 1 : 0;
       }
       sG[rr * Cf::STR + cc] = gv;
-      sSel[rr * Cf::SST + cc] = sl;
+      // lane l holds row 4 (l / 16) + v, column l % 16 of the tile
+      const unsigned long long bal = __ballot(sl);
+      if ((lane & 15) == 0) sSel[rr * (RP / 16) + tc] = (unsigned short)(bal >> (lane & 48));
+      cnt += __popcll(bal & (0x0001000100010001ull << (lane & 15)));
     }
+    if (lane < 16 && cnt) atomicAdd(&sCnt[cc], cnt);
   }
   __syncthreads();
   if (tid < Cf::RB && row0 + tid < I) {
     if constexpr (RP <= 64)
-      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, sH, hi);
+      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * (RP / 16), sH, hi);
     else
-      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * Cf::SST, sH, hi);
+      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * (RP / 16), sH, hi);
   }
   __syncthreads();
   for (int i = tid; i < Cf::RB * RP; i += kThreads) {
@@ -406,113 +409,137 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *_
   gram_tiles<RP>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
-// Gram reduction in FP64, fixed order, two levels.  Block (ec, b) sums the
-// partials [b*PB, (b+1)*PB) of the entries [ec*EC, (ec+1)*EC) of the
-// row-major R x R matrix (upper 16x16 tiles only; the lower ones are not
-// formed); the last block of element chunk ec to arrive sums the level-2
-// partials in order and writes Gram_n (mirrored from i <= j); the last of
-// those forms the objective
+// Sum of the values base[p * stride], p = s, s + 16, s + 32, ... < n, in
+// index order, sixteen loads in flight at a time.
+template <typename Acc, typename T>
+__device__ __forceinline__ Acc stripe_sum(const T *base, long long stride, int s, int n) {
+  Acc acc = 0;
+  for (int p0 = s; p0 < n; p0 += 16 * 16) {
+    T v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int p = p0 + 16 * k;
+      v[k] = (p < n) ? base[(long long)p * stride] : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += (Acc)v[k];
+  }
+  return acc;
+}
+
+// Adds red[tid] over the 16 stripes s = tid / 16 in a fixed tree order;
+// the sum for entry e = tid % 16 ends in red[e].
+template <typename T>
+__device__ __forceinline__ void stripe_tree(T *red) {
+  __syncthreads();
+  for (int w = 8; w > 0; w >>= 1) {
+    if ((int)(threadIdx.x >> 4) < w) red[threadIdx.x] += red[threadIdx.x + 16 * w];
+    __syncthreads();
+  }
+}
+
+// Number of 16-entry strips of the upper 16x16 tiles of an RP x RP matrix.
+template <int RP>
+constexpr int gram_strips() {
+  return 16 * (RP / 16) * (RP / 16 + 1) / 2;
+}
+
+// Gram reduction in FP64 and the sweep's scalars, one level, fixed order.
+// Blocks [0, NS): one 16-entry strip (row i, columns 16 tj .. 16 tj + 15,
+// tile tj >= tile of i) of Gram_n each; thread (e, s) = (tid % 16, tid / 16)
+// adds the block partials s, s + 16, ... of entry e in order, the 16 stripes
+// are then added in a fixed tree order.  The strip is written to Gram_n and
+// mirrored, and with with_f the block also writes its share of
+//   sum_rs (Gram_n * Gram_a * Gram_b)_rs
+// (entries of off-diagonal tiles count twice).  Blocks [NS, NS + RP/16):
+// selection counts of 16 columns.  Block NS + RP/16: <M, A_n>.  The last
+// block to arrive forms the objective
 //   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
-// and the selection counts.
+// and the total selection count.
 template <int RP>
 __global__ __launch_bounds__(kThreads) void k_gram_final(
-    int nparts, int PB, const float *__restrict__ gpart, double *__restrict__ g2,
-    long long *__restrict__ cnt2, double *__restrict__ inner2, double *Gn, const double *G0,
-    const double *G1, const double *G2, const double *__restrict__ inner_part,
+    int nparts, const float *__restrict__ gpart, double *__restrict__ mpart, double *Gn,
+    const double *__restrict__ Ga, const double *__restrict__ Gb, const double *__restrict__ inner_part,
     const int *__restrict__ cnt_part, long long *__restrict__ colcnt, double normX2, int with_f,
-    unsigned *ec_counter, ModeState *st) {
-  constexpr int RR = RP * RP;
-  constexpr int EC = RR < 1024 ? RR : 1024;
-  constexpr int NEC = RR / EC;
-  constexpr int EPT = (EC + kThreads - 1) / kThreads;
+    unsigned *counter, ModeState *st) {
+  constexpr int RR = RP * RP, n16 = RP / 16, NS = gram_strips<RP>();
   __shared__ double red[kThreads];
+  __shared__ long long redl[kThreads];
   __shared__ int s_last;
-  const int tid = threadIdx.x;
-  const int ec = blockIdx.x % NEC, b = blockIdx.x / NEC;
-  const int NB2 = gridDim.x / NEC;
-  const int p0 = b * PB, p1 = (p0 + PB < nparts) ? p0 + PB : nparts;
-#pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = ec * EC + tid + k * kThreads;
-    if (tid + k * kThreads < EC && (e / RP) / 16 <= (e % RP) / 16) {
-      g2[(long long)b * RR + e] = sum_strided<double>(gpart + (long long)p0 * RR + e, RR, p1 - p0);
+  const int tid = threadIdx.x, e = tid & 15, s = tid >> 4;
+  const int b = blockIdx.x;
+  if (b < NS) {
+    int rem = b, ti = 0;
+    while (rem >= 16 * (n16 - ti)) {
+      rem -= 16 * (n16 - ti);
+      ++ti;
     }
-  }
-  if (ec == 0) {
-    if (cnt_part)
-      for (int c = tid; c < RP; c += kThreads) {
-        cnt2[(long long)b * RP + c] = sum_strided<long long>(cnt_part + (long long)p0 * RP + c, RP, p1 - p0);
+    const int i = ti * 16 + rem / (n16 - ti), tj = ti + rem % (n16 - ti);
+    const int j = tj * 16 + e;
+    const int x = i * RP + j;
+    double wab = 0.0;
+    if (with_f && s == 0) wab = (ti == tj ? 1.0 : 2.0) * Ga[x] * Gb[x];  // issued early
+    red[tid] = stripe_sum<double>(gpart + x, RR, s, nparts);
+    stripe_tree(red);
+    if (s == 0) {
+      const double v = red[e];
+      Gn[x] = v;
+      Gn[j * RP + i] = v;
+      if (with_f) red[tid] = v * wab;
+    }
+    if (with_f) {
+      __syncthreads();
+      if (tid == 0) {
+        double m = 0.0;
+        for (int k = 0; k < 16; ++k) m += red[k];
+        mpart[b] = m;
       }
-    if (inner_part && tid == 0) {
-      inner2[b] = sum_strided<double>(inner_part + p0, 1, p1 - p0);
     }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned prev = atomicAdd(&ec_counter[ec], 1u);
-    s_last = (prev == (unsigned)NB2 - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+  } else if (b < NS + n16) {
+    if (cnt_part) {
+      const int c = (b - NS) * 16 + e;
+      redl[tid] = stripe_sum<long long>(cnt_part + c, RP, s, nparts);
+      stripe_tree(redl);
+      if (s == 0) colcnt[c] = redl[e];
+    }
+  } else {
+    if (inner_part) {
+      double v = 0.0;
+      for (int p0 = tid; p0 < nparts; p0 += 4 * kThreads) {
+        double w[4];
 #pragma unroll
-  for (int k = 0; k < EPT; ++k) {
-    const int e = ec * EC + tid + k * kThreads;
-    const int i = e / RP, j = e % RP;
-    if (tid + k * kThreads < EC && i <= j) {
-      const double s = sum_strided<double>(g2 + e, RR, NB2);
-      Gn[i * RP + j] = s;
-      Gn[j * RP + i] = s;
+        for (int k = 0; k < 4; ++k) w[k] = (p0 + k * kThreads < nparts) ? inner_part[p0 + k * kThreads] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += w[k];
+      }
+      const double in = block_sum(v, red);
+      if (tid == 0) st->inner = in;
     }
   }
   __syncthreads();
   if (tid == 0) {
-    ec_counter[ec] = 0;
     __threadfence();
-    const unsigned prev = atomicAdd(&st->cnt_gram, 1u);
-    s_last = (prev == (unsigned)NEC - 1);
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
+  double mv = 0.0;
+  long long cv = 0;
+  for (int k = tid; k < NS; k += kThreads)
+    if (with_f) mv += ld_coherent(&mpart[k]);
+  if (cnt_part && tid < RP) cv = ld_coherent(&colcnt[tid]);
+  const double inner = with_f ? ld_coherent(&st->inner) : 0.0;
   if (with_f) {
-    // model norm: sum of the Hadamard product of the three Gram matrices;
-    // four elements per thread in flight at a time
-    double mn = 0.0;
-    for (int x0 = tid; x0 < RR; x0 += 4 * kThreads) {
-      double v0[4], v1[4], v2[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int x = x0 + k * kThreads;
-        const bool ok = x < RR;
-        v0[k] = ok ? ld_coherent(&G0[x]) : 0.0;
-        v1[k] = ok ? ld_coherent(&G1[x]) : 0.0;
-        v2[k] = ok ? ld_coherent(&G2[x]) : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k) mn += v0[k] * v1[k] * v2[k];
-    }
-    const double model = block_sum(mn, red);
-    double in = 0.0;
-    for (int q = tid; q < NB2; q += kThreads) in += ld_coherent(&inner2[q]);
-    const double inner = block_sum(in, red);
-    if (tid == 0) {
-      st->inner = inner;
-      st->f = normX2 - 2.0 * inner + model;
-    }
+    const double model = block_sum(mv, red);
+    if (tid == 0) st->f = normX2 - 2.0 * inner + model;
   }
   if (cnt_part) {
-    long long tot = 0;
-    for (int c = tid; c < RP; c += kThreads) {
-      const long long cnt = sum_strided<long long>(cnt2 + c, RP, NB2);
-      colcnt[c] = cnt;
-      tot += cnt;
-    }
-    const double all = block_sum((double)tot, red);
+    const double all = block_sum((double)cv, red);
     if (tid == 0) st->nsel = (long long)all;
   }
-  if (tid == 0) st->cnt_gram = 0;
+  if (tid == 0) *counter = 0;
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_factor(float *__restrict__ A, int I, int R, int RP,
@@ -699,39 +726,26 @@ hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipS
   }
 }
 
-int gram_level2_blocks(int nparts) {
-  const int PB = gram_pb(nparts);
-  return (nparts + PB - 1) / PB;
-}
-
-int gram_pb(int nparts) {
-  int pb = (nparts + 31) / 32;
-  return pb < 8 ? 8 : pb;
-}
-
 template <int RP>
-static hipError_t gf_t(const GramReduce &g, double *Gn, const double *G0, const double *G1,
-                       const double *G2, const double *inner_part, const int *cnt_part,
-                       long long *colcnt, double normX2, int with_f, ModeState *st, hipStream_t s) {
-  constexpr int RR = RP * RP;
-  constexpr int NEC = RR < 1024 ? 1 : RR / 1024;
-  const int PB = gram_pb(g.nparts);
-  const int nb2 = (g.nparts + PB - 1) / PB;
-  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb2 * NEC), dim3(kThreads), 0, s, g.nparts, PB, g.gpart,
-                     g.g2, g.cnt2, g.inner2, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2,
-                     with_f, g.ec_counter, st);
+static hipError_t gf_t(const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
+                       const double *inner_part, const int *cnt_part, long long *colcnt, double normX2,
+                       int with_f, ModeState *st, hipStream_t s) {
+  const int nb = gram_strips<RP>() + RP / 16 + 1;
+  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb), dim3(kThreads), 0, s, g.nparts, g.gpart, g.mpart, Gn, Ga,
+                     Gb, inner_part, cnt_part, colcnt, normX2, with_f, g.counter, st);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *G0, const double *G1,
-                             const double *G2, const double *inner_part, const int *cnt_part,
-                             long long *colcnt, double normX2, int with_f, ModeState *st,
-                             hipStream_t s) {
+int gram_model_parts(int RP) { return 16 * (RP / 16) * (RP / 16 + 1) / 2; }
+
+hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
+                             const double *inner_part, const int *cnt_part, long long *colcnt,
+                             double normX2, int with_f, ModeState *st, hipStream_t s) {
   switch (RP) {
-    case 16: return gf_t<16>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 32: return gf_t<32>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 64: return gf_t<64>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 128: return gf_t<128>(g, Gn, G0, G1, G2, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 16: return gf_t<16>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 32: return gf_t<32>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 64: return gf_t<64>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 128: return gf_t<128>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -149,6 +149,8 @@ struct sacd_model {
   MttkrpPlan plan[3];
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  // measurement: events recorded around the MTTKRP launches (6 per iteration)
+  std::vector<hipEvent_t> tev;
   double *h_pinned = nullptr;
   bool counted = false;  // included in t->nmodels
   int last_mode = -1;  // mode of the most recent sweep, -1: objective must be recomputed
@@ -185,14 +187,18 @@ GramReduce gram_reduce(const sacd_model *m, int n) {
   return g;
 }
 
-sacd_status enqueue_sweep(sacd_model *m, int n) {
+// Enqueues one sweep of mode n on the model's stream.  mark (optional): two
+// events recorded right before and right after the MTTKRP launch.
+sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr) {
   sacd_tensor *t = m->t;
   int a, b;
   other_modes(n, &a, &b);
   const int I = (int)t->dims[n];
   hipStream_t s = m->s;
+  if (mark) HIP_TRY(hipEventRecord(mark[0], s));
   HIP_TRY(launch_mttkrp(m->RP, m->plan[n], t->keys[n], t->vals[n], t->lay[n], m->A[a], m->A[b], m->M[n],
                         m->part, s));
+  if (mark) HIP_TRY(hipEventRecord(mark[1], s));
   HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[n], t->ptr[n], I, m->part, m->M[n], m->G64[a], m->G64[b],
                             m->H[n], m->hinfo[n], m->st + n, s));
   HIP_TRY(launch_importance(m->RP, I, m->A[n], m->M[n], m->H[n], m->hinfo[n], m->ti_part, m->st + n, s));
@@ -219,8 +225,8 @@ void drop_graph(sacd_model *m) {
   m->graph = nullptr;
 }
 
-sacd_status ensure_graph(sacd_model *m) {
-  if (m->gexec) return SACD_OK;
+// Captures one iteration (sweeps of modes 0, 1, 2) into an executable graph.
+sacd_status capture_iteration(sacd_model *m, hipGraph_t *graph, hipGraphExec_t *exec) {
   HIP_TRY(hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal));
   sacd_status st = SACD_OK;
   for (int n = 0; n < 3 && st == SACD_OK; ++n) st = enqueue_sweep(m, n);
@@ -237,9 +243,14 @@ sacd_status ensure_graph(sacd_model *m) {
     (void)hipGraphDestroy(g);
     return fail(SACD_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
   }
-  m->graph = g;
-  m->gexec = ge;
+  *graph = g;
+  *exec = ge;
   return SACD_OK;
+}
+
+sacd_status ensure_graph(sacd_model *m) {
+  if (m->gexec) return SACD_OK;
+  return capture_iteration(m, &m->graph, &m->gexec);
 }
 
 sacd_status read_state(const sacd_model *m, int n, ModeState *out) {
@@ -729,6 +740,37 @@ sacd_status sacd_iterate(sacd_model *m, int32_t n_iters) {
   return SACD_OK;
 }
 
+sacd_status sacd_timing_prepare(sacd_model *m, int32_t n_iters) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (n_iters < 1 || n_iters > 100000) return fail(SACD_ERR_INVALID_ARG, "n_iters out of [1, 100000]");
+  SACD_TRY(enter(m->t->dev));
+  while ((int)m->tev.size() < 6 * n_iters) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    m->tev.push_back(e);
+  }
+  return SACD_OK;
+}
+
+sacd_status sacd_iterate_timed(sacd_model *m, int32_t n_iters, float *mttkrp_ms) {
+  if (!m || !mttkrp_ms) return fail(SACD_ERR_INVALID_ARG, "model or output is NULL");
+  if (n_iters < 1 || 6 * n_iters > (int)m->tev.size())
+    return fail(SACD_ERR_BAD_STATE, "sacd_timing_prepare was not called for %d iterations", (int)n_iters);
+  SACD_TRY(enter(m->t->dev));
+  for (int i = 0; i < n_iters; ++i)
+    for (int n = 0; n < 3; ++n) SACD_TRY(enqueue_sweep(m, n, &m->tev[6 * i + 2 * n]));
+  m->last_mode = 2;
+  m->dirty = false;
+  HIP_TRY(hipStreamSynchronize(m->s));
+  for (int i = 0; i < n_iters; ++i)
+    for (int n = 0; n < 3; ++n) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, m->tev[6 * i + 2 * n], m->tev[6 * i + 2 * n + 1]));
+      mttkrp_ms[3 * i + n] = ms;
+    }
+  return SACD_OK;
+}
+
 sacd_status sacd_fit(sacd_model *m, double *fit, double *objective) {
   if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
   SACD_TRY(enter(m->t->dev));
@@ -956,6 +998,8 @@ void sacd_destroy_model(sacd_model *m) {
   (void)hipSetDevice(t->dev);
   if (m->s) (void)hipStreamSynchronize(m->s);
   drop_graph(m);
+  for (hipEvent_t e : m->tev) (void)hipEventDestroy(e);
+  m->tev.clear();
   m->mem.release_all();
   if (m->h_pinned) (void)hipHostFree(m->h_pinned);
   const bool counted = m->counted;

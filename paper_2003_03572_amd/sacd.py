@@ -78,6 +78,8 @@ def lib():
             "sacd_get_diagnostics": [p, i32, p, p, p],
             "sacd_set_diagnostics": [p, i32],
             "sacd_time_kernel": [p, i32, i32, i32, p],
+            "sacd_timing_prepare": [p, i32],
+            "sacd_iterate_timed": [p, i32, p],
             "sacd_kernel_bytes": [p, i32, i32, p],
             "sacd_model_bytes": [p, p],
         }
@@ -292,6 +294,19 @@ class Model:
         ms = C.c_float()
         _check(lib().sacd_time_kernel(self._h, which, mode, reps, C.byref(ms)), "sacd_time_kernel")
         return ms.value
+
+    def timing_prepare(self, n_iters: int):
+        """Create the HIP events for n_iters timed iterations (see iterate_timed)."""
+        _check(lib().sacd_timing_prepare(self._h, n_iters), "sacd_timing_prepare")
+
+    def iterate_timed(self, n_iters: int):
+        """n_iters outer iterations, the same work as iterate() but enqueued
+        launch by launch with HIP events around the MTTKRP launches.  Waits
+        for them; returns the MTTKRP kernel milliseconds as a list of n_iters
+        [mode 0, 1, 2]."""
+        out = (C.c_float * (3 * n_iters))()
+        _check(lib().sacd_iterate_timed(self._h, n_iters, out), "sacd_iterate_timed")
+        return [[out[3 * i + n] for n in range(3)] for i in range(n_iters)]
 
     def kernel_bytes(self, which: int, mode: int) -> float:
         b = C.c_double()

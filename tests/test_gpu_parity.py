@@ -208,6 +208,25 @@ def test_graph_iterate_equals_eager_sweeps(sacd):
                                           to_np(b.factor(n)).view(np.uint32))
 
 
+def test_timed_iterations_equal_iterate(sacd):
+    """Timed iterations (launch by launch, events around MTTKRP) do the same
+    work as iterate(): bit-identical factors, positive kernel times."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    a = sacd.Model(T_g, 8, seed=42)
+    b = sacd.Model(T_g, 8, seed=42)
+    b.timing_prepare(3)
+    with pytest.raises(sacd.SacdError):
+        b.iterate_timed(4)
+    a.iterate(3)
+    ms = b.iterate_timed(3)
+    assert len(ms) == 3 and all(len(r) == 3 and all(0.0 < v < 1e3 for v in r) for r in ms)
+    for n in range(3):
+        np.testing.assert_array_equal(to_np(a.factor(n)).view(np.uint32),
+                                      to_np(b.factor(n)).view(np.uint32))
+    assert a.fit() == b.fit()
+
+
 def test_run_until_rule(sacd, oracle_mod):
     w = gen.SMALL_UNIFORM
     dims, idx, vals = gen.make(w)

@@ -178,43 +178,115 @@ sacd_status make_stream(void *stream, hipStream_t *out, bool *own) {
 
 // ---------------------------------------------------------------- sweep ----
 
-GramReduce gram_reduce(const sacd_model *m, int n) {
-  GramReduce g;
-  g.nparts = m->nparts[n];
-  g.gpart = m->gpart;
-  g.mpart = m->mpart;
-  g.counter = m->gcounter;
-  return g;
+// Kernel arguments of mode n of one model (also the per-job entries of the
+// job-batched launches).
+MttkrpArgs mttkrp_args(const sacd_model *m, int n) {
+  const sacd_tensor *t = m->t;
+  int a, b;
+  other_modes(n, &a, &b);
+  MttkrpArgs x;
+  x.keys = t->keys[n];
+  x.vals = t->vals[n];
+  x.units = m->plan[n].units;
+  x.nunits = m->plan[n].nunits;
+  x.lay = t->lay[n];
+  x.Aa = m->A[a];
+  x.Ab = m->A[b];
+  x.M = m->M[n];
+  x.part = m->part;
+  return x;
 }
+
+FixArgs fix_args(const sacd_model *m, int n) {
+  const sacd_tensor *t = m->t;
+  int a, b;
+  other_modes(n, &a, &b);
+  FixArgs x;
+  x.longs = m->plan[n].longs;
+  x.nlong = m->plan[n].nlong;
+  x.part = m->part;
+  x.ptr = t->ptr[n];
+  x.I = (int)t->dims[n];
+  x.M = m->M[n];
+  x.Ga = m->G64[a];
+  x.Gb = m->G64[b];
+  x.H = m->H[n];
+  x.hinfo = m->hinfo[n];
+  x.st = m->st + n;
+  return x;
+}
+
+ImpArgs imp_args(const sacd_model *m, int n) {
+  ImpArgs x;
+  x.I = (int)m->t->dims[n];
+  x.A = m->A[n];
+  x.M = m->M[n];
+  x.H = m->H[n];
+  x.hi = m->hinfo[n];
+  x.ti_part = m->ti_part;
+  x.st = m->st + n;
+  return x;
+}
+
+UpdArgs upd_args(const sacd_model *m, int n) {
+  UpdArgs x;
+  x.I = (int)m->t->dims[n];
+  x.A = m->A[n];
+  x.M = m->M[n];
+  x.Z = m->Z[n];
+  x.H = m->H[n];
+  x.hi = m->hinfo[n];
+  x.st = m->st + n;
+  x.gpart = m->gpart;
+  x.inner_part = m->inner_part;
+  x.cnt_part = m->cnt_part;
+  x.selmask = m->selmask[n];
+  return x;
+}
+
+// with_f: the sweep form (Gram, counts, <M, A_n>, objective); otherwise the
+// Gram of a factor set from outside (partials from k_gram_partial).
+GramArgs gram_args(const sacd_model *m, int n, bool with_f) {
+  int a, b;
+  other_modes(n, &a, &b);
+  GramArgs x;
+  x.nparts = m->nparts[n];
+  x.gpart = m->gpart;
+  x.mpart = m->mpart;
+  x.Gn = m->G64[n];
+  x.Ga = with_f ? m->G64[a] : nullptr;
+  x.Gb = with_f ? m->G64[b] : nullptr;
+  x.inner_part = with_f ? m->inner_part : nullptr;
+  x.cnt_part = with_f ? m->cnt_part : nullptr;
+  x.colcnt = with_f ? m->colcnt[n] : nullptr;
+  x.normX2 = with_f ? m->t->norm2 : 0.0;
+  x.with_f = with_f ? 1 : 0;
+  x.counter = m->gcounter;
+  x.st = m->st + n;
+  return x;
+}
+
+bool is_bf16(const sacd_model *m) { return m->prec == SACD_PREC_MIXED_BF16; }
 
 // Enqueues one sweep of mode n on the model's stream.  mark (optional): two
 // events recorded right before and right after the MTTKRP launch.
 sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr) {
-  sacd_tensor *t = m->t;
-  int a, b;
-  other_modes(n, &a, &b);
-  const int I = (int)t->dims[n];
   hipStream_t s = m->s;
+  const bool bf = is_bf16(m);
   if (mark) HIP_TRY(hipEventRecord(mark[0], s));
-  HIP_TRY(launch_mttkrp(m->RP, m->plan[n], t->keys[n], t->vals[n], t->lay[n], m->A[a], m->A[b], m->M[n],
-                        m->part, s));
+  HIP_TRY(launch_mttkrp(m->RP, mttkrp_args(m, n), s));
   if (mark) HIP_TRY(hipEventRecord(mark[1], s));
-  HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[n], t->ptr[n], I, m->part, m->M[n], m->G64[a], m->G64[b],
-                            m->H[n], m->hinfo[n], m->st + n, s));
-  HIP_TRY(launch_importance(m->RP, I, m->A[n], m->M[n], m->H[n], m->hinfo[n], m->ti_part, m->st + n, s));
-  HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[n], m->M[n], m->Z[n], m->H[n],
-                               m->hinfo[n], m->st + n, m->gpart, m->inner_part, m->cnt_part,
-                               m->selmask[n], s));
-  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], m->G64[a], m->G64[b], m->inner_part,
-                            m->cnt_part, m->colcnt[n], t->norm2, 1, m->st + n, s));
+  HIP_TRY(launch_mttkrp_fix(m->RP, fix_args(m, n), s));
+  HIP_TRY(launch_importance(m->RP, bf, imp_args(m, n), s));
+  HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, bf, upd_args(m, n), s));
+  HIP_TRY(launch_gram_final(m->RP, gram_args(m, n, true), s));
   return SACD_OK;
 }
 
 sacd_status recompute_gram(sacd_model *m, int n) {
   const int I = (int)m->t->dims[n];
-  HIP_TRY(launch_gram_partial(m->RP, I, m->A[n], m->gpart, m->s));
-  HIP_TRY(launch_gram_final(m->RP, gram_reduce(m, n), m->G64[n], nullptr, nullptr, nullptr, nullptr,
-                            nullptr, 0.0, 0, m->st + n, m->s));
+  HIP_TRY(launch_gram_partial(m->RP, is_bf16(m), I, m->A[n], m->gpart, m->s));
+  HIP_TRY(launch_gram_final(m->RP, gram_args(m, n, false), m->s));
   return SACD_OK;
 }
 
@@ -691,8 +763,6 @@ sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_pre
   if (R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "rank %d not in [1, %d]", R, kMaxRP);
   if (prec != SACD_PREC_FP32 && prec != SACD_PREC_MIXED_BF16)
     return fail(SACD_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
-  if (prec == SACD_PREC_MIXED_BF16)
-    return fail(SACD_ERR_INVALID_ARG, "the mixed BF16 form is not built in this library");
   if (update != SACD_UPDATE_GS && update != SACD_UPDATE_JACOBI)
     return fail(SACD_ERR_INVALID_ARG, "unknown update rule %d", (int)update);
   SACD_TRY(enter(t->dev));
@@ -924,10 +994,6 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   SACD_TRY(check_mode(m, mode));
   if (which < 0 || which > 2 || reps < 1 || !avg_ms) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
   SACD_TRY(enter(m->t->dev));
-  sacd_tensor *t = m->t;
-  int a, b;
-  other_modes(mode, &a, &b);
-  const int I = (int)t->dims[mode];
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
@@ -937,15 +1003,11 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   HIP_TRY(hipEventRecord(e0, m->s));
   for (int i = 0; i < reps; ++i) {
     if (which == 0)
-      HIP_TRY(launch_mttkrp(m->RP, m->plan[mode], t->keys[mode], t->vals[mode], t->lay[mode], m->A[a],
-                            m->A[b], m->M[mode], m->part, m->s));
+      HIP_TRY(launch_mttkrp(m->RP, mttkrp_args(m, mode), m->s));
     else if (which == 1)
-      HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, I, m->A[mode], m->M[mode], m->Z[mode],
-                                   m->H[mode], m->hinfo[mode], m->st + mode, m->gpart, m->inner_part,
-                                   m->cnt_part, m->selmask[mode], m->s));
+      HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, is_bf16(m), upd_args(m, mode), m->s));
     else
-      HIP_TRY(launch_importance(m->RP, I, m->A[mode], m->M[mode], m->H[mode], m->hinfo[mode],
-                                m->ti_part, m->st + mode, m->s));
+      HIP_TRY(launch_importance(m->RP, is_bf16(m), imp_args(m, mode), m->s));
   }
   HIP_TRY(hipEventRecord(e1, m->s));
   HIP_TRY(hipEventSynchronize(e1));
@@ -956,9 +1018,7 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   *avg_ms = ms / reps;
   if (which == 0) {
     // restore the complete MTTKRP (spanning slices) for later sweeps' diagnostics
-    HIP_TRY(launch_mttkrp_fix(m->RP, m->plan[mode], t->ptr[mode], I, m->part, m->M[mode], m->G64[a],
-                              m->G64[b], m->H[mode], m->hinfo[mode],
-                              m->st + mode, m->s));
+    HIP_TRY(launch_mttkrp_fix(m->RP, fix_args(m, mode), m->s));
   }
   HIP_TRY(hipMemcpyAsync(m->st + mode, &saved, sizeof(ModeState), hipMemcpyHostToDevice, m->s));
   HIP_TRY(hipStreamSynchronize(m->s));

@@ -123,35 +123,89 @@ struct MttkrpPlan {
   int nslots;         // partial slots
 };
 int mttkrp_units_per_block(int RP);
-hipError_t launch_mttkrp(int RP, const MttkrpPlan &p, const unsigned long long *keys, const float *vals,
-                         KeyLayout lay, const float *Aa, const float *Ab, float *M, float *part,
-                         hipStream_t s);
-hipError_t launch_mttkrp_fix(int RP, const MttkrpPlan &p, const int *ptr, int I, const float *part,
-                             float *M, const double *Ga, const double *Gb, float *H, HInfo *hinfo,
-                             ModeState *st, hipStream_t s);
+int mttkrp_blocks(int RP, int nunits);
+__host__ __device__ inline int fix_row_blocks(int I) { return (I + kThreads - 1) / kThreads; }
+int fix_blocks(int nlong, int I);
+struct MttkrpArgs {
+  const unsigned long long *keys;
+  const float *vals;
+  const int4 *units;
+  int nunits;
+  KeyLayout lay;
+  const float *Aa, *Ab;
+  float *M, *part;
+};
+struct FixArgs {
+  const int4 *longs;
+  int nlong;
+  const float *part;
+  const int *ptr;
+  int I;
+  float *M;
+  const double *Ga, *Gb;
+  float *H;
+  HInfo *hinfo;
+  ModeState *st;
+};
+hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s);
+hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
+hipError_t launch_mttkrp_fix(int RP, const FixArgs &a, hipStream_t s);
+hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 
 // sweep.hip
-int rows_per_block(int RP);
-hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long seed,
-                              unsigned long long offset, hipStream_t s);
-hipError_t launch_importance(int RP, int I, const float *A, const float *M, const float *H,
-                             const HInfo *hinfo, double *ti_part, ModeState *st, hipStream_t s);
-hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, const float *M,
-                                float *Z, const float *H, const HInfo *hinfo, const ModeState *st,
-                                float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
-                                hipStream_t s);
-hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s);
-// Gram reduction buffers (see k_gram_final).
-struct GramReduce {
+// Arguments of one job's element kernels.  The solo launchers pass them by
+// value; the job-batched launchers take device arrays of them plus a block
+// map with one int4 (job, block of the job, blocks of the job, 0) per block.
+struct ImpArgs {
+  int I;
+  const float *A, *M, *H;
+  const HInfo *hi;
+  double *ti_part;
+  ModeState *st;
+};
+struct UpdArgs {
+  int I;
+  float *A;
+  const float *M;
+  float *Z;
+  const float *H;
+  const HInfo *hi;
+  const ModeState *st;
+  float *gpart;
+  double *inner_part;
+  int *cnt_part;
+  uint8_t *selmask;
+};
+struct GramArgs {
   int nparts;           // per-block partials written by the update / Gram kernel
   const float *gpart;   // nparts x RP x RP
   double *mpart;        // gram_model_parts(RP) model-norm partials
+  double *Gn;           // result Gram_n (RP x RP, FP64)
+  const double *Ga, *Gb;  // the other modes' Grams (objective only)
+  const double *inner_part;
+  const int *cnt_part;
+  long long *colcnt;
+  double normX2;
+  int with_f;
   unsigned *counter;    // arrival counter (zero between launches)
+  ModeState *st;
 };
+int rows_per_block(int RP);
+int importance_blocks(int RP, int I);
+int update_blocks(int RP, int I);
+int gram_final_blocks(int RP);
 int gram_model_parts(int RP);
-hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
-                             const double *inner_part, const int *cnt_part, long long *colcnt,
-                             double normX2, int with_f, ModeState *st, hipStream_t s);
+hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long seed,
+                              unsigned long long offset, hipStream_t s);
+hipError_t launch_importance(int RP, bool bf, const ImpArgs &a, hipStream_t s);
+hipError_t launch_importance_b(int RP, bool bf, const ImpArgs *jobs, const int4 *bmap, int nblocks,
+                               hipStream_t s);
+hipError_t launch_select_update(int RP, int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s);
+hipError_t launch_select_update_b(int RP, bool bf, const UpdArgs *jobs, const int4 *bmap, int nblocks,
+                                  hipStream_t s);
+hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s);
+hipError_t launch_gram_final(int RP, const GramArgs &a, hipStream_t s);
+hipError_t launch_gram_final_b(int RP, const GramArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,
                              KeyLayout lay0, int RP, const float *A0, const float *A1,
                              const float *A2, double *partials, int nparts, double *out,

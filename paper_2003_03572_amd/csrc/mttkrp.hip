@@ -43,21 +43,25 @@ struct MCfg {
 __device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
 __device__ __forceinline__ void st4(float *p, f32x4 v) { *(f32x4 *)p = v; }
 
+// Block blk of the MTTKRP of one sweep.
 template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp(const unsigned long long *__restrict__ keys,
-                                                     const float *__restrict__ vals,
-                                                     const int4 *__restrict__ units, int nunits,
-                                                     KeyLayout lay, const float *__restrict__ Aa,
-                                                     const float *__restrict__ Ab,
-                                                     float *__restrict__ M,
-                                                     float *__restrict__ part) {
+__device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
+  const unsigned long long *__restrict__ keys = args.keys;
+  const float *__restrict__ vals = args.vals;
+  const int4 *__restrict__ units = args.units;
+  const int nunits = args.nunits;
+  const KeyLayout lay = args.lay;
+  const float *__restrict__ Aa = args.Aa;
+  const float *__restrict__ Ab = args.Ab;
+  float *__restrict__ M = args.M;
+  float *__restrict__ part = args.part;
   using Cf = MCfg<RP>;
   constexpr int LPN = Cf::LPN, NV = Cf::NV, U = Cf::U;
   constexpr int UPB = kThreads / LPN;  // units per block
   __shared__ __align__(16) float s_acc[UPB * RP];
   __shared__ int s_slot[UPB];
   const int ub = threadIdx.x / LPN;  // unit within the block
-  const int gid = blockIdx.x * UPB + ub;
+  const int gid = blk * UPB + ub;
   const bool active = gid < nunits;
   // lane sub owns the float4 column chunks 4*sub + 4*LPN*j (j < NV): each
   // load instruction of a lane group covers contiguous bytes of a row
@@ -170,6 +174,19 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(const unsigned long long *_
   }
 }
 
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a) {
+  mttkrp_body<RP>(a, blockIdx.x);
+}
+
+// Job-batched form: block map entry (job, block of the job, blocks of the job).
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_mttkrp_b(const MttkrpArgs *__restrict__ jobs,
+                                                       const int4 *__restrict__ bmap) {
+  const int4 m = bmap[blockIdx.x];
+  mttkrp_body<RP>(jobs[m.x], m.y);
+}
+
 }  // namespace
 
 int mttkrp_units_per_block(int RP) {
@@ -188,15 +205,20 @@ namespace {
 // block forms H = Gram_a * Gram_b, L = ||H||_F and the diagonal of H for the
 // element kernels of this sweep (eq. 10, eq. 15, Alg. 1).
 template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_fix(const int4 *__restrict__ longs, int nlong,
-                                                         const float *__restrict__ part,
-                                                         const int *__restrict__ ptr, int I,
-                                                         float *__restrict__ M, int row_blocks,
-                                                         const double *__restrict__ Ga,
-                                                         const double *__restrict__ Gb,
-                                                         float *__restrict__ H, HInfo *hinfo,
-                                                         ModeState *st) {
-  const int b = blockIdx.x, tid = threadIdx.x;
+__device__ __forceinline__ void fix_body(const FixArgs &args, int blk) {
+  const int4 *__restrict__ longs = args.longs;
+  const int nlong = args.nlong;
+  const float *__restrict__ part = args.part;
+  const int *__restrict__ ptr = args.ptr;
+  const int I = args.I;
+  float *__restrict__ M = args.M;
+  const int row_blocks = fix_row_blocks(I);
+  const double *__restrict__ Ga = args.Ga;
+  const double *__restrict__ Gb = args.Gb;
+  float *__restrict__ H = args.H;
+  HInfo *hinfo = args.hinfo;
+  ModeState *st = args.st;
+  const int b = blk, tid = threadIdx.x;
   if (b < nlong) {
     const int4 L = longs[b];  // (slice, first slot, slots, -)
     constexpr int Q = RP / 4;
@@ -263,51 +285,79 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(const int4 *__restrict_
 }
 
 template <int RP>
-hipError_t launch_mttkrp_t(const MttkrpPlan &p, const unsigned long long *keys, const float *vals,
-                           KeyLayout lay, const float *Aa, const float *Ab, float *M, float *part,
-                           hipStream_t s) {
-  if (p.nunits <= 0) return hipSuccess;
-  const long long threads = (long long)p.nunits * MCfg<RP>::LPN;
-  const int blocks = (int)((threads + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_mttkrp<RP>, dim3(blocks), dim3(kThreads), 0, s, keys, vals, p.units, p.nunits,
-                     lay, Aa, Ab, M, part);
-  return hipGetLastError();
+__global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs a) {
+  fix_body<RP>(a, blockIdx.x);
 }
 
 template <int RP>
-hipError_t launch_fix_t(const MttkrpPlan &p, const int *ptr, int I, const float *part, float *M,
-                        const double *Ga, const double *Gb, float *H, HInfo *hinfo, ModeState *st,
-                        hipStream_t s) {
-  const int row_blocks = (I + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_mttkrp_fix<RP>, dim3(p.nlong + row_blocks + 1), dim3(kThreads), 0, s, p.longs,
-                     p.nlong, part, ptr, I, M, row_blocks, Ga, Gb, H, hinfo, st);
-  return hipGetLastError();
+__global__ __launch_bounds__(kThreads) void k_mttkrp_fix_b(const FixArgs *__restrict__ jobs,
+                                                           const int4 *__restrict__ bmap) {
+  const int4 m = bmap[blockIdx.x];
+  fix_body<RP>(jobs[m.x], m.y);
 }
+
+template <template <int> class F, typename... Args>
+hipError_t rp_dispatch(int RP, Args &&...args) {
+  switch (RP) {
+    case 16: return F<16>::run(args...);
+    case 32: return F<32>::run(args...);
+    case 64: return F<64>::run(args...);
+    case 128: return F<128>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int RP>
+struct MtL {
+  static hipError_t run(const MttkrpArgs &a, hipStream_t s) {
+    const int nb = mttkrp_blocks(RP, a.nunits);
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mttkrp<RP>, dim3(nb), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct MtBL {
+  static hipError_t run(const MttkrpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mttkrp_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct FxL {
+  static hipError_t run(const FixArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_mttkrp_fix<RP>, dim3(fix_blocks(a.nlong, a.I)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct FxBL {
+  static hipError_t run(const FixArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mttkrp_fix_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    return hipGetLastError();
+  }
+};
 
 }  // namespace
 
-hipError_t launch_mttkrp(int RP, const MttkrpPlan &p, const unsigned long long *keys, const float *vals,
-                         KeyLayout lay, const float *Aa, const float *Ab, float *M, float *part,
-                         hipStream_t s) {
-  switch (RP) {
-    case 16: return launch_mttkrp_t<16>(p, keys, vals, lay, Aa, Ab, M, part, s);
-    case 32: return launch_mttkrp_t<32>(p, keys, vals, lay, Aa, Ab, M, part, s);
-    case 64: return launch_mttkrp_t<64>(p, keys, vals, lay, Aa, Ab, M, part, s);
-    case 128: return launch_mttkrp_t<128>(p, keys, vals, lay, Aa, Ab, M, part, s);
-    default: return hipErrorInvalidValue;
-  }
+int mttkrp_blocks(int RP, int nunits) {
+  const int upb = mttkrp_units_per_block(RP);
+  return (nunits + upb - 1) / upb;
 }
+int fix_blocks(int nlong, int I) { return nlong + fix_row_blocks(I) + 1; }
 
-hipError_t launch_mttkrp_fix(int RP, const MttkrpPlan &p, const int *ptr, int I, const float *part,
-                             float *M, const double *Ga, const double *Gb, float *H, HInfo *hinfo,
-                             ModeState *st, hipStream_t s) {
-  switch (RP) {
-    case 16: return launch_fix_t<16>(p, ptr, I, part, M, Ga, Gb, H, hinfo, st, s);
-    case 32: return launch_fix_t<32>(p, ptr, I, part, M, Ga, Gb, H, hinfo, st, s);
-    case 64: return launch_fix_t<64>(p, ptr, I, part, M, Ga, Gb, H, hinfo, st, s);
-    case 128: return launch_fix_t<128>(p, ptr, I, part, M, Ga, Gb, H, hinfo, st, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s) { return rp_dispatch<MtL>(RP, a, s); }
+hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {
+  return rp_dispatch<MtBL>(RP, jobs, bmap, nblocks, s);
+}
+hipError_t launch_mttkrp_fix(int RP, const FixArgs &a, hipStream_t s) { return rp_dispatch<FxL>(RP, a, s); }
+hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {
+  return rp_dispatch<FxBL>(RP, jobs, bmap, nblocks, s);
 }
 
 }  // namespace sacd

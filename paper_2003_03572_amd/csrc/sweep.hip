@@ -35,6 +35,21 @@ __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// BF16 operands (mixed-precision form): FP32 -> BF16 with round to nearest
+// even (inputs are finite), 16x16x16 MFMA with FP32 accumulation.  Lane l
+// supplies A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j < 4.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Load of data stored by other blocks of the same grid.  Every block stores,
 // then issues a device-scope fence (release) before it increments the
 // arrival counter; the last block issues a device-scope fence (acquire) after
@@ -94,23 +109,39 @@ __device__ __forceinline__ void load_h(float *sH, const float *__restrict__ H) {
 }
 
 // C tile (16 x 16) of the block's rows times H: rows tr*16.., columns tc*16..
-template <int RP>
+// BF: operands rounded to BF16, FP32 accumulation.
+template <int RP, bool BF>
 __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int tr, int tc, int lane) {
   using Cf = UCfg<RP>;
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
 #pragma unroll
-  for (int kk = 0; kk < RP / 4; ++kk) {
-    const float a = sA[(tr * 16 + (lane & 15)) * Cf::STR + kk * 4 + (lane >> 4)];
-    const float b = sH[(kk * 4 + (lane >> 4)) * (RP + 1) + tc * 16 + (lane & 15)];
-    acc = mfma4(a, b, acc);
+    for (int kk = 0; kk < RP / 16; ++kk) {
+      bf16x4 a, b;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kk * 16 + 4 * (lane >> 4) + j;
+        a[j] = to_bf16(sA[(tr * 16 + (lane & 15)) * Cf::STR + k]);
+        b[j] = to_bf16(sH[k * (RP + 1) + tc * 16 + (lane & 15)]);
+      }
+      acc = mfma_bf16(a, b, acc);
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < RP / 4; ++kk) {
+      const float a = sA[(tr * 16 + (lane & 15)) * Cf::STR + kk * 4 + (lane >> 4)];
+      const float b = sH[(kk * 4 + (lane >> 4)) * (RP + 1) + tc * 16 + (lane & 15)];
+      acc = mfma4(a, b, acc);
+    }
   }
   return acc;
 }
 
 // Partial Gram matrix of the block's rows (the upper 16x16 tiles of
 // sA^T sA), written to gp.  Four independent MFMA accumulation chains over
-// interleaved row groups, added in a fixed order at the end.
-template <int RP>
+// interleaved row groups, added in a fixed order at the end.  BF: operands
+// rounded to BF16, FP32 accumulation.
+template <int RP, bool BF>
 __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, int lane) {
   using Cf = UCfg<RP>;
   constexpr int n16 = RP / 16;
@@ -120,13 +151,29 @@ __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, i
     f32x4 acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < Cf::RB; k0 += 16) {
+    if constexpr (BF) {
+      for (int k0 = 0; k0 < Cf::RB; k0 += 64) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int row = k0 + 4 * c + (lane >> 4);
-        const float a = sA[row * Cf::STR + ti_ * 16 + (lane & 15)];
-        const float b = sA[row * Cf::STR + tj * 16 + (lane & 15)];
-        acc[c] = mfma4(a, b, acc[c]);
+        for (int c = 0; c < 4; ++c) {
+          bf16x4 a, b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int row = k0 + 16 * c + 4 * (lane >> 4) + j;
+            a[j] = to_bf16(sA[row * Cf::STR + ti_ * 16 + (lane & 15)]);
+            b[j] = to_bf16(sA[row * Cf::STR + tj * 16 + (lane & 15)]);
+          }
+          acc[c] = mfma_bf16(a, b, acc[c]);
+        }
+      }
+    } else {
+      for (int k0 = 0; k0 < Cf::RB; k0 += 16) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int row = k0 + 4 * c + (lane >> 4);
+          const float a = sA[row * Cf::STR + ti_ * 16 + (lane & 15)];
+          const float b = sA[row * Cf::STR + tj * 16 + (lane & 15)];
+          acc[c] = mfma4(a, b, acc[c]);
+        }
       }
     }
     const f32x4 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
@@ -134,23 +181,6 @@ __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, i
     for (int v = 0; v < 4; ++v)
       gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = tot[v];
   }
-}
-
-// Sequential sum of n values base[0], base[stride], ... in index order,
-// loads issued eight at a time so their latencies overlap.
-template <typename Acc, typename T>
-__device__ __forceinline__ Acc sum_strided(const T *base, long long stride, int n) {
-  Acc s = 0;
-  int i = 0;
-  for (; i + 8 <= n; i += 8) {
-    T v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = base[(long long)(i + k) * stride];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s += (Acc)v[k];
-  }
-  for (; i < n; ++i) s += (Acc)base[(long long)i * stride];
-  return s;
 }
 
 // Block-wide FP64 sum in a fixed tree order (all threads call; result in red[0]).
@@ -166,19 +196,23 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return r;
 }
 
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__restrict__ A,
-                                                         const float *__restrict__ M,
-                                                         const float *__restrict__ H,
-                                                         const HInfo *__restrict__ hi,
-                                                         double *__restrict__ ti_part, ModeState *st) {
+// Block blk (of nblk) of the importance pass of one sweep.
+template <int RP, bool BF>
+__device__ __forceinline__ void importance_body(const ImpArgs &args, int blk, int nblk) {
+  const int I = args.I;
+  const float *__restrict__ A = args.A;
+  const float *__restrict__ M = args.M;
+  const float *__restrict__ H = args.H;
+  const HInfo *__restrict__ hi = args.hi;
+  double *__restrict__ ti_part = args.ti_part;
+  ModeState *st = args.st;
   using Cf = UCfg<RP>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
   __shared__ double red[kThreads];
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int row0 = blockIdx.x * Cf::RB;
+  const int row0 = blk * Cf::RB;
   // this thread's MTTKRP entries for all its tiles, fetched before anything
   // waits on them
   float mv[Cf::NTW][4];
@@ -202,7 +236,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP>(sA, sH, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -218,16 +252,16 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
   }
   const double bs = block_sum(zs, red);
   if (tid == 0) {
-    ti_part[blockIdx.x] = bs;
+    ti_part[blk] = bs;
     __threadfence();
     const unsigned prev = atomicAdd(&st->cnt_imp, 1u);
-    s_last = (prev == gridDim.x - 1);
+    s_last = (prev == (unsigned)nblk - 1);
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   double s = 0.0;
-  for (int i = tid; i < (int)gridDim.x; i += kThreads) s += ld_coherent(&ti_part[i]);
+  for (int i = tid; i < nblk; i += kThreads) s += ld_coherent(&ti_part[i]);
   const double ti = block_sum(s, red);
   if (tid == 0) {
     const long long k = st->k + 1;
@@ -239,6 +273,19 @@ __global__ __launch_bounds__(kThreads) void k_importance(int I, const float *__r
     st->ti_prev = ti;  // becomes ti^{k-1} of the next sweep (eq. 26)
     st->cnt_imp = 0;
   }
+}
+
+template <int RP, bool BF>
+__global__ __launch_bounds__(kThreads) void k_importance(ImpArgs a) {
+  importance_body<RP, BF>(a, blockIdx.x, gridDim.x);
+}
+
+// Job-batched form: block map entry (job, block of the job, blocks of the job).
+template <int RP, bool BF>
+__global__ __launch_bounds__(kThreads) void k_importance_b(const ImpArgs *__restrict__ jobs,
+                                                           const int4 *__restrict__ bmap) {
+  const int4 m = bmap[blockIdx.x];
+  importance_body<RP, BF>(jobs[m.x], m.y, m.z);
 }
 
 // Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
@@ -295,12 +342,20 @@ __device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const uns
   }
 }
 
-template <int RP, int UPD, bool DIAG>
-__global__ __launch_bounds__(kThreads) void k_select_update(
-    int I, float *__restrict__ A, const float *__restrict__ M, float *__restrict__ Z,
-    const float *__restrict__ H, const HInfo *__restrict__ hi, const ModeState *__restrict__ st,
-    float *__restrict__ gpart, double *__restrict__ inner_part, int *__restrict__ cnt_part,
-    uint8_t *__restrict__ selmask) {
+// Block blk of the selection / update pass of one sweep.
+template <int RP, int UPD, bool DIAG, bool BF>
+__device__ __forceinline__ void select_update_body(const UpdArgs &args, int blk) {
+  const int I = args.I;
+  float *__restrict__ A = args.A;
+  const float *__restrict__ M = args.M;
+  float *__restrict__ Z = args.Z;
+  const float *__restrict__ H = args.H;
+  const HInfo *__restrict__ hi = args.hi;
+  const ModeState *__restrict__ st = args.st;
+  float *__restrict__ gpart = args.gpart;
+  double *__restrict__ inner_part = args.inner_part;
+  int *__restrict__ cnt_part = args.cnt_part;
+  uint8_t *__restrict__ selmask = args.selmask;
   using Cf = UCfg<RP>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
@@ -309,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   __shared__ double red[kThreads];
   __shared__ int sCnt[RP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int row0 = blockIdx.x * Cf::RB;
+  const int row0 = blk * Cf::RB;
   // this thread's MTTKRP and previous-importance entries for all its tiles,
   // fetched before anything waits on them
   float mreg[Cf::NTW][4], zpreg[Cf::NTW][4];
@@ -335,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP>(sA, sH, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -391,14 +446,26 @@ __global__ __launch_bounds__(kThreads) void k_select_update(
     }
   }
   const double bs = block_sum(inner, red);
-  if (tid == 0) inner_part[blockIdx.x] = bs;
-  for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blockIdx.x * RP + c] = sCnt[c];
+  if (tid == 0) inner_part[blk] = bs;
+  for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
-  gram_tiles<RP>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
+  gram_tiles<RP, BF>(sA, gpart + (long long)blk * RP * RP, wv, lane);
+}
+
+template <int RP, int UPD, bool DIAG, bool BF>
+__global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs a) {
+  select_update_body<RP, UPD, DIAG, BF>(a, blockIdx.x);
+}
+
+template <int RP, bool BF>
+__global__ __launch_bounds__(kThreads) void k_select_update_b(const UpdArgs *__restrict__ jobs,
+                                                              const int4 *__restrict__ bmap) {
+  const int4 m = bmap[blockIdx.x];
+  select_update_body<RP, 0, false, BF>(jobs[m.x], m.y);
 }
 
 // Gram partials of an arbitrary factor (initialisation, set_factor).
-template <int RP>
+template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *__restrict__ A,
                                                            float *__restrict__ gpart) {
   using Cf = UCfg<RP>;
@@ -406,7 +473,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *_
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   load_rows<RP>(sA, A, blockIdx.x * Cf::RB, I);
   __syncthreads();
-  gram_tiles<RP>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
+  gram_tiles<RP, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
 // Sum of the values base[p * stride], p = s, s + 16, s + 32, ... < n, in
@@ -457,17 +524,26 @@ constexpr int gram_strips() {
 //   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
 // and the total selection count.
 template <int RP>
-__global__ __launch_bounds__(kThreads) void k_gram_final(
-    int nparts, const float *__restrict__ gpart, double *__restrict__ mpart, double *Gn,
-    const double *__restrict__ Ga, const double *__restrict__ Gb, const double *__restrict__ inner_part,
-    const int *__restrict__ cnt_part, long long *__restrict__ colcnt, double normX2, int with_f,
-    unsigned *counter, ModeState *st) {
+__device__ __forceinline__ void gram_final_body(const GramArgs &args, int blk, int nblk) {
+  const int nparts = args.nparts;
+  const float *__restrict__ gpart = args.gpart;
+  double *__restrict__ mpart = args.mpart;
+  double *Gn = args.Gn;
+  const double *__restrict__ Ga = args.Ga;
+  const double *__restrict__ Gb = args.Gb;
+  const double *__restrict__ inner_part = args.inner_part;
+  const int *__restrict__ cnt_part = args.cnt_part;
+  long long *__restrict__ colcnt = args.colcnt;
+  const double normX2 = args.normX2;
+  const int with_f = args.with_f;
+  unsigned *counter = args.counter;
+  ModeState *st = args.st;
   constexpr int RR = RP * RP, n16 = RP / 16, NS = gram_strips<RP>();
   __shared__ double red[kThreads];
   __shared__ long long redl[kThreads];
   __shared__ int s_last;
   const int tid = threadIdx.x, e = tid & 15, s = tid >> 4;
-  const int b = blockIdx.x;
+  const int b = blk;
   if (b < NS) {
     int rem = b, ti = 0;
     while (rem >= 16 * (n16 - ti)) {
@@ -520,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(
   if (tid == 0) {
     __threadfence();
     const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
+    s_last = (prev == (unsigned)nblk - 1);
   }
   __syncthreads();
   if (!s_last) return;
@@ -540,6 +616,18 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(
     if (tid == 0) st->nsel = (long long)all;
   }
   if (tid == 0) *counter = 0;
+}
+
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs a) {
+  gram_final_body<RP>(a, blockIdx.x, gridDim.x);
+}
+
+template <int RP>
+__global__ __launch_bounds__(kThreads) void k_gram_final_b(const GramArgs *__restrict__ jobs,
+                                                           const int4 *__restrict__ bmap) {
+  const int4 m = bmap[blockIdx.x];
+  gram_final_body<RP>(jobs[m.x], m.y, m.z);
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_factor(float *__restrict__ A, int I, int R, int RP,
@@ -656,98 +744,124 @@ hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long
   return hipGetLastError();
 }
 
-template <int RP>
-static hipError_t imp_t(int I, const float *A, const float *M, const float *H, const HInfo *hinfo,
-                        double *ti_part, ModeState *st, hipStream_t s) {
-  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
-  hipLaunchKernelGGL(k_importance<RP>, dim3(nb), dim3(kThreads), 0, s, I, A, M, H, hinfo, ti_part, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_importance(int RP, int I, const float *A, const float *M, const float *H,
-                             const HInfo *hinfo, double *ti_part, ModeState *st, hipStream_t s) {
-  switch (RP) {
-    case 16: return imp_t<16>(I, A, M, H, hinfo, ti_part, st, s);
-    case 32: return imp_t<32>(I, A, M, H, hinfo, ti_part, st, s);
-    case 64: return imp_t<64>(I, A, M, H, hinfo, ti_part, st, s);
-    case 128: return imp_t<128>(I, A, M, H, hinfo, ti_part, st, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int RP, int UPD, bool DIAG>
-static hipError_t upd_t3(int I, float *A, const float *M, float *Z, const float *H, const HInfo *hinfo,
-                         const ModeState *st, float *gpart, double *inner_part, int *cnt_part,
-                         uint8_t *selmask, hipStream_t s) {
-  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
-  hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG>), dim3(nb), dim3(kThreads), 0, s, I, A, M, Z, H,
-                     hinfo, st, gpart, inner_part, cnt_part, selmask);
-  return hipGetLastError();
-}
-
-template <int RP>
-static hipError_t upd_t(int update, bool diag, int I, float *A, const float *M, float *Z, const float *H,
-                        const HInfo *hinfo, const ModeState *st, float *gpart, double *inner_part,
-                        int *cnt_part, uint8_t *selmask, hipStream_t s) {
-  if (update == 0)
-    return diag ? upd_t3<RP, 0, true>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s)
-                : upd_t3<RP, 0, false>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-  return diag ? upd_t3<RP, 1, true>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s)
-              : upd_t3<RP, 1, false>(I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-}
-
-hipError_t launch_select_update(int RP, int update, bool diag, int I, float *A, const float *M,
-                                float *Z, const float *H, const HInfo *hinfo, const ModeState *st,
-                                float *gpart, double *inner_part, int *cnt_part, uint8_t *selmask,
-                                hipStream_t s) {
-  switch (RP) {
-    case 16: return upd_t<16>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-    case 32: return upd_t<32>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-    case 64: return upd_t<64>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-    case 128: return upd_t<128>(update, diag, I, A, M, Z, H, hinfo, st, gpart, inner_part, cnt_part, selmask, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int RP>
-static hipError_t gp_t(int I, const float *A, float *gpart, hipStream_t s) {
-  const int nb = (I + UCfg<RP>::RB - 1) / UCfg<RP>::RB;
-  hipLaunchKernelGGL(k_gram_partial<RP>, dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_partial(int RP, int I, const float *A, float *gpart, hipStream_t s) {
-  switch (RP) {
-    case 16: return gp_t<16>(I, A, gpart, s);
-    case 32: return gp_t<32>(I, A, gpart, s);
-    case 64: return gp_t<64>(I, A, gpart, s);
-    case 128: return gp_t<128>(I, A, gpart, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int RP>
-static hipError_t gf_t(const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
-                       const double *inner_part, const int *cnt_part, long long *colcnt, double normX2,
-                       int with_f, ModeState *st, hipStream_t s) {
-  const int nb = gram_strips<RP>() + RP / 16 + 1;
-  hipLaunchKernelGGL(k_gram_final<RP>, dim3(nb), dim3(kThreads), 0, s, g.nparts, g.gpart, g.mpart, Gn, Ga,
-                     Gb, inner_part, cnt_part, colcnt, normX2, with_f, g.counter, st);
-  return hipGetLastError();
-}
-
+int importance_blocks(int RP, int I) { return (I + rows_per_block(RP) - 1) / rows_per_block(RP); }
+int update_blocks(int RP, int I) { return importance_blocks(RP, I); }
+int gram_final_blocks(int RP) { return 16 * (RP / 16) * (RP / 16 + 1) / 2 + RP / 16 + 1; }
 int gram_model_parts(int RP) { return 16 * (RP / 16) * (RP / 16 + 1) / 2; }
 
-hipError_t launch_gram_final(int RP, const GramReduce &g, double *Gn, const double *Ga, const double *Gb,
-                             const double *inner_part, const int *cnt_part, long long *colcnt,
-                             double normX2, int with_f, ModeState *st, hipStream_t s) {
+namespace {
+
+// Dispatch of a launcher template over the padded rank.
+template <template <int> class F, typename... Args>
+hipError_t rp_dispatch(int RP, Args &&...args) {
   switch (RP) {
-    case 16: return gf_t<16>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 32: return gf_t<32>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 64: return gf_t<64>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
-    case 128: return gf_t<128>(g, Gn, Ga, Gb, inner_part, cnt_part, colcnt, normX2, with_f, st, s);
+    case 16: return F<16>::run(args...);
+    case 32: return F<32>::run(args...);
+    case 64: return F<64>::run(args...);
+    case 128: return F<128>::run(args...);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int RP>
+struct ImpL {
+  static hipError_t run(bool bf, const ImpArgs &a, hipStream_t s) {
+    const int nb = importance_blocks(RP, a.I);
+    if (nb == 0) return hipSuccess;
+    if (bf) hipLaunchKernelGGL((k_importance<RP, true>), dim3(nb), dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_importance<RP, false>), dim3(nb), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct ImpBL {
+  static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    if (bf) hipLaunchKernelGGL((k_importance_b<RP, true>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    else hipLaunchKernelGGL((k_importance_b<RP, false>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    return hipGetLastError();
+  }
+};
+
+template <int RP, int UPD, bool DIAG>
+hipError_t upd_launch(bool bf, const UpdArgs &a, int nb, hipStream_t s) {
+  if (bf) hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true>), dim3(nb), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false>), dim3(nb), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int RP>
+struct UpdL {
+  static hipError_t run(int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s) {
+    const int nb = update_blocks(RP, a.I);
+    if (nb == 0) return hipSuccess;
+    if (update == 0)
+      return diag ? upd_launch<RP, 0, true>(bf, a, nb, s) : upd_launch<RP, 0, false>(bf, a, nb, s);
+    return diag ? upd_launch<RP, 1, true>(bf, a, nb, s) : upd_launch<RP, 1, false>(bf, a, nb, s);
+  }
+};
+
+template <int RP>
+struct UpdBL {
+  static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    if (bf) hipLaunchKernelGGL((k_select_update_b<RP, true>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    else hipLaunchKernelGGL((k_select_update_b<RP, false>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct GpL {
+  static hipError_t run(bool bf, int I, const float *A, float *gpart, hipStream_t s) {
+    const int nb = update_blocks(RP, I);
+    if (nb == 0) return hipSuccess;
+    if (bf) hipLaunchKernelGGL((k_gram_partial<RP, true>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
+    else hipLaunchKernelGGL((k_gram_partial<RP, false>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct GfL {
+  static hipError_t run(const GramArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_gram_final<RP>, dim3(gram_final_blocks(RP)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int RP>
+struct GfBL {
+  static hipError_t run(const GramArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gram_final_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t launch_importance(int RP, bool bf, const ImpArgs &a, hipStream_t s) {
+  return rp_dispatch<ImpL>(RP, bf, a, s);
+}
+hipError_t launch_importance_b(int RP, bool bf, const ImpArgs *jobs, const int4 *bmap, int nblocks,
+                               hipStream_t s) {
+  return rp_dispatch<ImpBL>(RP, bf, jobs, bmap, nblocks, s);
+}
+hipError_t launch_select_update(int RP, int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s) {
+  return rp_dispatch<UpdL>(RP, update, diag, bf, a, s);
+}
+hipError_t launch_select_update_b(int RP, bool bf, const UpdArgs *jobs, const int4 *bmap, int nblocks,
+                                  hipStream_t s) {
+  return rp_dispatch<UpdBL>(RP, bf, jobs, bmap, nblocks, s);
+}
+hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s) {
+  return rp_dispatch<GpL>(RP, bf, I, A, gpart, s);
+}
+hipError_t launch_gram_final(int RP, const GramArgs &a, hipStream_t s) { return rp_dispatch<GfL>(RP, a, s); }
+hipError_t launch_gram_final_b(int RP, const GramArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {
+  return rp_dispatch<GfBL>(RP, jobs, bmap, nblocks, s);
 }
 
 hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,

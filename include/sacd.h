@@ -215,6 +215,71 @@ void sacd_destroy_model(sacd_model *m);
 /* ------------------------------------------------------------------------ */
 /* Misc                                                                      */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------
+ * Serving: many independent jobs resident on one GPU.
+ *
+ * A server holds factorization jobs (a tensor, a rank, a seed) of uneven size.
+ * Requests are queued by sacd_server_submit and admitted first come first
+ * served while the device bytes of the running jobs plus the new job's upper
+ * bound (sacd_job_bytes: resident + transient ingest bytes) stay within the
+ * budget and a slot is free.  Each sacd_server_step admits what fits, then
+ * runs one outer iteration (Alg. 1: sweeps of modes 0, 1, 2) of every running
+ * job with job-batched kernels -- per mode and per padded rank one launch of
+ * each sweep kernel covers all jobs -- replayed from a HIP graph while the
+ * set of running jobs is unchanged, and retires the jobs that met the
+ * stopping rule of sacd_run_until (relative fit change < tol after at least
+ * two iterations, or max_iter).  A job's arithmetic is the same as when it
+ * runs alone (sacd_init_factors + sacd_run_until with the same arguments):
+ * results are bit-identical alone and in the mix.  Updates are Gauss-Seidel.
+ * The server's work runs on its stream; calls synchronise it. */
+typedef struct sacd_server sacd_server;
+
+typedef struct {
+  int64_t budget_bytes;     /* device bytes the running jobs may hold */
+  int32_t max_slots;        /* running jobs at most */
+  int32_t max_iter;         /* outer iterations per job at most */
+  double tol;               /* relative fit change that stops a job */
+  sacd_precision precision; /* arithmetic of every job */
+  int32_t use_graphs;       /* 1: replay unchanged job sets from a HIP graph */
+} sacd_server_config;
+
+enum { SACD_JOB_QUEUED = 0, SACD_JOB_RUNNING = 1, SACD_JOB_DONE = 2, SACD_JOB_FAILED = 3 };
+
+typedef struct {
+  int32_t running, queued;
+  int64_t bytes_in_use, peak_bytes;
+  int64_t steps, graph_builds, graph_launches, eager_launches;
+} sacd_server_stats_t;
+
+/* Upper bounds of the device bytes of a job of this shape (host only, no GPU
+ * call): *resident while it runs, *transient extra during its ingest. */
+sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, int64_t *resident,
+                           int64_t *transient);
+/* alloc, stream: as for sacd_create_tensor (every job's buffers come from
+ * alloc; all work runs on the stream). */
+sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocator *alloc, void *stream,
+                               sacd_server **out);
+/* Queue a job.  idx (nnz x 3 int32, 0-based) and vals (nnz f32) are HOST
+ * arrays, copied at once.  NO_MEMORY if the job's bound exceeds the whole
+ * budget.  *ticket identifies the job in later calls. */
+sacd_status sacd_server_submit(sacd_server *s, const int64_t dims[3], int64_t nnz, const int32_t *idx,
+                               const float *vals, int32_t R, uint64_t seed, int64_t *ticket);
+/* Admit, iterate every running job once, retire finished ones. */
+sacd_status sacd_server_step(sacd_server *s, int32_t *n_running, int32_t *n_queued);
+/* Tickets that finished (done or failed) in the last step: the first
+ * min(cap, *n) are written to tickets (host). */
+sacd_status sacd_server_finished(const sacd_server *s, int64_t *tickets, int32_t cap, int32_t *n);
+/* State (SACD_JOB_*), iterations done, fit and objective of a job; a failed
+ * job returns the status its admission failed with. */
+sacd_status sacd_server_poll(const sacd_server *s, int64_t ticket, int32_t *state, int32_t *iters,
+                             double *fit, double *objective);
+/* Factor `mode` of a done job into dst (HOST, I_n x R row-major f32). */
+sacd_status sacd_server_result(const sacd_server *s, int64_t ticket, int32_t mode, float *dst);
+/* Forget a done or failed job's result. */
+sacd_status sacd_server_release(sacd_server *s, int64_t ticket);
+sacd_status sacd_server_stats(const sacd_server *s, sacd_server_stats_t *out);
+void sacd_server_destroy(sacd_server *s);
+
 const char *sacd_status_string(sacd_status s);
 const char *sacd_last_error(void);
 /* Library version, e.g. "0.1.0". */

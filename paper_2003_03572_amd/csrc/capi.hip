@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <deque>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -1066,6 +1068,571 @@ void sacd_destroy_model(sacd_model *m) {
   delete m;
   if (counted && t->nmodels > 0) t->nmodels--;
   if (t->destroy_pending && t->nmodels == 0) release_tensor(t);
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- serving --
+//
+// Many independent factorization jobs resident on one GPU.  Each job is a
+// tensor plus a model with its own buffers; an iteration of the server runs
+// one outer iteration of every running job with job-batched launches: per
+// mode and per padded rank, one launch of each of the five sweep kernels
+// covers the blocks of all jobs of that rank (a block map gives each block
+// its job and its block index within the job).  The blocks of a job are the
+// ones its solo launches would run, so each job's arithmetic -- partials and
+// their reduction order -- is the same as alone: results are bit-identical
+// alone and in the mix.
+
+namespace {
+
+int64_t al256(int64_t b) { return ((b > 0 ? b : 16) + 255) & ~(int64_t)255; }
+
+int pad_rank(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : (R <= 64 ? 64 : 128)); }
+
+// Upper bounds of the device bytes of a job: resident (tensor + model) and
+// the transient ingest buffers.
+void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int64_t *transient) {
+  const int RP = pad_rank(R);
+  const int64_t slack = 64 * 1024;
+  int64_t maxI = 0, maxunits = 0, ten = 0, mod = 0;
+  for (int n = 0; n < 3; ++n) {
+    const int64_t I = dims[n];
+    maxI = std::max(maxI, I);
+    const int64_t units = nnz / kSegment + I + 2;
+    maxunits = std::max(maxunits, units);
+    ten += al256(8 * nnz) + al256(4 * nnz) + al256(4 * (I + 1)) + al256(16 * units) + al256(16 * (I + 2));
+    mod += 3 * al256(4 * I * RP) + al256(I * RP) + 2 * al256(4 * RP * RP) + al256(8 * RP * RP) +
+           al256(sizeof(HInfo)) + al256(8 * RP);
+  }
+  const int64_t parts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
+  mod += al256(3 * sizeof(ModeState)) + al256(4 * maxunits * RP) + al256(4 * parts * RP * RP) +
+         2 * al256(8 * parts) + al256(4 * parts * RP) + al256(8 * gram_model_parts(RP)) + al256(8 * 1024) +
+         6 * 256;
+  int64_t tb = (int64_t)radix_sort_temp_bytes(nnz);
+  tb = std::max(tb, (int64_t)dedup_temp_bytes(nnz));
+  for (int n = 0; n < 3; ++n) tb = std::max(tb, (int64_t)build_ptr_temp_bytes(nnz, (int)dims[n]));
+  *resident = ten + mod + slack;
+  *transient = 2 * al256(8 * nnz) + 2 * al256(4 * nnz) + al256(tb) + al256(16 * maxunits) + slack;
+}
+
+struct ServerReq {
+  int64_t ticket;
+  int64_t dims[3];
+  int64_t nnz;
+  std::vector<int32_t> idx;
+  std::vector<float> vals;
+  int R;
+  uint64_t seed;
+  int64_t est_resident, est_transient;
+};
+
+struct ServerJob {
+  int64_t ticket;
+  sacd_tensor *t = nullptr;
+  sacd_model *m = nullptr;
+  int64_t bytes = 0;
+  int iters = 0;
+  double prev_fit = 0.0, fit = 0.0, f = 0.0;
+};
+
+struct ServerResult {
+  int state = 0;  // SACD_JOB_*
+  sacd_status err = SACD_OK;
+  int iters = 0;
+  double fit = 0.0, f = 0.0;
+  int64_t dims[3] = {0, 0, 0};
+  int R = 0;
+  std::vector<float> A[3];
+};
+
+// Batched launch tables of the running jobs of one padded rank.
+struct BatchGroup {
+  int RP = 0;
+  std::vector<int> jobs;  // indices into sacd_server::active
+  MttkrpArgs *mt[3] = {};
+  FixArgs *fx[3] = {};
+  ImpArgs *im[3] = {};
+  UpdArgs *up[3] = {};
+  GramArgs *gf[3] = {};
+  int4 *bm_mt[3] = {}, *bm_fx[3] = {}, *bm_im[3] = {}, *bm_gf[3] = {};
+  int nb_mt[3] = {}, nb_fx[3] = {}, nb_im[3] = {}, nb_gf[3] = {};
+};
+
+}  // namespace
+
+struct sacd_server {
+  sacd_server_config cfg{};
+  sacd_allocator alloc{};
+  bool custom_alloc = false;
+  int dev = 0;
+  hipStream_t s = nullptr;
+  bool own_stream = false;
+  std::deque<ServerReq> queue;
+  std::vector<ServerJob> active;
+  std::map<int64_t, ServerResult> results;
+  std::vector<int64_t> finished;  // tickets finished in the last step
+  int64_t next_ticket = 1;
+  int64_t bytes_in_use = 0, peak_bytes = 0;
+  // launch tables
+  DevAlloc tables;
+  char *h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  std::vector<BatchGroup> groups;
+  const ModeState **d_sts = nullptr;
+  double *d_f = nullptr, *h_f = nullptr;
+  size_t h_f_cap = 0;
+  bool dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int stable_steps = 0;
+  int64_t steps = 0, graph_builds = 0, graph_launches = 0, eager_launches = 0;
+};
+
+namespace {
+
+void server_drop_graph(sacd_server *S) {
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->graph) (void)hipGraphDestroy(S->graph);
+  S->gexec = nullptr;
+  S->graph = nullptr;
+}
+
+void destroy_job(ServerJob &j) {
+  if (j.m) sacd_destroy_model(j.m);
+  if (j.t) sacd_destroy_tensor(j.t);
+  j.m = nullptr;
+  j.t = nullptr;
+}
+
+// Admission of one queued request: upload, ingest, initial factors.
+sacd_status admit(sacd_server *S, ServerReq &q, ServerJob *out) {
+  ServerJob j;
+  j.ticket = q.ticket;
+  DevAlloc up;
+  if (S->custom_alloc) {
+    up.alloc = S->alloc;
+    up.custom = true;
+  }
+  int32_t *didx = nullptr;
+  float *dvals = nullptr;
+  sacd_status st = SACD_OK;
+  if (q.nnz > 0) {
+    st = up.get_t((size_t)q.nnz * 3, &didx);
+    if (st == SACD_OK) st = up.get_t((size_t)q.nnz, &dvals);
+    if (st == SACD_OK) {
+      hipError_t e = hipMemcpyAsync(didx, q.idx.data(), sizeof(int32_t) * 3 * q.nnz, hipMemcpyHostToDevice, S->s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(dvals, q.vals.data(), sizeof(float) * q.nnz, hipMemcpyHostToDevice, S->s);
+      if (e != hipSuccess) st = fail(SACD_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (st == SACD_OK)
+    st = sacd_create_tensor(q.dims, q.nnz, didx, dvals, S->custom_alloc ? &S->alloc : nullptr, S->s, &j.t);
+  (void)hipStreamSynchronize(S->s);
+  up.release_all();
+  if (st == SACD_OK) st = sacd_init_factors(j.t, q.R, q.seed, S->cfg.precision, SACD_UPDATE_GS, &j.m);
+  if (st != SACD_OK) {
+    destroy_job(j);
+    return st;
+  }
+  j.bytes = j.t->mem.bytes + j.m->mem.bytes;
+  *out = j;
+  return SACD_OK;
+}
+
+// Host table of one batched launch: per-job arguments, then the block map.
+template <typename Args>
+size_t table_bytes(size_t njobs, size_t nblocks) {
+  return al256(sizeof(Args) * njobs) + al256(sizeof(int4) * nblocks);
+}
+
+sacd_status rebuild_tables(sacd_server *S) {
+  server_drop_graph(S);
+  S->tables.release_all();
+  S->groups.clear();
+  const int J = (int)S->active.size();
+  for (int rp : {16, 32, 64, 128}) {
+    BatchGroup g;
+    g.RP = rp;
+    for (int i = 0; i < J; ++i)
+      if (S->active[i].m->RP == rp) g.jobs.push_back(i);
+    if (!g.jobs.empty()) S->groups.push_back(g);
+  }
+  // sizes
+  size_t total = al256(sizeof(ModeState *) * (J + 1)) + al256(sizeof(double) * (J + 1));
+  for (BatchGroup &g : S->groups)
+    for (int n = 0; n < 3; ++n) {
+      g.nb_mt[n] = g.nb_fx[n] = g.nb_im[n] = g.nb_gf[n] = 0;
+      for (int i : g.jobs) {
+        const sacd_model *m = S->active[i].m;
+        const int I = (int)m->t->dims[n];
+        g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
+        g.nb_fx[n] += fix_blocks(m->plan[n].nlong, I);
+        g.nb_im[n] += importance_blocks(g.RP, I);
+        g.nb_gf[n] += gram_final_blocks(g.RP);
+      }
+      const size_t nj = g.jobs.size();
+      total += table_bytes<MttkrpArgs>(nj, g.nb_mt[n]) + table_bytes<FixArgs>(nj, g.nb_fx[n]) +
+               table_bytes<ImpArgs>(nj, g.nb_im[n]) + al256(sizeof(UpdArgs) * nj) +
+               table_bytes<GramArgs>(nj, g.nb_gf[n]);
+    }
+  if (total > S->h_stage_bytes) {
+    if (S->h_stage) (void)hipHostFree(S->h_stage);
+    S->h_stage = nullptr;
+    S->h_stage_bytes = 0;
+    HIP_TRY(hipHostMalloc((void **)&S->h_stage, total, hipHostMallocDefault));
+    S->h_stage_bytes = total;
+  }
+  char *dbase = nullptr;
+  SACD_TRY(S->tables.get(total, (void **)&dbase));
+  size_t off = 0;
+  // carve host and device views at the same offsets
+  auto carve = [&](size_t bytes, void **h, void **d) {
+    *h = S->h_stage + off;
+    *d = dbase + off;
+    off += al256(bytes);
+  };
+  void *h, *d;
+  carve(sizeof(ModeState *) * (J + 1), &h, &d);
+  for (int i = 0; i < J; ++i) ((const ModeState **)h)[i] = S->active[i].m->st + 2;
+  S->d_sts = (const ModeState **)d;
+  carve(sizeof(double) * (J + 1), &h, &d);
+  S->d_f = (double *)d;
+  auto fill_map = [&](int4 *bm, const BatchGroup &g, int n, int which) {
+    int b = 0;
+    for (size_t k = 0; k < g.jobs.size(); ++k) {
+      const sacd_model *m = S->active[g.jobs[k]].m;
+      const int I = (int)m->t->dims[n];
+      int nb = 0;
+      if (which == 0) nb = mttkrp_blocks(g.RP, m->plan[n].nunits);
+      else if (which == 1) nb = fix_blocks(m->plan[n].nlong, I);
+      else if (which == 2) nb = importance_blocks(g.RP, I);
+      else nb = gram_final_blocks(g.RP);
+      for (int q = 0; q < nb; ++q) bm[b++] = make_int4((int)k, q, nb, 0);
+    }
+  };
+  for (BatchGroup &g : S->groups)
+    for (int n = 0; n < 3; ++n) {
+      const size_t nj = g.jobs.size();
+      carve(sizeof(MttkrpArgs) * nj, &h, &d);
+      for (size_t k = 0; k < nj; ++k) ((MttkrpArgs *)h)[k] = mttkrp_args(S->active[g.jobs[k]].m, n);
+      g.mt[n] = (MttkrpArgs *)d;
+      carve(sizeof(int4) * g.nb_mt[n], &h, &d);
+      fill_map((int4 *)h, g, n, 0);
+      g.bm_mt[n] = (int4 *)d;
+      carve(sizeof(FixArgs) * nj, &h, &d);
+      for (size_t k = 0; k < nj; ++k) ((FixArgs *)h)[k] = fix_args(S->active[g.jobs[k]].m, n);
+      g.fx[n] = (FixArgs *)d;
+      carve(sizeof(int4) * g.nb_fx[n], &h, &d);
+      fill_map((int4 *)h, g, n, 1);
+      g.bm_fx[n] = (int4 *)d;
+      carve(sizeof(ImpArgs) * nj, &h, &d);
+      for (size_t k = 0; k < nj; ++k) ((ImpArgs *)h)[k] = imp_args(S->active[g.jobs[k]].m, n);
+      g.im[n] = (ImpArgs *)d;
+      carve(sizeof(int4) * g.nb_im[n], &h, &d);
+      fill_map((int4 *)h, g, n, 2);
+      g.bm_im[n] = (int4 *)d;
+      carve(sizeof(UpdArgs) * nj, &h, &d);
+      for (size_t k = 0; k < nj; ++k) ((UpdArgs *)h)[k] = upd_args(S->active[g.jobs[k]].m, n);
+      g.up[n] = (UpdArgs *)d;
+      carve(sizeof(GramArgs) * nj, &h, &d);
+      for (size_t k = 0; k < nj; ++k) ((GramArgs *)h)[k] = gram_args(S->active[g.jobs[k]].m, n, true);
+      g.gf[n] = (GramArgs *)d;
+      carve(sizeof(int4) * g.nb_gf[n], &h, &d);
+      fill_map((int4 *)h, g, n, 3);
+      g.bm_gf[n] = (int4 *)d;
+    }
+  HIP_TRY(hipMemcpyAsync(dbase, S->h_stage, off, hipMemcpyHostToDevice, S->s));
+  HIP_TRY(hipStreamSynchronize(S->s));
+  if ((size_t)J > S->h_f_cap) {
+    if (S->h_f) (void)hipHostFree(S->h_f);
+    S->h_f = nullptr;
+    S->h_f_cap = 0;
+    HIP_TRY(hipHostMalloc((void **)&S->h_f, sizeof(double) * J, hipHostMallocDefault));
+    S->h_f_cap = J;
+  }
+  S->dirty = false;
+  S->stable_steps = 0;
+  return SACD_OK;
+}
+
+// One outer iteration of every running job, then the gather of their
+// objectives.  Per mode, the ranks' launches follow each other on the stream.
+sacd_status enqueue_batched_iteration(sacd_server *S) {
+  const bool bf = S->cfg.precision == SACD_PREC_MIXED_BF16;
+  hipStream_t s = S->s;
+  for (int n = 0; n < 3; ++n)
+    for (BatchGroup &g : S->groups) {
+      HIP_TRY(launch_mttkrp_b(g.RP, g.mt[n], g.bm_mt[n], g.nb_mt[n], s));
+      HIP_TRY(launch_mttkrp_fix_b(g.RP, g.fx[n], g.bm_fx[n], g.nb_fx[n], s));
+      HIP_TRY(launch_importance_b(g.RP, bf, g.im[n], g.bm_im[n], g.nb_im[n], s));
+      HIP_TRY(launch_select_update_b(g.RP, bf, g.up[n], g.bm_im[n], g.nb_im[n], s));
+      HIP_TRY(launch_gram_final_b(g.RP, g.gf[n], g.bm_gf[n], g.nb_gf[n], s));
+    }
+  HIP_TRY(launch_gather_f(S->d_sts, (int)S->active.size(), S->d_f, s));
+  return SACD_OK;
+}
+
+sacd_status run_iteration(sacd_server *S) {
+  if (S->gexec) {
+    HIP_TRY(hipGraphLaunch(S->gexec, S->s));
+    S->graph_launches++;
+    return SACD_OK;
+  }
+  if (S->cfg.use_graphs && S->stable_steps >= 1) {
+    // the set of running jobs did not change last step: capture it
+    HIP_TRY(hipStreamBeginCapture(S->s, hipStreamCaptureModeThreadLocal));
+    sacd_status st = enqueue_batched_iteration(S);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(S->s, &g);
+    if (st != SACD_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(SACD_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      S->gexec = nullptr;
+      return fail(SACD_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    S->graph = g;
+    S->graph_builds++;
+    HIP_TRY(hipGraphLaunch(S->gexec, S->s));
+    S->graph_launches++;
+    return SACD_OK;
+  }
+  SACD_TRY(enqueue_batched_iteration(S));
+  S->eager_launches++;
+  return SACD_OK;
+}
+
+sacd_status retire(sacd_server *S, ServerJob &j, int state) {
+  ServerResult &r = S->results[j.ticket];
+  r.state = state;
+  r.iters = j.iters;
+  r.fit = j.fit;
+  r.f = j.f;
+  r.R = j.m->R;
+  for (int n = 0; n < 3; ++n) {
+    r.dims[n] = j.t->dims[n];
+    r.A[n].resize((size_t)j.t->dims[n] * j.m->R);
+    HIP_TRY(hipMemcpy2DAsync(r.A[n].data(), sizeof(float) * j.m->R, j.m->A[n], sizeof(float) * j.m->RP,
+                             sizeof(float) * j.m->R, (size_t)j.t->dims[n], hipMemcpyDeviceToHost, S->s));
+  }
+  HIP_TRY(hipStreamSynchronize(S->s));
+  S->bytes_in_use -= j.bytes;
+  destroy_job(j);
+  S->finished.push_back(j.ticket);
+  return SACD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, int64_t *resident,
+                           int64_t *transient) {
+  if (!dims || nnz < 0 || R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  int64_t a = 0, b = 0;
+  job_bytes(dims, nnz, R, &a, &b);
+  if (resident) *resident = a;
+  if (transient) *transient = b;
+  return SACD_OK;
+}
+
+sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocator *alloc, void *stream,
+                               sacd_server **out) {
+  if (!out || !cfg) return fail(SACD_ERR_INVALID_ARG, "cfg / out is NULL");
+  *out = nullptr;
+  if (cfg->budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_iter < 1 || !(cfg->tol >= 0.0))
+    return fail(SACD_ERR_INVALID_ARG, "budget, max_slots, max_iter must be positive and tol >= 0");
+  if (cfg->precision != SACD_PREC_FP32 && cfg->precision != SACD_PREC_MIXED_BF16)
+    return fail(SACD_ERR_INVALID_ARG, "unknown precision %d", (int)cfg->precision);
+  if (alloc && (!alloc->alloc || !alloc->release)) return fail(SACD_ERR_INVALID_ARG, "allocator callbacks are NULL");
+  (void)hipGetLastError();
+  sacd_server *S = new (std::nothrow) sacd_server();
+  if (!S) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
+  S->cfg = *cfg;
+  if (alloc) {
+    S->alloc = *alloc;
+    S->custom_alloc = true;
+    S->tables.alloc = *alloc;
+    S->tables.custom = true;
+  }
+  if (hipGetDevice(&S->dev) != hipSuccess) {
+    delete S;
+    return fail(SACD_ERR_DEVICE, "no HIP device");
+  }
+  sacd_status st = make_stream(stream, &S->s, &S->own_stream);
+  if (st != SACD_OK) {
+    delete S;
+    return st;
+  }
+  *out = S;
+  return SACD_OK;
+}
+
+sacd_status sacd_server_submit(sacd_server *S, const int64_t dims[3], int64_t nnz, const int32_t *idx,
+                               const float *vals, int32_t R, uint64_t seed, int64_t *ticket) {
+  if (!S || !dims || !ticket) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  if (R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "rank %d not in [1, %d]", R, kMaxRP);
+  if (nnz < 0 || (nnz > 0 && (!idx || !vals))) return fail(SACD_ERR_INVALID_ARG, "bad nnz / idx / vals");
+  for (int n = 0; n < 3; ++n)
+    if (dims[n] < 1 || dims[n] > 2147483647LL) return fail(SACD_ERR_INVALID_ARG, "dims[%d] out of range", n);
+  ServerReq q;
+  q.ticket = S->next_ticket;
+  for (int n = 0; n < 3; ++n) q.dims[n] = dims[n];
+  q.nnz = nnz;
+  q.R = R;
+  q.seed = seed;
+  job_bytes(dims, nnz, R, &q.est_resident, &q.est_transient);
+  if (q.est_resident + q.est_transient > S->cfg.budget_bytes)
+    return fail(SACD_ERR_NO_MEMORY, "job needs up to %lld bytes, more than the whole budget",
+                (long long)(q.est_resident + q.est_transient));
+  q.idx.assign(idx, idx + 3 * nnz);
+  q.vals.assign(vals, vals + nnz);
+  S->queue.push_back(std::move(q));
+  ServerResult &r = S->results[S->next_ticket];
+  r.state = SACD_JOB_QUEUED;
+  *ticket = S->next_ticket++;
+  return SACD_OK;
+}
+
+sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queued) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  SACD_TRY(enter(S->dev));
+  S->finished.clear();
+  // admission, first come first served, while the budget and slots allow
+  while (!S->queue.empty() && (int)S->active.size() < S->cfg.max_slots) {
+    ServerReq &q = S->queue.front();
+    if (S->bytes_in_use + q.est_resident + q.est_transient > S->cfg.budget_bytes) break;
+    ServerJob j;
+    sacd_status st = admit(S, q, &j);
+    ServerResult &r = S->results[q.ticket];
+    if (st != SACD_OK) {
+      r.state = SACD_JOB_FAILED;
+      r.err = st;
+      S->finished.push_back(q.ticket);
+    } else {
+      r.state = SACD_JOB_RUNNING;
+      S->active.push_back(j);
+      S->bytes_in_use += j.bytes;
+      S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
+      S->dirty = true;
+    }
+    S->queue.pop_front();
+  }
+  if (!S->active.empty()) {
+    if (S->dirty) SACD_TRY(rebuild_tables(S));
+    SACD_TRY(run_iteration(S));
+    const int J = (int)S->active.size();
+    HIP_TRY(hipMemcpyAsync(S->h_f, S->d_f, sizeof(double) * J, hipMemcpyDeviceToHost, S->s));
+    HIP_TRY(hipStreamSynchronize(S->s));
+    S->steps++;
+    S->stable_steps++;
+    std::vector<ServerJob> keep;
+    keep.reserve(J);
+    for (int i = 0; i < J; ++i) {
+      ServerJob &j = S->active[i];
+      j.iters++;
+      j.f = S->h_f[i];
+      const double nx = std::sqrt(j.t->norm2);
+      j.fit = nx > 0.0 ? 1.0 - std::sqrt(j.f > 0.0 ? j.f : 0.0) / nx : 0.0;
+      // the stopping rule of sacd_run_until
+      const bool conv = j.iters >= 2 && std::fabs(j.fit - j.prev_fit) < S->cfg.tol * std::fabs(j.prev_fit);
+      j.prev_fit = j.fit;
+      if (conv || j.iters >= S->cfg.max_iter || !(nx > 0.0)) {
+        SACD_TRY(retire(S, j, SACD_JOB_DONE));
+        S->dirty = true;
+      } else {
+        keep.push_back(j);
+      }
+    }
+    S->active.swap(keep);
+    if (S->dirty) server_drop_graph(S);
+  }
+  if (n_running) *n_running = (int32_t)S->active.size();
+  if (n_queued) *n_queued = (int32_t)S->queue.size();
+  return SACD_OK;
+}
+
+sacd_status sacd_server_finished(const sacd_server *S, int64_t *tickets, int32_t cap, int32_t *n) {
+  if (!S || !n || cap < 0 || (cap > 0 && !tickets)) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  const int k = std::min<int>(cap, (int)S->finished.size());
+  for (int i = 0; i < k; ++i) tickets[i] = S->finished[i];
+  *n = (int32_t)S->finished.size();
+  return SACD_OK;
+}
+
+sacd_status sacd_server_poll(const sacd_server *S, int64_t ticket, int32_t *state, int32_t *iters, double *fit,
+                             double *objective) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  auto it = S->results.find(ticket);
+  if (it == S->results.end()) return fail(SACD_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  const ServerResult &r = it->second;
+  if (state) *state = r.state;
+  int it_now = r.iters;
+  double fit_now = r.fit, f_now = r.f;
+  if (r.state == SACD_JOB_RUNNING)
+    for (const ServerJob &j : S->active)
+      if (j.ticket == ticket) {
+        it_now = j.iters;
+        fit_now = j.fit;
+        f_now = j.f;
+      }
+  if (iters) *iters = it_now;
+  if (fit) *fit = fit_now;
+  if (objective) *objective = f_now;
+  return r.state == SACD_JOB_FAILED ? r.err : SACD_OK;
+}
+
+sacd_status sacd_server_result(const sacd_server *S, int64_t ticket, int32_t mode, float *dst) {
+  if (!S || !dst || mode < 0 || mode > 2) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  auto it = S->results.find(ticket);
+  if (it == S->results.end()) return fail(SACD_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  if (it->second.state != SACD_JOB_DONE) return fail(SACD_ERR_BAD_STATE, "job %lld is not done", (long long)ticket);
+  const std::vector<float> &A = it->second.A[mode];
+  std::memcpy(dst, A.data(), sizeof(float) * A.size());
+  return SACD_OK;
+}
+
+sacd_status sacd_server_release(sacd_server *S, int64_t ticket) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  auto it = S->results.find(ticket);
+  if (it == S->results.end()) return fail(SACD_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  if (it->second.state != SACD_JOB_DONE && it->second.state != SACD_JOB_FAILED)
+    return fail(SACD_ERR_BAD_STATE, "job %lld is still queued or running", (long long)ticket);
+  S->results.erase(it);
+  return SACD_OK;
+}
+
+sacd_status sacd_server_stats(const sacd_server *S, sacd_server_stats_t *out) {
+  if (!S || !out) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  out->running = (int32_t)S->active.size();
+  out->queued = (int32_t)S->queue.size();
+  out->bytes_in_use = S->bytes_in_use;
+  out->peak_bytes = S->peak_bytes;
+  out->steps = S->steps;
+  out->graph_builds = S->graph_builds;
+  out->graph_launches = S->graph_launches;
+  out->eager_launches = S->eager_launches;
+  return SACD_OK;
+}
+
+void sacd_server_destroy(sacd_server *S) {
+  if (!S) return;
+  (void)hipSetDevice(S->dev);
+  if (S->s) (void)hipStreamSynchronize(S->s);
+  server_drop_graph(S);
+  for (ServerJob &j : S->active) destroy_job(j);
+  S->active.clear();
+  S->tables.release_all();
+  if (S->h_stage) (void)hipHostFree(S->h_stage);
+  if (S->h_f) (void)hipHostFree(S->h_f);
+  if (S->own_stream && S->s) (void)hipStreamDestroy(S->s);
+  delete S;
 }
 
 }  // extern "C"

@@ -706,6 +706,12 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(const float *__restrict_
   }
 }
 
+// Objective of the last sweep of each of n jobs, gathered into one array.
+__global__ __launch_bounds__(kThreads) void k_gather_f(const ModeState *const *__restrict__ sts, int n,
+                                                       double *__restrict__ out) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = sts[i]->f;
+}
+
 __global__ __launch_bounds__(kThreads) void k_check_factor(const float *__restrict__ a, long long n,
                                                            int *flag) {
   int bad = 0;
@@ -877,6 +883,12 @@ hipError_t launch_copy_rows(const float *src, int src_stride, float *dst, int ds
                             int ncols, int zero_cols_to, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((long long)I * zero_cols_to)), dim3(kThreads), 0, s, src,
                      src_stride, dst, dst_stride, I, ncols, zero_cols_to);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f(const ModeState *const *sts, int n, double *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_f, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, sts, n, out);
   return hipGetLastError();
 }
 

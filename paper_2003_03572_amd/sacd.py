@@ -41,6 +41,19 @@ class _Stats(C.Structure):
                 ("flip", C.c_int32), ("n_selected", C.c_int64), ("objective", C.c_double)]
 
 
+class _ServerConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("max_iter", C.c_int32),
+                ("tol", C.c_double), ("precision", C.c_int), ("use_graphs", C.c_int32)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("running", C.c_int32), ("queued", C.c_int32), ("bytes_in_use", C.c_int64),
+                ("peak_bytes", C.c_int64), ("steps", C.c_int64), ("graph_builds", C.c_int64),
+                ("graph_launches", C.c_int64), ("eager_launches", C.c_int64)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -82,6 +95,15 @@ def lib():
             "sacd_iterate_timed": [p, i32, p],
             "sacd_kernel_bytes": [p, i32, i32, p],
             "sacd_model_bytes": [p, p],
+            "sacd_job_bytes": [p, i64, i32, p, p],
+            "sacd_server_create": [p, p, p, C.POINTER(p)],
+            "sacd_server_submit": [p, p, i64, p, p, i32, C.c_uint64, p],
+            "sacd_server_step": [p, p, p],
+            "sacd_server_finished": [p, p, i32, p],
+            "sacd_server_poll": [p, i64, p, p, p, p],
+            "sacd_server_result": [p, i64, i32, p],
+            "sacd_server_release": [p, i64],
+            "sacd_server_stats": [p, p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -91,6 +113,8 @@ def lib():
         L.sacd_destroy_tensor.restype = None
         L.sacd_destroy_model.argtypes = [p]
         L.sacd_destroy_model.restype = None
+        L.sacd_server_destroy.argtypes = [p]
+        L.sacd_server_destroy.restype = None
         L.sacd_last_error.restype = C.c_char_p
         L.sacd_status_string.restype = C.c_char_p
         L.sacd_version.restype = C.c_char_p
@@ -320,3 +344,92 @@ class Model:
 
     def synchronize(self):
         self.t.stream.synchronize()
+
+
+def job_bytes(dims: Sequence[int], nnz: int, rank: int) -> Tuple[int, int]:
+    """Upper bounds (resident, transient) of the device bytes of a job."""
+    d = (C.c_int64 * 3)(*[int(x) for x in dims])
+    a, b = C.c_int64(), C.c_int64()
+    _check(lib().sacd_job_bytes(d, int(nnz), int(rank), C.byref(a), C.byref(b)), "sacd_job_bytes")
+    return a.value, b.value
+
+
+class Server:
+    """Many factorization jobs resident on the GPU, iterated together
+    (sacd_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_slots: int = 256, max_iter: int = 500,
+                 tol: float = 1e-4, precision: int = PREC_FP32, use_graphs: bool = True,
+                 stream: Optional[torch.cuda.Stream] = None, torch_allocator: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the SaCD library runs on the GPU only")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.alloc = TorchAllocator(self.device) if torch_allocator else None
+        cfg = _ServerConfig(int(budget_bytes), int(max_slots), int(max_iter), float(tol),
+                            int(precision), int(bool(use_graphs)))
+        h = C.c_void_p()
+        _check(lib().sacd_server_create(C.byref(cfg), C.byref(self.alloc.struct) if self.alloc else None,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+               "sacd_server_create")
+        self._h = h
+
+    def submit(self, dims, idx: np.ndarray, vals: np.ndarray, rank: int, seed: int) -> int:
+        idx = np.ascontiguousarray(idx, np.int32).reshape(-1, 3)
+        vals = np.ascontiguousarray(vals, np.float32).reshape(-1)
+        d = (C.c_int64 * 3)(*[int(x) for x in dims])
+        t = C.c_int64()
+        _check(lib().sacd_server_submit(self._h, d, idx.shape[0], idx.ctypes.data_as(C.c_void_p),
+                                        vals.ctypes.data_as(C.c_void_p), int(rank), C.c_uint64(seed),
+                                        C.byref(t)), "sacd_server_submit")
+        return t.value
+
+    def step(self) -> Tuple[int, int]:
+        r, q = C.c_int32(), C.c_int32()
+        _check(lib().sacd_server_step(self._h, C.byref(r), C.byref(q)), "sacd_server_step")
+        return r.value, q.value
+
+    def finished(self):
+        n = C.c_int32()
+        _check(lib().sacd_server_finished(self._h, None, 0, C.byref(n)), "sacd_server_finished")
+        buf = (C.c_int64 * max(n.value, 1))()
+        _check(lib().sacd_server_finished(self._h, buf, n.value, C.byref(n)), "sacd_server_finished")
+        return [buf[i] for i in range(n.value)]
+
+    def poll(self, ticket: int) -> dict:
+        st, it = C.c_int32(), C.c_int32()
+        fit, f = C.c_double(), C.c_double()
+        rc = lib().sacd_server_poll(self._h, int(ticket), C.byref(st), C.byref(it), C.byref(fit),
+                                    C.byref(f))
+        if rc != 0 and st.value != JOB_FAILED:
+            _check(rc, "sacd_server_poll")
+        return dict(state=st.value, iters=it.value, fit=fit.value, f=f.value, status=rc)
+
+    def result(self, ticket: int, dims: Sequence[int], rank: int):
+        out = []
+        for n in range(3):
+            A = np.empty((int(dims[n]), int(rank)), np.float32)
+            _check(lib().sacd_server_result(self._h, int(ticket), n, A.ctypes.data_as(C.c_void_p)),
+                   "sacd_server_result")
+            out.append(A)
+        return out
+
+    def release(self, ticket: int):
+        _check(lib().sacd_server_release(self._h, int(ticket)), "sacd_server_release")
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(lib().sacd_server_stats(self._h, C.byref(s)), "sacd_server_stats")
+        return {k: getattr(s, k) for k, _ in _ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sacd_server_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -50,3 +50,14 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sacd, "_lib", None)
     with pytest.raises(RuntimeError):
         sacd.lib()
+
+
+def test_job_bytes_bound_without_gpu():
+    """The admission bound is host arithmetic: positive, growing with nnz and rank."""
+    from paper_2003_03572_amd import sacd
+    r8, t8 = sacd.job_bytes((100, 200, 300), 10_000, 8)
+    r64, _ = sacd.job_bytes((100, 200, 300), 10_000, 64)
+    rbig, tbig = sacd.job_bytes((100, 200, 300), 100_000, 8)
+    assert 0 < r8 < r64 and r8 < rbig and 0 < t8 < tbig
+    # at least the three sorted copies (12 bytes per entry each) and the factors
+    assert r8 >= 36 * 10_000 + 4 * 8 * 600

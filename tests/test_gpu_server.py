@@ -1,0 +1,106 @@
+"""Serving form: many jobs resident on the GPU, iterated together with
+job-batched kernels.  Each job's result must be the same alone and in the
+mix (bit for bit: the batched launches run exactly the job's own blocks),
+admission must respect the HBM budget, and a job larger than the budget is
+refused."""
+import numpy as np
+import pytest
+
+from paper_2003_03572_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL, MAX_ITER = 1e-4, 60
+
+
+@pytest.fixture(scope="module")
+def sacd():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2003_03572_amd import sacd as S
+    return S
+
+
+def _small_jobs(n, max_nnz=40_000, ranks=None):
+    """The first n job specs of the batched workload whose nnz is small."""
+    out = []
+    for spec in gen.job_specs(200):
+        if spec.nnz_target <= max_nnz:
+            dims, idx, vals = gen.job_tensor(spec)
+            R = spec.rank if ranks is None else ranks[len(out) % len(ranks)]
+            out.append((spec.seed, dims, idx, vals, R))
+        if len(out) == n:
+            break
+    return out
+
+
+def _alone(sacd, dims, idx, vals, R, seed, precision):
+    T = sacd.Tensor.from_numpy(dims, idx, vals)
+    m = sacd.Model(T, R, seed=seed, precision=precision)
+    it, fit = m.run_until(TOL, MAX_ITER)
+    A = [m.factor(n).cpu().numpy() for n in range(3)]
+    return it, fit, A
+
+
+def _serve(sacd, jobs, budget, precision, max_slots=64):
+    S = sacd.Server(budget, max_slots=max_slots, max_iter=MAX_ITER, tol=TOL, precision=precision)
+    tickets = [S.submit(dims, idx, vals, R, seed) for (seed, dims, idx, vals, R) in jobs]
+    est = {t: sum(sacd.job_bytes(j[1], j[2].shape[0], j[4])) for t, j in zip(tickets, jobs)}
+    trace = []
+    for _ in range(10_000):
+        running, queued = S.step()
+        st = S.stats()
+        trace.append(st)
+        assert st["bytes_in_use"] <= budget
+        if running == 0 and queued == 0:
+            break
+    out = {}
+    for t, (seed, dims, idx, vals, R) in zip(tickets, jobs):
+        p = S.poll(t)
+        assert p["state"] == sacd.JOB_DONE, p
+        out[t] = (p["iters"], p["fit"], S.result(t, dims, R))
+    return S, tickets, out, trace, est
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed_bf16"])
+def test_results_same_alone_and_in_the_mix(sacd, precision):
+    jobs = _small_jobs(6, ranks=[8, 16, 32, 64, 20, 8])
+    S, tickets, served, trace, _ = _serve(sacd, jobs, budget=1 << 32, precision=precision)
+    assert max(s["running"] for s in trace) == len(jobs)  # all in the mix at once
+    iters = []
+    for t, (seed, dims, idx, vals, R) in zip(tickets, jobs):
+        it, fit, A = _alone(sacd, dims, idx, vals, R, seed, precision)
+        it_s, fit_s, A_s = served[t]
+        iters.append(it)
+        assert it_s == it and fit_s == fit, (t, it, it_s, fit, fit_s)
+        for n in range(3):
+            np.testing.assert_array_equal(A_s[n].view(np.uint32), A[n].view(np.uint32))
+    # the jobs finish at different iterations, so the mix changes while it runs
+    assert len(set(iters)) > 1
+    assert S.stats()["graph_launches"] > 0
+
+
+def test_admission_by_budget(sacd):
+    jobs = _small_jobs(8)
+    sizes = [sum(sacd.job_bytes(j[1], j[2].shape[0], j[4])) for j in jobs]
+    budget = int(2.2 * max(sizes))  # room for about two jobs at a time
+    S, tickets, served, trace, est = _serve(sacd, jobs, budget=budget, precision=0)
+    assert max(s["running"] for s in trace) < len(jobs)
+    assert max(s["peak_bytes"] for s in trace) <= budget
+    assert all(served[t][0] >= 2 for t in tickets)
+
+
+def test_oversized_job_is_refused(sacd):
+    (seed, dims, idx, vals, R), = _small_jobs(1)
+    S = sacd.Server(1 << 16, max_iter=MAX_ITER, tol=TOL)
+    with pytest.raises(sacd.SacdError) as e:
+        S.submit(dims, idx, vals, R, seed)
+    assert e.value.status == -3
+
+
+def test_actual_bytes_within_estimate(sacd):
+    for (seed, dims, idx, vals, R) in _small_jobs(4, ranks=[8, 32, 64, 128]):
+        T = sacd.Tensor.from_numpy(dims, idx, vals)
+        m = sacd.Model(T, R, seed=seed)
+        resident, _ = sacd.job_bytes(dims, idx.shape[0], R)
+        assert T.info()["device_bytes"] + m.device_bytes() <= resident

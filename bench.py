@@ -10,6 +10,9 @@ nnz * R / (seconds per step).
 Prints one JSON line.  Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W] [--workload zipf|small|uniform64|uniform128]
+                    [--precision fp32|mixed]
+    python bench.py --workload batched     # 256 uneven jobs to tolerance, batched vs serial
+    python bench.py --workload serving     # Poisson arrivals, served vs serial, p50/p99
 """
 import argparse
 import json
@@ -63,6 +66,194 @@ def cpu_baseline(w, dims, idx, vals, budget_s: float):
     }
 
 
+def mixed_vs_fp32(sacd, T, w, m_mixed, iters: int):
+    """Objective, fit and factors of the mixed run against the FP32 GPU path
+    (itself within 1e-5 of the FP64 oracle per sweep) after the same number
+    of iterations from the same initial factors."""
+    import numpy as np
+    m32 = sacd.Model(T, w.rank, seed=w.init_seed)
+    m32.iterate(iters)
+    fit_b, f_b = m_mixed.fit()
+    fit_a, f_a = m32.fit()
+    rel = []
+    for n in range(3):
+        a = m32.factor(n).double().cpu().numpy()
+        b = m_mixed.factor(n).double().cpu().numpy()
+        rel.append(float(np.linalg.norm(b - a) / max(np.linalg.norm(a), 1e-300)))
+    return {"iterations": iters, "f_rel": abs(f_b - f_a) / abs(f_a), "fit_mixed": fit_b, "fit_fp32": fit_a,
+            "factor_rel": rel}
+
+
+def _pool(gen, n_jobs: int, cache_dir: str):
+    """The batched workload's job pool (generated, or loaded from the cache)."""
+    import numpy as np
+    specs = gen.job_specs(n_jobs)
+    path = os.path.join(cache_dir, f"jobs{n_jobs}.npz") if cache_dir else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        return [(sp, tuple(int(d) for d in z[f"d{j}"]), z[f"i{j}"], z[f"v{j}"]) for j, sp in enumerate(specs)]
+    t0 = time.perf_counter()
+    out = []
+    for sp in specs:
+        dims, idx, vals = gen.job_tensor(sp)
+        out.append((sp, dims, idx, vals))
+    log(f"[bench] generated {n_jobs} jobs in {time.perf_counter() - t0:.1f} s")
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        arrs = {}
+        for j, (sp, dims, idx, vals) in enumerate(out):
+            arrs[f"d{j}"], arrs[f"i{j}"], arrs[f"v{j}"] = np.array(dims), idx, vals
+        np.savez(path, **arrs)
+    return out
+
+
+def _serial(sacd, pool, prec, tol, max_iter):
+    """The plain path: each job alone (ingest, factors, run to tolerance),
+    one after the other.  Returns per-job (seconds, iterations, fit)."""
+    import torch
+    res = []
+    for sp, dims, idx, vals in pool:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = sacd.Tensor.from_numpy(dims, idx, vals)
+        m = sacd.Model(T, sp.rank, seed=sp.seed, precision=prec)
+        it, fit = m.run_until(tol, max_iter)
+        res.append((time.perf_counter() - t0, it, fit))
+        del m, T
+    return res
+
+
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def run_many(args):
+    """Batched (all jobs at once) or served (Poisson arrivals) form against
+    the plain one-job-at-a-time GPU path, at equal final fit."""
+    import numpy as np
+    import torch
+    from paper_2003_03572_amd import gen, sacd
+    tol, max_iter = 1e-4, 500
+    serving = args.workload == "serving"
+    prec_name = args.precision or ("mixed" if serving else "fp32")
+    prec = sacd.PREC_MIXED_BF16 if prec_name == "mixed" else sacd.PREC_FP32
+    pool = _pool(gen, args.jobs, args.data_cache)
+    nnzR = [idx.shape[0] * sp.rank for sp, dims, idx, vals in pool]
+    # warm the library (first launches, code objects) before timing
+    _serial(sacd, pool[:2], prec, tol, 5)
+    ser = _serial(sacd, pool, prec, tol, max_iter)
+    ser_t = [r[0] for r in ser]
+    log(f"[bench] serial path: {sum(ser_t):.2f} s for {len(pool)} jobs, "
+        f"iterations {min(r[1] for r in ser)}..{max(r[1] for r in ser)}")
+    base = {"n_gpus": 1, "higher_is_better": not serving, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32" if prec == sacd.PREC_FP32 else "bf16-mfma+f32", "data": "synthetic",
+            "steps": None, "warmup": None}
+    if not serving:
+        budget = 16 << 30
+        S = sacd.Server(budget, max_slots=len(pool), max_iter=max_iter, tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [S.submit(dims, idx, vals, sp.rank, sp.seed) for sp, dims, idx, vals in pool]
+        steps = 0
+        while True:
+            running, queued = S.step()
+            steps += 1
+            if running == 0 and queued == 0:
+                break
+        T_b = time.perf_counter() - t0
+        polls = [S.poll(t) for t in tickets]
+        equal = all(p["iters"] == r[1] and p["fit"] == r[2] for p, r in zip(polls, ser))
+        work = sum(nr * p["iters"] for nr, p in zip(nnzR, polls))
+        st = S.stats()
+        out = dict(base)
+        out.update({
+            "metric": "nnz*R SaCD updates/sec, 256 uneven jobs run to tolerance",
+            "value": work / T_b, "unit": "nnz*R/s", "ms_per_step": 1e3 * T_b / max(steps, 1),
+            "steps": steps,
+            "config": {"workload": f"batched-{len(pool)}-jobs-zipf1.1-r8to64", "tol": tol, "max_iter": max_iter,
+                       "precision": prec_name, "batched_seconds": T_b, "serial_seconds": sum(ser_t),
+                       "serial_value": work / sum(ser_t), "speedup_vs_serial": sum(ser_t) / T_b,
+                       "results_equal_to_serial": equal, "total_nnz": int(sum(p[2].shape[0] for p in pool)),
+                       "iterations_p50": _pct([p["iters"] for p in polls], 50),
+                       "iterations_max": max(p["iters"] for p in polls),
+                       "jobs_at_max_iter": sum(p["iters"] >= max_iter for p in polls),
+                       "server": st,
+                       "note": "batched: every job submitted at t=0 and resident at once; time includes "
+                               "upload and ingest of every job; serial: each job alone, one after the other"},
+        })
+        print(json.dumps(out), flush=True)
+        return
+    # serving
+    rates = [float(x) for x in args.rates.split(",")]
+    sizes = [sum(sacd.job_bytes(dims, idx.shape[0], sp.rank)) for sp, dims, idx, vals in pool]
+    budget = int(args.budget_mb * 2**20) if args.budget_mb > 0 else int(24 * np.mean(sizes))
+    per_rate = {}
+    for lam in rates:
+        rng = np.random.Generator(np.random.PCG64(3000 + int(lam)))
+        arr = gen.poisson_arrivals(lam, args.requests, 3000 + int(lam))
+        pick = rng.integers(0, len(pool), size=args.requests)
+        # serial: one job at a time, first come first served, from the measured service times
+        fin, lat_s = 0.0, []
+        for a, j in zip(arr, pick):
+            fin = max(fin, a) + ser_t[j]
+            lat_s.append(fin - a)
+        S = sacd.Server(budget, max_slots=256, max_iter=max_iter, tol=tol, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nxt, lat, done_t, info = 0, {}, {}, {}
+        max_running = 0
+        while len(done_t) < args.requests:
+            now = time.perf_counter() - t0
+            while nxt < args.requests and arr[nxt] <= now:
+                sp, dims, idx, vals = pool[pick[nxt]]
+                tk = S.submit(dims, idx, vals, sp.rank, sp.seed)
+                info[tk] = nxt
+                nxt += 1
+            running, queued = S.step()
+            max_running = max(max_running, running)
+            t_now = time.perf_counter() - t0
+            for tk in S.finished():
+                k = info[tk]
+                done_t[k] = t_now
+                p = S.poll(tk)
+                lat[k] = (t_now - arr[k], p["iters"], p["fit"])
+                S.release(tk)
+            if running == 0 and queued == 0 and nxt < args.requests:
+                wait = arr[nxt] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+        T_total = time.perf_counter() - t0
+        st = S.stats()
+        S.close()
+        lat_v = [lat[k][0] for k in range(args.requests)]
+        equal = all(lat[k][1] == ser[pick[k]][1] and lat[k][2] == ser[pick[k]][2] for k in range(args.requests))
+        per_rate[str(int(lam))] = {
+            "served_p50_ms": 1e3 * _pct(lat_v, 50), "served_p99_ms": 1e3 * _pct(lat_v, 99),
+            "serial_p50_ms": 1e3 * _pct(lat_s, 50), "serial_p99_ms": 1e3 * _pct(lat_s, 99),
+            "served_jobs_per_s": args.requests / T_total, "serial_jobs_per_s": args.requests / fin,
+            "served_nnzR_per_s": sum(nnzR[pick[k]] * lat[k][1] for k in range(args.requests)) / T_total,
+            "max_running": max_running, "peak_bytes": st["peak_bytes"], "steps": st["steps"],
+            "graph_launches": st["graph_launches"], "eager_launches": st["eager_launches"],
+            "results_equal_to_serial": equal}
+        log(f"[bench] rate {lam:.0f}/s: served p50 {per_rate[str(int(lam))]['served_p50_ms']:.1f} ms "
+            f"p99 {per_rate[str(int(lam))]['served_p99_ms']:.1f} ms; serial p50 "
+            f"{per_rate[str(int(lam))]['serial_p50_ms']:.1f} ms p99 {per_rate[str(int(lam))]['serial_p99_ms']:.1f} ms; "
+            f"max running {max_running}")
+    top = per_rate[str(int(rates[-1]))]
+    out = dict(base)
+    out.update({
+        "metric": f"p99 time-to-tolerance (ms), served, {rates[-1]:.0f} req/s",
+        "value": top["served_p99_ms"], "unit": "ms", "ms_per_step": None,
+        "config": {"workload": f"serving-poisson-{args.requests}req-pool{len(pool)}", "tol": tol,
+                   "max_iter": max_iter, "precision": prec_name, "budget_bytes": budget,
+                   "rates": per_rate,
+                   "note": "latency from arrival to result, incl. upload, ingest and queueing; serial: "
+                           "one job at a time, first come first served, from each job's measured time alone"},
+    })
+    print(json.dumps(out), flush=True)
+
+
 def measured_traffic(workload: str):
     """HBM bytes per MTTKRP launch from the committed rocprofv3 counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration),
@@ -89,7 +280,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="zipf", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="zipf", choices=sorted(WORKLOADS) + ["batched", "serving"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "mixed"],
+                    help="arithmetic of the dense products (default: fp32; serving: mixed)")
+    ap.add_argument("--jobs", type=int, default=256, help="batched / serving: job pool size")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: requests per arrival rate")
+    ap.add_argument("--rates", default="50,200,800", help="serving: arrival rates (1/s)")
+    ap.add_argument("--budget-mb", type=float, default=0.0,
+                    help="serving: HBM budget of the server (MB); 0 picks one that binds at the top rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--kernel-reps", type=int, default=10)
@@ -120,6 +318,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     sacd.lib()
+    if args.workload in ("batched", "serving"):
+        return run_many(args)
+    prec = sacd.PREC_MIXED_BF16 if args.precision == "mixed" else sacd.PREC_FP32
     w = getattr(gen, WORKLOADS[args.workload])
     t0 = time.perf_counter()
     cache = os.path.join(args.data_cache, w.name + ".npz") if args.data_cache else None
@@ -140,7 +341,7 @@ def main():
     nnz = T.nnz
     torch.cuda.synchronize()
     t_ingest = time.perf_counter() - t0
-    m = sacd.Model(T, w.rank, seed=w.init_seed)
+    m = sacd.Model(T, w.rank, seed=w.init_seed, precision=prec)
     m.synchronize()
     log(f"[bench] GPU ingest {t_ingest:.3f} s (incl. host->device copy), model ready")
 
@@ -210,7 +411,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == sacd.PREC_FP32 else "bf16-mfma+f32",
         "data": "synthetic",
         "config": {"workload": w.name, "dims": list(dims), "nnz": nnz, "rank": w.rank,
                    "step": "one outer iteration (sweeps of modes 0, 1, 2) incl. FP64 objective",
@@ -223,6 +424,9 @@ def main():
                      "algorithmic_bytes_per_launch": sum(mt_bytes_mode) / 3.0,
                      "avg_launch_us": sum(mt_avg_us) / 3.0},
     }
+    if prec != sacd.PREC_FP32:
+        out["config"]["precision"] = "mixed: Gram and A*H on BF16 MFMA, FP32 accumulation"
+        out["config"]["vs_fp32_gpu"] = mixed_vs_fp32(sacd, T, w, m, args.warmup + 2 * args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, dims, idx, vals, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -249,6 +249,9 @@ typedef struct {
   int32_t running, queued;
   int64_t bytes_in_use, peak_bytes;
   int64_t steps, graph_builds, graph_launches, eager_launches;
+  /* host wall seconds spent admitting jobs, building launch tables, running
+   * iterations (launch to the objectives read back) and retiring jobs */
+  double sec_admit, sec_tables, sec_iterate, sec_retire;
 } sacd_server_stats_t;
 
 /* Upper bounds of the device bytes of a job of this shape (host only, no GPU

@@ -11,8 +11,10 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -105,6 +107,40 @@ struct DevAlloc {
     blocks.clear();
   }
 };
+
+// Small pinned host buffers (64 bytes each) for scalar read-backs, carved
+// from process-wide 64 KB slabs that live until the process ends:
+// hipHostMalloc / hipHostFree cost milliseconds and synchronise the device,
+// too much to pay per model when jobs come and go.
+struct PinnedPool {
+  std::mutex mu;
+  std::vector<double *> free_list;
+};
+
+PinnedPool &pinned_pool() {
+  static PinnedPool *p = new PinnedPool();  // never destroyed: slabs outlive every model
+  return *p;
+}
+
+sacd_status pinned_get(double **out) {
+  PinnedPool &P = pinned_pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  if (P.free_list.empty()) {
+    char *slab = nullptr;
+    HIP_TRY(hipHostMalloc((void **)&slab, 65536, hipHostMallocDefault));
+    for (int i = 0; i < 1024; ++i) P.free_list.push_back((double *)(slab + 64 * i));
+  }
+  *out = P.free_list.back();
+  P.free_list.pop_back();
+  return SACD_OK;
+}
+
+void pinned_put(double *p) {
+  if (!p) return;
+  PinnedPool &P = pinned_pool();
+  std::lock_guard<std::mutex> lock(P.mu);
+  P.free_list.push_back(p);
+}
 
 }  // namespace
 
@@ -517,7 +553,9 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
   }
   const int total_bits = bits[0] + bits[1] + bits[2];
   const long long n = nnz;
-  DevAlloc tmp;
+  DevAlloc tmp;  // ingest buffers, from the tensor's allocator, released at the end
+  tmp.alloc = t->mem.alloc;
+  tmp.custom = t->mem.custom;
   unsigned long long *k0 = nullptr, *k1 = nullptr;
   float *v0 = nullptr, *v1 = nullptr;
   int *err = nullptr, *cnt = nullptr;
@@ -737,7 +775,7 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   SACD_TRY(A.get_t((size_t)m->full_nparts, &m->full_part));
   SACD_TRY(A.get_t(1, &m->full_out));
   SACD_TRY(A.get_t(4, &m->full_cnt));
-  HIP_TRY(hipHostMalloc((void **)&m->h_pinned, 64, hipHostMallocDefault));
+  SACD_TRY(pinned_get(&m->h_pinned));
   hipStream_t s = m->s;
   HIP_TRY(hipMemsetAsync(m->st, 0, 3 * sizeof(ModeState), s));
   HIP_TRY(hipMemsetAsync(m->full_cnt, 0, 16, s));
@@ -1063,7 +1101,7 @@ void sacd_destroy_model(sacd_model *m) {
   for (hipEvent_t e : m->tev) (void)hipEventDestroy(e);
   m->tev.clear();
   m->mem.release_all();
-  if (m->h_pinned) (void)hipHostFree(m->h_pinned);
+  pinned_put(m->h_pinned);
   const bool counted = m->counted;
   delete m;
   if (counted && t->nmodels > 0) t->nmodels--;
@@ -1116,6 +1154,58 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int
   *transient = 2 * al256(8 * nnz) + 2 * al256(4 * nnz) + al256(tb) + al256(16 * maxunits) + slack;
 }
 
+// Device memory of a server: one block of the budget's size, handed out in
+// 256-byte aligned pieces (first fit, free neighbours merged on release), so
+// that jobs come and go without a round trip to the system allocator.
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0;
+  std::map<size_t, size_t> free_;  // offset -> length
+  std::map<size_t, size_t> used_;  // offset -> length
+
+  void init(void *b, size_t n) {
+    base = (char *)b;
+    size = n & ~(size_t)255;
+    free_.clear();
+    used_.clear();
+    if (size) free_[0] = size;
+  }
+  void *alloc(size_t n) {
+    n = (std::max<size_t>(n, 1) + 255) & ~(size_t)255;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[off + n] = len - n;
+      used_[off] = n;
+      return base + off;
+    }
+    return nullptr;
+  }
+  void release(void *p) {
+    auto u = used_.find((size_t)((char *)p - base));
+    if (u == used_.end()) return;
+    size_t off = u->first, len = u->second;
+    used_.erase(u);
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + len == nx->first) {
+      len += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {
+        pv->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+};
+
+void *arena_alloc(size_t n, void *user) { return ((Arena *)user)->alloc(n); }
+void arena_release(void *p, void *user) { ((Arena *)user)->release(p); }
+
 struct ServerReq {
   int64_t ticket;
   int64_t dims[3];
@@ -1163,8 +1253,9 @@ struct BatchGroup {
 
 struct sacd_server {
   sacd_server_config cfg{};
-  sacd_allocator alloc{};
-  bool custom_alloc = false;
+  DevAlloc block;          // the arena's one device block (caller's allocator or hipMalloc)
+  Arena arena;
+  sacd_allocator alloc{};  // hands out arena pieces to the jobs
   int dev = 0;
   hipStream_t s = nullptr;
   bool own_stream = false;
@@ -1182,12 +1273,21 @@ struct sacd_server {
   const ModeState **d_sts = nullptr;
   double *d_f = nullptr, *h_f = nullptr;
   size_t h_f_cap = 0;
+  float *h_res = nullptr;  // pinned staging of a retiring job's factors
+  size_t h_res_cap = 0;
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int stable_steps = 0;
   int64_t steps = 0, graph_builds = 0, graph_launches = 0, eager_launches = 0;
+  double sec_admit = 0.0, sec_tables = 0.0, sec_iterate = 0.0, sec_retire = 0.0;  // host wall time
 };
+
+namespace {
+double now_sec() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
 
 namespace {
 
@@ -1210,10 +1310,8 @@ sacd_status admit(sacd_server *S, ServerReq &q, ServerJob *out) {
   ServerJob j;
   j.ticket = q.ticket;
   DevAlloc up;
-  if (S->custom_alloc) {
-    up.alloc = S->alloc;
-    up.custom = true;
-  }
+  up.alloc = S->alloc;
+  up.custom = true;
   int32_t *didx = nullptr;
   float *dvals = nullptr;
   sacd_status st = SACD_OK;
@@ -1228,7 +1326,7 @@ sacd_status admit(sacd_server *S, ServerReq &q, ServerJob *out) {
     }
   }
   if (st == SACD_OK)
-    st = sacd_create_tensor(q.dims, q.nnz, didx, dvals, S->custom_alloc ? &S->alloc : nullptr, S->s, &j.t);
+    st = sacd_create_tensor(q.dims, q.nnz, didx, dvals, &S->alloc, S->s, &j.t);
   (void)hipStreamSynchronize(S->s);
   up.release_all();
   if (st == SACD_OK) st = sacd_init_factors(j.t, q.R, q.seed, S->cfg.precision, SACD_UPDATE_GS, &j.m);
@@ -1415,13 +1513,30 @@ sacd_status retire(sacd_server *S, ServerJob &j, int state) {
   r.fit = j.fit;
   r.f = j.f;
   r.R = j.m->R;
+  size_t total = 0;
+  for (int n = 0; n < 3; ++n) total += (size_t)j.t->dims[n] * j.m->R;
+  if (total > S->h_res_cap) {
+    if (S->h_res) (void)hipHostFree(S->h_res);
+    S->h_res = nullptr;
+    S->h_res_cap = 0;
+    const size_t cap = std::max(total, (size_t)1 << 20);
+    HIP_TRY(hipHostMalloc((void **)&S->h_res, sizeof(float) * cap, hipHostMallocDefault));
+    S->h_res_cap = cap;
+  }
+  size_t off = 0;
   for (int n = 0; n < 3; ++n) {
     r.dims[n] = j.t->dims[n];
-    r.A[n].resize((size_t)j.t->dims[n] * j.m->R);
-    HIP_TRY(hipMemcpy2DAsync(r.A[n].data(), sizeof(float) * j.m->R, j.m->A[n], sizeof(float) * j.m->RP,
+    HIP_TRY(hipMemcpy2DAsync(S->h_res + off, sizeof(float) * j.m->R, j.m->A[n], sizeof(float) * j.m->RP,
                              sizeof(float) * j.m->R, (size_t)j.t->dims[n], hipMemcpyDeviceToHost, S->s));
+    off += (size_t)j.t->dims[n] * j.m->R;
   }
   HIP_TRY(hipStreamSynchronize(S->s));
+  off = 0;
+  for (int n = 0; n < 3; ++n) {
+    const size_t len = (size_t)j.t->dims[n] * j.m->R;
+    r.A[n].assign(S->h_res + off, S->h_res + off + len);
+    off += len;
+  }
   S->bytes_in_use -= j.bytes;
   destroy_job(j);
   S->finished.push_back(j.ticket);
@@ -1456,8 +1571,8 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
   if (!S) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
   S->cfg = *cfg;
   if (alloc) {
-    S->alloc = *alloc;
-    S->custom_alloc = true;
+    S->block.alloc = *alloc;
+    S->block.custom = true;
     S->tables.alloc = *alloc;
     S->tables.custom = true;
   }
@@ -1465,11 +1580,18 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
     delete S;
     return fail(SACD_ERR_DEVICE, "no HIP device");
   }
-  sacd_status st = make_stream(stream, &S->s, &S->own_stream);
+  void *base = nullptr;
+  sacd_status st = S->block.get((size_t)cfg->budget_bytes, &base);
+  if (st == SACD_OK) st = make_stream(stream, &S->s, &S->own_stream);
   if (st != SACD_OK) {
+    S->block.release_all();
     delete S;
     return st;
   }
+  S->arena.init(base, (size_t)cfg->budget_bytes);
+  S->alloc.alloc = arena_alloc;
+  S->alloc.release = arena_release;
+  S->alloc.user = &S->arena;
   *out = S;
   return SACD_OK;
 }
@@ -1504,12 +1626,14 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
   if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
   SACD_TRY(enter(S->dev));
   S->finished.clear();
+  double t0 = now_sec();
   // admission, first come first served, while the budget and slots allow
   while (!S->queue.empty() && (int)S->active.size() < S->cfg.max_slots) {
     ServerReq &q = S->queue.front();
     if (S->bytes_in_use + q.est_resident + q.est_transient > S->cfg.budget_bytes) break;
     ServerJob j;
     sacd_status st = admit(S, q, &j);
+    if (st == SACD_ERR_NO_MEMORY && !S->active.empty()) break;  // fragmented: retry when jobs leave
     ServerResult &r = S->results[q.ticket];
     if (st != SACD_OK) {
       r.state = SACD_JOB_FAILED;
@@ -1524,12 +1648,18 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
     }
     S->queue.pop_front();
   }
+  double t1 = now_sec();
+  S->sec_admit += t1 - t0;
   if (!S->active.empty()) {
     if (S->dirty) SACD_TRY(rebuild_tables(S));
+    double t2 = now_sec();
+    S->sec_tables += t2 - t1;
     SACD_TRY(run_iteration(S));
     const int J = (int)S->active.size();
     HIP_TRY(hipMemcpyAsync(S->h_f, S->d_f, sizeof(double) * J, hipMemcpyDeviceToHost, S->s));
     HIP_TRY(hipStreamSynchronize(S->s));
+    t1 = now_sec();
+    S->sec_iterate += t1 - t2;
     S->steps++;
     S->stable_steps++;
     std::vector<ServerJob> keep;
@@ -1552,6 +1682,7 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
     }
     S->active.swap(keep);
     if (S->dirty) server_drop_graph(S);
+    S->sec_retire += now_sec() - t1;
   }
   if (n_running) *n_running = (int32_t)S->active.size();
   if (n_queued) *n_queued = (int32_t)S->queue.size();
@@ -1618,6 +1749,10 @@ sacd_status sacd_server_stats(const sacd_server *S, sacd_server_stats_t *out) {
   out->graph_builds = S->graph_builds;
   out->graph_launches = S->graph_launches;
   out->eager_launches = S->eager_launches;
+  out->sec_admit = S->sec_admit;
+  out->sec_tables = S->sec_tables;
+  out->sec_iterate = S->sec_iterate;
+  out->sec_retire = S->sec_retire;
   return SACD_OK;
 }
 
@@ -1629,8 +1764,10 @@ void sacd_server_destroy(sacd_server *S) {
   for (ServerJob &j : S->active) destroy_job(j);
   S->active.clear();
   S->tables.release_all();
+  S->block.release_all();
   if (S->h_stage) (void)hipHostFree(S->h_stage);
   if (S->h_f) (void)hipHostFree(S->h_f);
+  if (S->h_res) (void)hipHostFree(S->h_res);
   if (S->own_stream && S->s) (void)hipStreamDestroy(S->s);
   delete S;
 }

@@ -49,7 +49,9 @@ class _ServerConfig(C.Structure):
 class _ServerStats(C.Structure):
     _fields_ = [("running", C.c_int32), ("queued", C.c_int32), ("bytes_in_use", C.c_int64),
                 ("peak_bytes", C.c_int64), ("steps", C.c_int64), ("graph_builds", C.c_int64),
-                ("graph_launches", C.c_int64), ("eager_launches", C.c_int64)]
+                ("graph_launches", C.c_int64), ("eager_launches", C.c_int64),
+                ("sec_admit", C.c_double), ("sec_tables", C.c_double), ("sec_iterate", C.c_double),
+                ("sec_retire", C.c_double)]
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3

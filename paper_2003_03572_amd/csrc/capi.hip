@@ -1259,6 +1259,10 @@ struct sacd_server {
   int dev = 0;
   hipStream_t s = nullptr;
   bool own_stream = false;
+  // one stream per padded rank: the ranks' launch chains run concurrently,
+  // forked from and joined back to s
+  hipStream_t gs[4] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[4] = {};
   std::deque<ServerReq> queue;
   std::vector<ServerJob> active;
   std::map<int64_t, ServerResult> results;
@@ -1459,16 +1463,22 @@ sacd_status rebuild_tables(sacd_server *S) {
 // objectives.  Per mode, the ranks' launches follow each other on the stream.
 sacd_status enqueue_batched_iteration(sacd_server *S) {
   const bool bf = S->cfg.precision == SACD_PREC_MIXED_BF16;
-  hipStream_t s = S->s;
-  for (int n = 0; n < 3; ++n)
-    for (BatchGroup &g : S->groups) {
+  HIP_TRY(hipEventRecord(S->ev_fork, S->s));
+  for (size_t gi = 0; gi < S->groups.size(); ++gi) {
+    BatchGroup &g = S->groups[gi];
+    hipStream_t s = S->gs[gi];
+    HIP_TRY(hipStreamWaitEvent(s, S->ev_fork, 0));
+    for (int n = 0; n < 3; ++n) {
       HIP_TRY(launch_mttkrp_b(g.RP, g.mt[n], g.bm_mt[n], g.nb_mt[n], s));
       HIP_TRY(launch_mttkrp_fix_b(g.RP, g.fx[n], g.bm_fx[n], g.nb_fx[n], s));
       HIP_TRY(launch_importance_b(g.RP, bf, g.im[n], g.bm_im[n], g.nb_im[n], s));
       HIP_TRY(launch_select_update_b(g.RP, bf, g.up[n], g.bm_im[n], g.nb_im[n], s));
       HIP_TRY(launch_gram_final_b(g.RP, g.gf[n], g.bm_gf[n], g.nb_gf[n], s));
     }
-  HIP_TRY(launch_gather_f(S->d_sts, (int)S->active.size(), S->d_f, s));
+    HIP_TRY(hipEventRecord(S->ev_join[gi], s));
+    HIP_TRY(hipStreamWaitEvent(S->s, S->ev_join[gi], 0));
+  }
+  HIP_TRY(launch_gather_f(S->d_sts, (int)S->active.size(), S->d_f, S->s));
   return SACD_OK;
 }
 
@@ -1583,9 +1593,15 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
   void *base = nullptr;
   sacd_status st = S->block.get((size_t)cfg->budget_bytes, &base);
   if (st == SACD_OK) st = make_stream(stream, &S->s, &S->own_stream);
+  for (int g = 0; g < 4 && st == SACD_OK; ++g) {
+    if (hipStreamCreateWithFlags(&S->gs[g], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_join[g], hipEventDisableTiming) != hipSuccess)
+      st = fail(SACD_ERR_DEVICE, "stream / event creation failed");
+  }
+  if (st == SACD_OK && hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess)
+    st = fail(SACD_ERR_DEVICE, "event creation failed");
   if (st != SACD_OK) {
-    S->block.release_all();
-    delete S;
+    sacd_server_destroy(S);
     return st;
   }
   S->arena.init(base, (size_t)cfg->budget_bytes);
@@ -1768,6 +1784,11 @@ void sacd_server_destroy(sacd_server *S) {
   if (S->h_stage) (void)hipHostFree(S->h_stage);
   if (S->h_f) (void)hipHostFree(S->h_f);
   if (S->h_res) (void)hipHostFree(S->h_res);
+  for (int g = 0; g < 4; ++g) {
+    if (S->gs[g]) (void)hipStreamDestroy(S->gs[g]);
+    if (S->ev_join[g]) (void)hipEventDestroy(S->ev_join[g]);
+  }
+  if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
   if (S->own_stream && S->s) (void)hipStreamDestroy(S->s);
   delete S;
 }

@@ -224,8 +224,9 @@ void sacd_destroy_model(sacd_model *m);
  * bound (sacd_job_bytes: resident + transient ingest bytes) stay within the
  * budget and a slot is free.  Each sacd_server_step admits what fits, then
  * runs one outer iteration (Alg. 1: sweeps of modes 0, 1, 2) of every running
- * job with job-batched kernels -- per mode and per padded rank one launch of
- * each sweep kernel covers all jobs -- replayed from a HIP graph while the
+ * job with persistent job-batched kernels -- per mode and per padded rank one
+ * launch of each sweep kernel covers all jobs, its blocks looping over the
+ * jobs' work items -- replayed from a HIP graph while the
  * set of running jobs is unchanged, and retires the jobs that met the
  * stopping rule of sacd_run_until (relative fit change < tol after at least
  * two iterations, or max_iter).  A job's arithmetic is the same as when it

@@ -26,6 +26,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kMaxRP = 128;
 
+// Grid of a job-batched (persistent) launch: at most kPersistentBlocks
+// blocks, each looping over the launch's work items (block-map entries).
+constexpr int kPersistentBlocks = 2048;
+inline int persistent_grid(int nb) { return nb < kPersistentBlocks ? nb : kPersistentBlocks; }
+
 // Per-mode selection / sweep state, resident in device memory so that a whole
 // iteration can be replayed as a HIP graph without host decisions.
 struct ModeState {
@@ -155,7 +160,8 @@ hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, in
 // sweep.hip
 // Arguments of one job's element kernels.  The solo launchers pass them by
 // value; the job-batched launchers take device arrays of them plus a block
-// map with one int4 (job, block of the job, blocks of the job, 0) per block.
+// map with one int4 (job, block of the job, blocks of the job, 0) per work
+// item; their blocks loop over the work items (persistent grid).
 struct ImpArgs {
   int I;
   const float *A, *M, *H;

@@ -179,12 +179,16 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a) {
   mttkrp_body<RP>(a, blockIdx.x);
 }
 
-// Job-batched form: block map entry (job, block of the job, blocks of the job).
+// Job-batched form: a persistent grid loops over the block map's entries
+// (job, block of the job, blocks of the job).
 template <int RP>
 __global__ __launch_bounds__(kThreads) void k_mttkrp_b(const MttkrpArgs *__restrict__ jobs,
-                                                       const int4 *__restrict__ bmap) {
-  const int4 m = bmap[blockIdx.x];
-  mttkrp_body<RP>(jobs[m.x], m.y);
+                                                       const int4 *__restrict__ bmap, int nb) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int4 m = bmap[b];
+    mttkrp_body<RP>(jobs[m.x], m.y);
+    __syncthreads();  // the block's LDS is reused by its next work item
+  }
 }
 
 }  // namespace
@@ -291,9 +295,12 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs a) {
 
 template <int RP>
 __global__ __launch_bounds__(kThreads) void k_mttkrp_fix_b(const FixArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap) {
-  const int4 m = bmap[blockIdx.x];
-  fix_body<RP>(jobs[m.x], m.y);
+                                                           const int4 *__restrict__ bmap, int nb) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int4 m = bmap[b];
+    fix_body<RP>(jobs[m.x], m.y);
+    __syncthreads();  // the block's LDS is reused by its next work item
+  }
 }
 
 template <template <int> class F, typename... Args>
@@ -321,7 +328,7 @@ template <int RP>
 struct MtBL {
   static hipError_t run(const MttkrpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mttkrp_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    hipLaunchKernelGGL(k_mttkrp_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
     return hipGetLastError();
   }
 };
@@ -338,7 +345,7 @@ template <int RP>
 struct FxBL {
   static hipError_t run(const FixArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mttkrp_fix_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    hipLaunchKernelGGL(k_mttkrp_fix_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
     return hipGetLastError();
   }
 };

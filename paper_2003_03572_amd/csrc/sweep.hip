@@ -280,12 +280,16 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs a) {
   importance_body<RP, BF>(a, blockIdx.x, gridDim.x);
 }
 
-// Job-batched form: block map entry (job, block of the job, blocks of the job).
+// Job-batched form: a persistent grid loops over the block map's entries
+// (job, block of the job, blocks of the job).
 template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_importance_b(const ImpArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap) {
-  const int4 m = bmap[blockIdx.x];
-  importance_body<RP, BF>(jobs[m.x], m.y, m.z);
+                                                           const int4 *__restrict__ bmap, int nb) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int4 m = bmap[b];
+    importance_body<RP, BF>(jobs[m.x], m.y, m.z);
+    __syncthreads();  // the block's LDS is reused by its next work item
+  }
 }
 
 // Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
@@ -459,9 +463,12 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs a) {
 
 template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_select_update_b(const UpdArgs *__restrict__ jobs,
-                                                              const int4 *__restrict__ bmap) {
-  const int4 m = bmap[blockIdx.x];
-  select_update_body<RP, 0, false, BF>(jobs[m.x], m.y);
+                                                              const int4 *__restrict__ bmap, int nb) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int4 m = bmap[b];
+    select_update_body<RP, 0, false, BF>(jobs[m.x], m.y);
+    __syncthreads();  // the block's LDS is reused by its next work item
+  }
 }
 
 // Gram partials of an arbitrary factor (initialisation, set_factor).
@@ -625,9 +632,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs a) {
 
 template <int RP>
 __global__ __launch_bounds__(kThreads) void k_gram_final_b(const GramArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap) {
-  const int4 m = bmap[blockIdx.x];
-  gram_final_body<RP>(jobs[m.x], m.y, m.z);
+                                                           const int4 *__restrict__ bmap, int nb) {
+  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int4 m = bmap[b];
+    gram_final_body<RP>(jobs[m.x], m.y, m.z);
+    __syncthreads();  // the block's LDS is reused by its next work item
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_factor(float *__restrict__ A, int I, int R, int RP,
@@ -784,8 +794,8 @@ template <int RP>
 struct ImpBL {
   static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_importance_b<RP, true>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
-    else hipLaunchKernelGGL((k_importance_b<RP, false>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    if (bf) hipLaunchKernelGGL((k_importance_b<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    else hipLaunchKernelGGL((k_importance_b<RP, false>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
     return hipGetLastError();
   }
 };
@@ -812,8 +822,8 @@ template <int RP>
 struct UpdBL {
   static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_select_update_b<RP, true>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
-    else hipLaunchKernelGGL((k_select_update_b<RP, false>), dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    if (bf) hipLaunchKernelGGL((k_select_update_b<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    else hipLaunchKernelGGL((k_select_update_b<RP, false>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
     return hipGetLastError();
   }
 };
@@ -841,7 +851,7 @@ template <int RP>
 struct GfBL {
   static hipError_t run(const GramArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram_final_b<RP>, dim3(nb), dim3(kThreads), 0, s, jobs, bmap);
+    hipLaunchKernelGGL(k_gram_final_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
     return hipGetLastError();
   }
 };

@@ -79,6 +79,8 @@ def lib():
         L.ora_objective.restype = dbl
         L.ora_fit.argtypes = [p, p, p]
         L.ora_run_until.argtypes = [p, dbl, i32, p, p, p]
+        L.ora_rmse.argtypes = [p, i64, p, p, p]
+        L.ora_pd.argtypes = [p, i32, p]
         _lib = L
     return _lib
 
@@ -262,6 +264,20 @@ class Model:
         f = C.c_double()
         _check(lib().ora_fit(self._h, C.byref(fit), C.byref(f)), "ora_fit")
         return fit.value, f.value
+
+    def rmse(self, idx: np.ndarray, vals: np.ndarray) -> float:
+        """eq. 30 on the given (held-out) entries."""
+        idx = np.ascontiguousarray(idx, np.int32).reshape(-1, 3)
+        vals = np.ascontiguousarray(vals, np.float32).reshape(-1)
+        out = C.c_double()
+        _check(lib().ora_rmse(self._h, idx.shape[0], _ptr(idx), _ptr(vals), C.byref(out)), "ora_rmse")
+        return out.value
+
+    def pd(self, mode: int = 2) -> float:
+        """Pattern distinctiveness (eq. pd) of the columns of factor `mode`."""
+        out = C.c_double()
+        _check(lib().ora_pd(self._h, mode, C.byref(out)), "ora_pd")
+        return out.value
 
     def run_until(self, tol: float, max_iter: int):
         trace = np.zeros(max_iter, np.float64)

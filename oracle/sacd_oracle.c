@@ -391,6 +391,50 @@ int ora_fit(const ora_model *m, double *fit, double *f) {
   return ORA_OK;
 }
 
+/* eq. 30 on the given entries: sqrt(sum (x - xhat)^2 / n), xhat from eq. 5. */
+int ora_rmse(const ora_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse) {
+  if (!m || !rmse || n < 0 || (n > 0 && (!idx || !vals))) return ORA_EINVAL;
+  const int R = m->R;
+  double se = 0.0;
+  for (int64_t p = 0; p < n; ++p) {
+    for (int k = 0; k < 3; ++k)
+      if (idx[3 * p + k] < 0 || idx[3 * p + k] >= m->t->dims[k]) return ORA_ERANGE;
+    double xhat = 0.0;
+    for (int r = 0; r < R; ++r)
+      xhat += m->A[0][(int64_t)idx[3 * p] * R + r] * m->A[1][(int64_t)idx[3 * p + 1] * R + r] *
+              m->A[2][(int64_t)idx[3 * p + 2] * R + r];
+    const double e = (double)vals[p] - xhat;
+    se += e * e;
+  }
+  *rmse = n > 0 ? sqrt(se / (double)n) : 0.0;
+  return ORA_OK;
+}
+
+/* eq. pd: cosine similarity of columns i < r of factor `mode`, averaged. */
+int ora_pd(const ora_model *m, int mode, double *pd) {
+  if (!m || !pd || mode < 0 || mode > 2) return ORA_EINVAL;
+  const int R = m->R;
+  const int64_t I = m->t->dims[mode];
+  const double *A = m->A[mode];
+  double sum = 0.0;
+  int64_t pairs = 0;
+  for (int i = 0; i < R; ++i)
+    for (int r = i + 1; r < R; ++r) {
+      double dot = 0.0, ni = 0.0, nr = 0.0;
+      for (int64_t q = 0; q < I; ++q) {
+        dot += A[q * R + i] * A[q * R + r];
+        ni += A[q * R + i] * A[q * R + i];
+        nr += A[q * R + r] * A[q * R + r];
+      }
+      if (ni > 0.0 && nr > 0.0) {
+        sum += dot / (sqrt(ni) * sqrt(nr));
+        ++pairs;
+      }
+    }
+  *pd = pairs > 0 ? sum / (double)pairs : 0.0;
+  return ORA_OK;
+}
+
 /* Update of one row's selected elements (step 9 below).  a: the row (R
  * values, updated in place); sel: decisions; M, delta: the row's MTTKRP and
  * snapshot steps; H: R x R. */

@@ -100,6 +100,17 @@ int ora_sweep_alternatives(const ora_model *m, int mode, int64_t *n_rows, int64_
 double ora_objective(const ora_model *m);
 int ora_fit(const ora_model *m, double *fit, double *f);
 
+/* Accuracy of a factorization (Sec. 6, evaluation criteria).
+ * ora_rmse: eq. 30, the root mean square error of the model on n entries
+ * (idx: n x 3 coordinates, vals: observed values), typically held out of the
+ * factorised tensor; n = 0 gives 0.  ERANGE for a coordinate outside dims.
+ * ora_pd: pattern distinctiveness of the columns of factor `mode`: the
+ * cosine similarity of every column pair i < r (eq. pd), averaged (the paper
+ * lists the pairs without saying how they are combined; the mean is the
+ * reading taken).  Pairs with a zero column are left out; no pair gives 0. */
+int ora_rmse(const ora_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse);
+int ora_pd(const ora_model *m, int mode, double *pd);
+
 /* Outer loop of Alg. 1: iterations of sweep(0), sweep(1), sweep(2); stops
  * after iteration k >= 2 when |fit_k - fit_{k-1}| < tol * |fit_{k-1}|, or at
  * max_iter.  fit_trace (may be NULL) receives one fit per iteration. */

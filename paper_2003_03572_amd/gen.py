@@ -214,6 +214,14 @@ def job_tensor(spec: JobSpec) -> TensorCOO:
                        max_rounds=8)
 
 
+def split_holdout(idx: np.ndarray, vals: np.ndarray, test_frac: float, seed: int):
+    """Seeded random split of the entries into a training tensor and held-out
+    test entries (a fraction test_frac of them), both in input order."""
+    rng = _rng(seed)
+    test = rng.random(idx.shape[0]) < test_frac
+    return idx[~test], vals[~test], idx[test], vals[test]
+
+
 def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
     """Arrival times (seconds) of a Poisson process of the given rate."""
     rng = _rng(seed)

@@ -366,3 +366,60 @@ def test_run_until_stops_on_relative_fit_change(oracle_mod):
     for k in range(1, it - 1):
         assert abs(trace[k] - trace[k - 1]) >= 1e-3 * abs(trace[k - 1])
     assert fit == trace[-1]
+
+
+# ------------------------------------------------- accuracy (Sec. 6) ------
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_rmse_is_dense_reconstruction_error_on_held_out_cells(oracle_mod, seed):
+    """eq. 30 against the dense CP reconstruction (eq. 5) at the held-out cells."""
+    dims, idx, vals = _tiny(seed, dims=(5, 4, 6), nnz=60)
+    tr_i, tr_v, te_i, te_v = gen.split_holdout(idx, vals, 0.3, seed)
+    assert te_i.shape[0] > 0 and tr_i.shape[0] + te_i.shape[0] == idx.shape[0]
+    T = oracle_mod.Tensor(dims, tr_i, tr_v)
+    m = oracle_mod.Model(T, 3, seed=seed)
+    for n in range(3):
+        m.sweep(n)
+    A = [m.factor(n) for n in range(3)]
+    Xhat = np.einsum("ir,jr,kr->ijk", A[0], A[1], A[2])
+    ref = math.sqrt(np.mean((te_v.astype(np.float64) - Xhat[te_i[:, 0], te_i[:, 1], te_i[:, 2]]) ** 2))
+    assert math.isclose(m.rmse(te_i, te_v), ref, rel_tol=1e-12)
+    assert m.rmse(te_i[:0], te_v[:0]) == 0.0
+
+
+def test_rmse_of_an_exact_model(oracle_mod):
+    """A tensor drawn from known nonnegative factors: the model holding those
+    factors has RMSE 0 on any of its cells, and 1 when every value is off by 1."""
+    rng = np.random.default_rng(3)
+    dims, R = (6, 5, 4), 2
+    F = [rng.random((d, R)) for d in dims]
+    X = np.einsum("ir,jr,kr->ijk", *F)
+    idx = np.argwhere(np.ones(dims, bool)).astype(np.int32)
+    vals = X[idx[:, 0], idx[:, 1], idx[:, 2]].astype(np.float32)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, R, seed=1)
+    for n in range(3):
+        m.set_factor(n, F[n])
+    exact = X[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert m.rmse(idx, exact.astype(np.float32)) < 1e-6  # float32 rounding of the values only
+    shifted = (exact + 1.0).astype(np.float32)
+    assert math.isclose(m.rmse(idx, shifted), 1.0, rel_tol=1e-6)
+    with pytest.raises(oracle_mod.OracleError):
+        m.rmse(np.array([[6, 0, 0]], np.int32), np.array([1.0], np.float32))
+
+
+def test_pattern_distinctiveness_closed_forms(oracle_mod):
+    """eq. pd: disjoint columns give 0, equal columns 1, columns 60 degrees
+    apart 1/2; pairs with a zero column are left out."""
+    dims = (2, 2, 4)
+    idx = np.array([[0, 0, 0], [1, 1, 1]], np.int32)
+    T = oracle_mod.Tensor(dims, idx, np.ones(2, np.float32))
+    m = oracle_mod.Model(T, 3, seed=1)
+    W = np.array([[1.0, 1.0, 0.0], [0.0, 0.0, 2.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    m.set_factor(2, W)  # pairs: (0,1) equal -> 1, (0,2) and (1,2) disjoint -> 0
+    assert math.isclose(m.pd(2), 1.0 / 3.0, rel_tol=1e-14)
+    W = np.array([[1.0, 0.5, 0.0], [0.0, math.sqrt(3.0) / 2.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    m.set_factor(2, W)  # only the pair (0, 1) counts: cos 60 deg
+    assert math.isclose(m.pd(2), 0.5, rel_tol=1e-14)
+    m.set_factor(2, np.zeros((4, 3)))
+    assert m.pd(2) == 0.0

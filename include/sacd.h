@@ -156,6 +156,19 @@ sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t 
 /* Copy factor `mode` out to / in from device memory (I_n x R row-major
  * FP32).  set_factor rejects negative or non-finite values (NUMERIC) and
  * recomputes that mode's Gram matrix.  Synchronises. */
+/* Accuracy of the factorization (Sec. 6, evaluation criteria).
+ * sacd_rmse: eq. 30, sqrt(sum (x - x_hat)^2 / n) over n entries, usually
+ * held out of the factorised tensor.  idx: device, n x 3 int32 0-based
+ * coordinates; vals: device, n f32.  x_hat (eq. 5) is formed from the FP32
+ * factors in FP64.  OUT_OF_RANGE if a coordinate is outside dims; n = 0
+ * gives 0.  Synchronises.
+ * sacd_pd: pattern distinctiveness (eq. pd) of the columns of factor `mode`
+ * (the paper uses the last factor): the cosine similarity of every column
+ * pair i < r, averaged over the pairs; pairs with a zero column are left out
+ * (no pair left: 0).  Computed from the factor's Gram matrix.  Synchronises. */
+sacd_status sacd_rmse(sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse);
+sacd_status sacd_pd(const sacd_model *m, int32_t mode, double *pd);
+
 sacd_status sacd_get_factor(const sacd_model *m, int32_t mode, float *dst);
 sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src);
 

@@ -898,6 +898,49 @@ sacd_status sacd_fit(sacd_model *m, double *fit, double *objective) {
   return SACD_OK;
 }
 
+sacd_status sacd_rmse(sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse) {
+  if (!m || !rmse || n < 0 || (n > 0 && (!idx || !vals))) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  if (n == 0) {
+    *rmse = 0.0;
+    return SACD_OK;
+  }
+  SACD_TRY(enter(m->t->dev));
+  HIP_TRY(hipMemsetAsync(m->flag, 0, sizeof(int), m->s));
+  HIP_TRY(launch_sq_error(idx, vals, n, m->t->dims, m->RP, m->A[0], m->A[1], m->A[2], m->full_part,
+                          m->full_nparts, m->full_out, m->full_cnt, m->flag, m->s));
+  HIP_TRY(hipMemcpyAsync(m->h_pinned, m->full_out, sizeof(double), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipMemcpyAsync(m->h_pinned + 1, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  int bad = 0;
+  std::memcpy(&bad, m->h_pinned + 1, sizeof(int));
+  if (bad) return fail(SACD_ERR_OUT_OF_RANGE, "a coordinate is outside the tensor's dims");
+  *rmse = std::sqrt(m->h_pinned[0] / (double)n);
+  return SACD_OK;
+}
+
+sacd_status sacd_pd(const sacd_model *m, int32_t mode, double *pd) {
+  SACD_TRY(check_mode(m, mode));
+  if (!pd) return fail(SACD_ERR_INVALID_ARG, "pd is NULL");
+  SACD_TRY(enter(m->t->dev));
+  const int RP = m->RP, R = m->R;
+  std::vector<double> G((size_t)RP * RP);
+  HIP_TRY(hipMemcpyAsync(G.data(), m->G64[mode], sizeof(double) * RP * RP, hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  // cosine of columns i < r from the Gram matrix of the factor
+  double sum = 0.0;
+  long long pairs = 0;
+  for (int i = 0; i < R; ++i)
+    for (int r = i + 1; r < R; ++r) {
+      const double gi = G[(size_t)i * RP + i], gr = G[(size_t)r * RP + r];
+      if (gi > 0.0 && gr > 0.0) {
+        sum += G[(size_t)i * RP + r] / (std::sqrt(gi) * std::sqrt(gr));
+        ++pairs;
+      }
+    }
+  *pd = pairs > 0 ? sum / (double)pairs : 0.0;
+  return SACD_OK;
+}
+
 sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t *iters_done,
                            double *final_fit) {
   if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");

@@ -218,6 +218,9 @@ hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0
                              unsigned *counter, hipStream_t s);
 hipError_t launch_copy_rows(const float *src, int src_stride, float *dst, int dst_stride, int I,
                             int ncols, int zero_cols_to, hipStream_t s);
+hipError_t launch_sq_error(const int32_t *idx, const float *vals, long long n, const int64_t *dims, int RP,
+                           const float *A0, const float *A1, const float *A2, double *partials, int nparts,
+                           double *out, unsigned *counter, int *bad, hipStream_t s);
 hipError_t launch_gather_f(const ModeState *const *sts, int n, double *out, hipStream_t s);
 hipError_t launch_check_factor(const float *src, long long n, int *flag, hipStream_t s);
 

@@ -716,6 +716,56 @@ __global__ __launch_bounds__(kThreads) void k_copy_rows(const float *__restrict_
   }
 }
 
+// Sum of squared errors of the model on n entries (the numerator of eq. 30):
+// x_hat = sum_r A0[i0, r] A1[i1, r] A2[i2, r] from the FP32 factors, in FP64.
+// Block partials are reduced by the last block in a fixed order.  A
+// coordinate outside dims sets *bad and adds nothing.
+__global__ __launch_bounds__(kThreads) void k_sq_error(const int32_t *__restrict__ idx,
+                                                       const float *__restrict__ vals, long long n,
+                                                       int d0, int d1, int d2, int RP,
+                                                       const float *__restrict__ A0,
+                                                       const float *__restrict__ A1,
+                                                       const float *__restrict__ A2,
+                                                       double *__restrict__ part, double *out,
+                                                       unsigned *counter, int *bad) {
+  __shared__ double red[kThreads];
+  __shared__ int s_last;
+  double s = 0.0;
+  int oob = 0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int i0 = idx[3 * p], i1 = idx[3 * p + 1], i2 = idx[3 * p + 2];
+    if (i0 < 0 || i0 >= d0 || i1 < 0 || i1 >= d1 || i2 < 0 || i2 >= d2) {
+      oob = 1;
+      continue;
+    }
+    double xh = 0.0;
+    for (int r = 0; r < RP; ++r)
+      xh += (double)A0[(long long)i0 * RP + r] * (double)A1[(long long)i1 * RP + r] *
+            (double)A2[(long long)i2 * RP + r];
+    const double e = (double)vals[p] - xh;
+    s += e * e;
+  }
+  if (oob) atomicOr(bad, 1);
+  const double bs = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = bs;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double t = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) t += ld_coherent(&part[i]);
+  const double tot = block_sum(t, red);
+  if (threadIdx.x == 0) {
+    *out = tot;
+    *counter = 0;
+  }
+}
+
 // Objective of the last sweep of each of n jobs, gathered into one array.
 __global__ __launch_bounds__(kThreads) void k_gather_f(const ModeState *const *__restrict__ sts, int n,
                                                        double *__restrict__ out) {
@@ -893,6 +943,17 @@ hipError_t launch_copy_rows(const float *src, int src_stride, float *dst, int ds
                             int ncols, int zero_cols_to, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((long long)I * zero_cols_to)), dim3(kThreads), 0, s, src,
                      src_stride, dst, dst_stride, I, ncols, zero_cols_to);
+  return hipGetLastError();
+}
+
+hipError_t launch_sq_error(const int32_t *idx, const float *vals, long long n, const int64_t *dims, int RP,
+                           const float *A0, const float *A1, const float *A2, double *partials, int nparts,
+                           double *out, unsigned *counter, int *bad, hipStream_t s) {
+  long long g = (n + kThreads - 1) / kThreads;
+  if (g < 1) g = 1;
+  if (g > nparts) g = nparts;
+  hipLaunchKernelGGL(k_sq_error, dim3((int)g), dim3(kThreads), 0, s, idx, vals, n, (int)dims[0], (int)dims[1],
+                     (int)dims[2], RP, A0, A1, A2, partials, out, counter, bad);
   return hipGetLastError();
 }
 

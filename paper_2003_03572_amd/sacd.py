@@ -98,6 +98,8 @@ def lib():
             "sacd_kernel_bytes": [p, i32, i32, p],
             "sacd_model_bytes": [p, p],
             "sacd_job_bytes": [p, i64, i32, p, p],
+            "sacd_rmse": [p, i64, p, p, p],
+            "sacd_pd": [p, i32, p],
             "sacd_server_create": [p, p, p, C.POINTER(p)],
             "sacd_server_submit": [p, p, i64, p, p, i32, C.c_uint64, p],
             "sacd_server_step": [p, p, p],
@@ -315,6 +317,23 @@ class Model:
         _check(lib().sacd_get_diagnostics(self._h, mode, _dptr(M), _dptr(sel),
                                           G.ctypes.data_as(C.c_void_p)), "sacd_get_diagnostics")
         return M, sel.bool(), G
+
+    def rmse(self, idx, vals) -> float:
+        """eq. 30 on the given (held-out) entries: idx (n, 3), vals (n,)."""
+        idx = torch.as_tensor(np.ascontiguousarray(idx, np.int32) if isinstance(idx, np.ndarray) else idx)
+        vals = torch.as_tensor(np.ascontiguousarray(vals, np.float32) if isinstance(vals, np.ndarray) else vals)
+        idx = idx.to(self.t.device, torch.int32).contiguous().view(-1, 3)
+        vals = vals.to(self.t.device, torch.float32).contiguous().view(-1)
+        self.t.stream.wait_stream(torch.cuda.current_stream(self.t.device))
+        out = C.c_double()
+        _check(lib().sacd_rmse(self._h, idx.shape[0], _dptr(idx), _dptr(vals), C.byref(out)), "sacd_rmse")
+        return out.value
+
+    def pd(self, mode: int = 2) -> float:
+        """Pattern distinctiveness (eq. pd) of the columns of factor `mode`."""
+        out = C.c_double()
+        _check(lib().sacd_pd(self._h, mode, C.byref(out)), "sacd_pd")
+        return out.value
 
     def time_kernel(self, which: int, mode: int, reps: int) -> float:
         ms = C.c_float()

@@ -14,8 +14,9 @@
 //   k_gram_final     reduces the Gram partials in FP64 in a fixed order; the
 //                    last block forms the objective eq. 6 in FP64.
 //
-// Rows are split into blocks of RB rows; a block keeps its rows of A_n in LDS
-// (row stride RP + 1 floats: conflict-free for the lane-per-row update).
+// Rows are split into blocks of RB rows (RB lanes x columns = 256 x 32 at
+// most); a block keeps its rows of A_n and H in LDS (row stride RP + 1
+// floats: conflict-free for the row-wise update).
 #include "common.hpp"
 
 namespace sacd {
@@ -292,58 +293,62 @@ __global__ __launch_bounds__(kThreads) void k_importance_b(const ImpArgs *__rest
   }
 }
 
-// Gauss-Seidel / Jacobi update of one row, row data in registers (RP <= 64).
-template <int RP, int UPD>
-__device__ __forceinline__ void update_row_reg(float *a_l, const float *g_l, const unsigned short *s_l,
-                                               const float *sH, const HInfo *__restrict__ hi) {
-  float a[RP], g[RP];
-  unsigned long long sel = 0;
+// Gauss-Seidel / Jacobi update of one row (eq. 11-13), LPR lanes per row:
+// lane `part` keeps the row's columns [part CPL, (part + 1) CPL) of a and g
+// in registers.  For each selected column r in order, the lane owning r
+// takes the one-variable step; under Gauss-Seidel the step d is passed to
+// the row's other lanes, which refresh their columns' gradient,
+// g_s += d H_rs.  Only columns s > r are read again, so the refresh of the
+// others (done to keep the loop free of per-lane bounds) changes nothing.
+template <int RP, int UPD, int LPR>
+__device__ __forceinline__ void update_row(float *a_l, const float *g_l, const unsigned short *s_l,
+                                           const float *sH, const HInfo *__restrict__ hi, int part) {
+  constexpr int CPL = RP / LPR;  // columns per lane
+  const int c0 = part * CPL;
+  float a[CPL], g[CPL];
 #pragma unroll
-  for (int w = 0; w < RP / 16; ++w) sel |= (unsigned long long)s_l[w] << (16 * w);
-#pragma unroll
-  for (int c = 0; c < RP; ++c) {
-    a[c] = a_l[c];
-    g[c] = g_l[c];
+  for (int j = 0; j < CPL; ++j) {
+    a[j] = a_l[c0 + j];
+    g[j] = g_l[c0 + j];
   }
-  if (sel == 0) return;
+  // selection bits of the whole row: the row's lanes walk the same steps
+  constexpr int NW = (RP + 63) / 64;
+  unsigned long long sel[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    sel[w] = 0;
+#pragma unroll
+    for (int k = 0; k < 4 && 4 * w + k < RP / 16; ++k)
+      sel[w] |= (unsigned long long)s_l[4 * w + k] << (16 * k);
+  }
 #pragma unroll
   for (int r = 0; r < RP; ++r) {
-    if ((sel >> r) & 1ull) {
-      const float h = hi->hdiag[r];
-      if (h > 0.0f) {
-        const float q = hi->nearzero[r] ? (float)((double)g[r] / (double)h) : __fdiv_rn(g[r], h);
-        const float an = fmaxf(__fsub_rn(a[r], q), 0.0f);  // eq. 11-13
-        const float d = __fsub_rn(an, a[r]);
-        a[r] = an;
-        if (UPD == 0 && d != 0.0f) {
-          // refresh the gradient of the row's later elements: g_s += d * H_rs
+    if (!((sel[r >> 6] >> (r & 63)) & 1ull)) continue;
+    const float h = hi->hdiag[r];
+    if (!(h > 0.0f)) continue;
+    const int owner = r / CPL, j = r % CPL;
+    float d = 0.0f;
+    if (LPR == 1 || part == owner) {
+      const float q = hi->nearzero[r] ? (float)((double)g[j] / (double)h) : __fdiv_rn(g[j], h);
+      const float an = fmaxf(__fsub_rn(a[j], q), 0.0f);  // eq. 11-13
+      d = __fsub_rn(an, a[j]);
+      a[j] = an;
+    }
+    if (UPD == 0) {
+      if (LPR > 1) d = __shfl(d, owner, LPR);
+      if (d != 0.0f) {
+        if (LPR == 1) {
 #pragma unroll
           for (int s = r + 1; s < RP; ++s) g[s] = __fmaf_rn(d, sH[r * (RP + 1) + s], g[s]);
+        } else if (c0 + CPL - 1 > r) {
+#pragma unroll
+          for (int jj = 0; jj < CPL; ++jj) g[jj] = __fmaf_rn(d, sH[r * (RP + 1) + c0 + jj], g[jj]);
         }
       }
     }
   }
 #pragma unroll
-  for (int c = 0; c < RP; ++c) a_l[c] = a[c];
-}
-
-// Same update with the row kept in LDS (RP = 128).
-template <int RP, int UPD>
-__device__ __forceinline__ void update_row_lds(float *a_l, float *g_l, const unsigned short *s_l,
-                                               const float *sH, const HInfo *__restrict__ hi) {
-  for (int r = 0; r < RP; ++r) {
-    if (!((s_l[r >> 4] >> (r & 15)) & 1)) continue;
-    const float h = hi->hdiag[r];
-    if (!(h > 0.0f)) continue;
-    const float gr = g_l[r], ar = a_l[r];
-    const float q = hi->nearzero[r] ? (float)((double)gr / (double)h) : __fdiv_rn(gr, h);
-    const float an = fmaxf(__fsub_rn(ar, q), 0.0f);
-    const float d = __fsub_rn(an, ar);
-    a_l[r] = an;
-    if (UPD == 0 && d != 0.0f) {
-      for (int s = r + 1; s < RP; ++s) g_l[s] = __fmaf_rn(d, sH[r * (RP + 1) + s], g_l[s]);
-    }
-  }
+  for (int j = 0; j < CPL; ++j) a_l[c0 + j] = a[j];
 }
 
 // Block blk of the selection / update pass of one sweep.
@@ -425,11 +430,12 @@ __device__ __forceinline__ void select_update_body(const UpdArgs &args, int blk)
     if (lane < 16 && cnt) atomicAdd(&sCnt[cc], cnt);
   }
   __syncthreads();
-  if (tid < Cf::RB && row0 + tid < I) {
-    if constexpr (RP <= 64)
-      update_row_reg<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * (RP / 16), sH, hi);
-    else
-      update_row_lds<RP, UPD>(sA + tid * Cf::STR, sG + tid * Cf::STR, sSel + tid * (RP / 16), sH, hi);
+  {
+    constexpr int LPR = kThreads / Cf::RB;  // lanes per row: 1, 2 or 4
+    const int row = tid / LPR;
+    if (row0 + row < I)  // the same for all lanes of a row
+      update_row<RP, UPD, LPR>(sA + row * Cf::STR, sG + row * Cf::STR, sSel + row * (RP / 16), sH, hi,
+                               tid % LPR);
   }
   __syncthreads();
   for (int i = tid; i < Cf::RB * RP; i += kThreads) {

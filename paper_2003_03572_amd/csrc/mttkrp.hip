@@ -43,9 +43,27 @@ struct MCfg {
 __device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
 __device__ __forceinline__ void st4(float *p, f32x4 v) { *(f32x4 *)p = v; }
 
-// Block blk of the MTTKRP of one sweep.
-template <int RP>
-__device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
+// MTTKRP of one sweep.  Solo form (BATCHED false): block b is work item b
+// of the job in `solo`.  Job-batched form: a persistent grid loops over the
+// block map's entries (job in `jobs`, block of the job, blocks of the job).
+// The body is written in the kernel itself rather than in a device function
+// called by two kernels: the compiler then keeps the kernel-argument
+// guarantees and schedules the row gathers without intermediate waits.
+template <int RP, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const MttkrpArgs *__restrict__ jobs,
+                                                     const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  MttkrpArgs args;
+  int blk;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    args = jobs[m.x];
+    blk = m.y;
+  } else {
+    args = solo;
+    blk = blockIdx.x;
+  }
   const unsigned long long *__restrict__ keys = args.keys;
   const float *__restrict__ vals = args.vals;
   const int4 *__restrict__ units = args.units;
@@ -83,6 +101,12 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
 #endif
   }
   unsigned long long fib = ~0ull;  // (i_n, i_a) of the current fibre
+  // software pipeline: the keys of batch k + 1 are loaded while batch k's
+  // rows are gathered, so gather addresses never wait on a load issued
+  // after another gather (loads complete in order)
+  unsigned long long kn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) kn[u] = (u < len) ? keys[p0 + u] : 0ull;
   for (int e = 0; e < len; e += U) {
     unsigned long long kk[U];
     float xv[U];
@@ -90,8 +114,7 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = e + u < len;
-      kk[u] = ok[u] ? keys[p0 + e + u] : 0ull;
-      xv[u] = ok[u] ? vals[p0 + e + u] : 0.0f;
+      kk[u] = kn[u];
     }
     f32x4 bv[U][NV], av[U][NV];
     bool nf[U];
@@ -112,6 +135,10 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
         for (int j = 0; j < NV; ++j) av[u][j] = ld4(pa + 4 * LPN * j);
       }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = ok[u] ? vals[p0 + e + u] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) kn[u] = (e + U + u < len) ? keys[p0 + e + U + u] : 0ull;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #if SACD_MT_FIBRE
@@ -172,23 +199,9 @@ __device__ __forceinline__ void mttkrp_body(const MttkrpArgs &args, int blk) {
     }
     if (run >= 0) part[(long long)run * RP + c] = s;
   }
-}
-
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs a) {
-  mttkrp_body<RP>(a, blockIdx.x);
-}
-
-// Job-batched form: a persistent grid loops over the block map's entries
-// (job, block of the job, blocks of the job).
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_b(const MttkrpArgs *__restrict__ jobs,
-                                                       const int4 *__restrict__ bmap, int nb) {
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int4 m = bmap[b];
-    mttkrp_body<RP>(jobs[m.x], m.y);
-    __syncthreads();  // the block's LDS is reused by its next work item
-  }
+  if constexpr (!BATCHED) break;
+  __syncthreads();  // the block's LDS is reused by its next work item
+ }
 }
 
 }  // namespace
@@ -319,7 +332,7 @@ struct MtL {
   static hipError_t run(const MttkrpArgs &a, hipStream_t s) {
     const int nb = mttkrp_blocks(RP, a.nunits);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mttkrp<RP>, dim3(nb), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_mttkrp<RP, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -328,7 +341,8 @@ template <int RP>
 struct MtBL {
   static hipError_t run(const MttkrpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mttkrp_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    hipLaunchKernelGGL((k_mttkrp<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, MttkrpArgs{},
+                       jobs, bmap, nb);
     return hipGetLastError();
   }
 };

@@ -221,8 +221,22 @@ namespace {
 // fixed tree order; the next row_blocks blocks zero empty slices; the last
 // block forms H = Gram_a * Gram_b, L = ||H||_F and the diagonal of H for the
 // element kernels of this sweep (eq. 10, eq. 15, Alg. 1).
-template <int RP>
-__device__ __forceinline__ void fix_body(const FixArgs &args, int blk) {
+template <int RP, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const FixArgs *__restrict__ jobs,
+                                                         const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  FixArgs args;
+  int blk;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    args = jobs[m.x];
+    blk = m.y;
+  } else {
+    args = solo;
+    blk = blockIdx.x;
+  }
+  do {
   const int4 *__restrict__ longs = args.longs;
   const int nlong = args.nlong;
   const float *__restrict__ part = args.part;
@@ -251,7 +265,7 @@ __device__ __forceinline__ void fix_body(const FixArgs &args, int blk) {
       __syncthreads();
     }
     if (slot == 0) st4(M + (long long)L.x * RP + 4 * q, red[0][q]);
-    return;
+    break;
   }
   if (b < nlong + row_blocks) {
     const int r = (b - nlong) * kThreads + tid;
@@ -260,7 +274,7 @@ __device__ __forceinline__ void fix_body(const FixArgs &args, int blk) {
 #pragma unroll
       for (int c = 0; c < RP; c += 4) st4(dst + c, f32x4{0.f, 0.f, 0.f, 0.f});
     }
-    return;
+    break;
   }
   // H, L, diagonal
   __shared__ double l2[kThreads];
@@ -299,21 +313,10 @@ __device__ __forceinline__ void fix_body(const FixArgs &args, int blk) {
     hinfo->halfL = 0.5f * (float)L;
     st->L = L;
   }
-}
-
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs a) {
-  fix_body<RP>(a, blockIdx.x);
-}
-
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_mttkrp_fix_b(const FixArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap, int nb) {
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int4 m = bmap[b];
-    fix_body<RP>(jobs[m.x], m.y);
-    __syncthreads();  // the block's LDS is reused by its next work item
-  }
+  } while (0);
+  if constexpr (!BATCHED) break;
+  __syncthreads();  // the block's LDS is reused by its next work item
+ }
 }
 
 template <template <int> class F, typename... Args>
@@ -350,7 +353,8 @@ struct MtBL {
 template <int RP>
 struct FxL {
   static hipError_t run(const FixArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_mttkrp_fix<RP>, dim3(fix_blocks(a.nlong, a.I)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_mttkrp_fix<RP, false>), dim3(fix_blocks(a.nlong, a.I)), dim3(kThreads), 0, s, a, nullptr,
+                       nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -359,7 +363,8 @@ template <int RP>
 struct FxBL {
   static hipError_t run(const FixArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mttkrp_fix_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    hipLaunchKernelGGL((k_mttkrp_fix<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, FixArgs{}, jobs,
+                       bmap, nb);
     return hipGetLastError();
   }
 };

@@ -198,8 +198,28 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // Block blk (of nblk) of the importance pass of one sweep.
-template <int RP, bool BF>
-__device__ __forceinline__ void importance_body(const ImpArgs &args, int blk, int nblk) {
+// Importance pass of one sweep.  Solo form: block b of the job in `solo`.
+// Job-batched form: a persistent grid loops over the block map's entries
+// (job in `jobs`, block of the job, blocks of the job).  The body sits in the
+// kernel itself (see k_mttkrp).
+template <int RP, bool BF, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const ImpArgs *__restrict__ jobs,
+                                                         const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  ImpArgs args;
+  int blk, nblk;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    args = jobs[m.x];
+    blk = m.y;
+    nblk = m.z;
+  } else {
+    args = solo;
+    blk = blockIdx.x;
+    nblk = gridDim.x;
+  }
+  do {
   const int I = args.I;
   const float *__restrict__ A = args.A;
   const float *__restrict__ M = args.M;
@@ -259,7 +279,7 @@ __device__ __forceinline__ void importance_body(const ImpArgs &args, int blk, in
     s_last = (prev == (unsigned)nblk - 1);
   }
   __syncthreads();
-  if (!s_last) return;
+  if (!s_last) break;
   __threadfence();
   double s = 0.0;
   for (int i = tid; i < nblk; i += kThreads) s += ld_coherent(&ti_part[i]);
@@ -274,23 +294,10 @@ __device__ __forceinline__ void importance_body(const ImpArgs &args, int blk, in
     st->ti_prev = ti;  // becomes ti^{k-1} of the next sweep (eq. 26)
     st->cnt_imp = 0;
   }
-}
-
-template <int RP, bool BF>
-__global__ __launch_bounds__(kThreads) void k_importance(ImpArgs a) {
-  importance_body<RP, BF>(a, blockIdx.x, gridDim.x);
-}
-
-// Job-batched form: a persistent grid loops over the block map's entries
-// (job, block of the job, blocks of the job).
-template <int RP, bool BF>
-__global__ __launch_bounds__(kThreads) void k_importance_b(const ImpArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap, int nb) {
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int4 m = bmap[b];
-    importance_body<RP, BF>(jobs[m.x], m.y, m.z);
-    __syncthreads();  // the block's LDS is reused by its next work item
-  }
+  } while (0);
+  if constexpr (!BATCHED) break;
+  __syncthreads();  // the block's LDS is reused by its next work item
+ }
 }
 
 // Gauss-Seidel / Jacobi update of one row (eq. 11-13), LPR lanes per row:
@@ -352,8 +359,23 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
 }
 
 // Block blk of the selection / update pass of one sweep.
-template <int RP, int UPD, bool DIAG, bool BF>
-__device__ __forceinline__ void select_update_body(const UpdArgs &args, int blk) {
+// Selection / update pass of one sweep (solo or job-batched, as k_importance).
+template <int RP, int UPD, bool DIAG, bool BF, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const UpdArgs *__restrict__ jobs,
+                                                            const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  UpdArgs args;
+  int blk;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    args = jobs[m.x];
+    blk = m.y;
+  } else {
+    args = solo;
+    blk = blockIdx.x;
+  }
+  do {
   const int I = args.I;
   float *__restrict__ A = args.A;
   const float *__restrict__ M = args.M;
@@ -460,21 +482,10 @@ __device__ __forceinline__ void select_update_body(const UpdArgs &args, int blk)
   for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
   gram_tiles<RP, BF>(sA, gpart + (long long)blk * RP * RP, wv, lane);
-}
-
-template <int RP, int UPD, bool DIAG, bool BF>
-__global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs a) {
-  select_update_body<RP, UPD, DIAG, BF>(a, blockIdx.x);
-}
-
-template <int RP, bool BF>
-__global__ __launch_bounds__(kThreads) void k_select_update_b(const UpdArgs *__restrict__ jobs,
-                                                              const int4 *__restrict__ bmap, int nb) {
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int4 m = bmap[b];
-    select_update_body<RP, 0, false, BF>(jobs[m.x], m.y);
-    __syncthreads();  // the block's LDS is reused by its next work item
-  }
+  } while (0);
+  if constexpr (!BATCHED) break;
+  __syncthreads();  // the block's LDS is reused by its next work item
+ }
 }
 
 // Gram partials of an arbitrary factor (initialisation, set_factor).
@@ -536,8 +547,24 @@ constexpr int gram_strips() {
 // block to arrive forms the objective
 //   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
 // and the total selection count.
-template <int RP>
-__device__ __forceinline__ void gram_final_body(const GramArgs &args, int blk, int nblk) {
+template <int RP, bool BATCHED>
+__global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const GramArgs *__restrict__ jobs,
+                                                         const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  GramArgs args;
+  int blk, nblk;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    args = jobs[m.x];
+    blk = m.y;
+    nblk = m.z;
+  } else {
+    args = solo;
+    blk = blockIdx.x;
+    nblk = gridDim.x;
+  }
+  do {
   const int nparts = args.nparts;
   const float *__restrict__ gpart = args.gpart;
   double *__restrict__ mpart = args.mpart;
@@ -612,7 +639,7 @@ __device__ __forceinline__ void gram_final_body(const GramArgs &args, int blk, i
     s_last = (prev == (unsigned)nblk - 1);
   }
   __syncthreads();
-  if (!s_last) return;
+  if (!s_last) break;
   __threadfence();
   double mv = 0.0;
   long long cv = 0;
@@ -629,21 +656,10 @@ __device__ __forceinline__ void gram_final_body(const GramArgs &args, int blk, i
     if (tid == 0) st->nsel = (long long)all;
   }
   if (tid == 0) *counter = 0;
-}
-
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs a) {
-  gram_final_body<RP>(a, blockIdx.x, gridDim.x);
-}
-
-template <int RP>
-__global__ __launch_bounds__(kThreads) void k_gram_final_b(const GramArgs *__restrict__ jobs,
-                                                           const int4 *__restrict__ bmap, int nb) {
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int4 m = bmap[b];
-    gram_final_body<RP>(jobs[m.x], m.y, m.z);
-    __syncthreads();  // the block's LDS is reused by its next work item
-  }
+  } while (0);
+  if constexpr (!BATCHED) break;
+  __syncthreads();  // the block's LDS is reused by its next work item
+ }
 }
 
 __global__ __launch_bounds__(kThreads) void k_init_factor(float *__restrict__ A, int I, int R, int RP,
@@ -840,8 +856,8 @@ struct ImpL {
   static hipError_t run(bool bf, const ImpArgs &a, hipStream_t s) {
     const int nb = importance_blocks(RP, a.I);
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_importance<RP, true>), dim3(nb), dim3(kThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_importance<RP, false>), dim3(nb), dim3(kThreads), 0, s, a);
+    if (bf) hipLaunchKernelGGL((k_importance<RP, true, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr, nullptr, 0);
+    else hipLaunchKernelGGL((k_importance<RP, false, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -850,16 +866,24 @@ template <int RP>
 struct ImpBL {
   static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_importance_b<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
-    else hipLaunchKernelGGL((k_importance_b<RP, false>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    if (bf)
+      hipLaunchKernelGGL((k_importance<RP, true, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
+                         jobs, bmap, nb);
+    else
+      hipLaunchKernelGGL((k_importance<RP, false, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
+                         jobs, bmap, nb);
     return hipGetLastError();
   }
 };
 
 template <int RP, int UPD, bool DIAG>
 hipError_t upd_launch(bool bf, const UpdArgs &a, int nb, hipStream_t s) {
-  if (bf) hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true>), dim3(nb), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false>), dim3(nb), dim3(kThreads), 0, s, a);
+  if (bf)
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr,
+                       nullptr, 0);
+  else
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr,
+                       nullptr, 0);
   return hipGetLastError();
 }
 
@@ -878,8 +902,12 @@ template <int RP>
 struct UpdBL {
   static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_select_update_b<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
-    else hipLaunchKernelGGL((k_select_update_b<RP, false>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    if (bf)
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
+                         UpdArgs{}, jobs, bmap, nb);
+    else
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
+                         UpdArgs{}, jobs, bmap, nb);
     return hipGetLastError();
   }
 };
@@ -898,7 +926,8 @@ struct GpL {
 template <int RP>
 struct GfL {
   static hipError_t run(const GramArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_gram_final<RP>, dim3(gram_final_blocks(RP)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_gram_final<RP, false>), dim3(gram_final_blocks(RP)), dim3(kThreads), 0, s, a, nullptr,
+                       nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -907,7 +936,8 @@ template <int RP>
 struct GfBL {
   static hipError_t run(const GramArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gram_final_b<RP>, dim3(persistent_grid(nb)), dim3(kThreads), 0, s, jobs, bmap, nb);
+    hipLaunchKernelGGL((k_gram_final<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, GramArgs{}, jobs,
+                       bmap, nb);
     return hipGetLastError();
   }
 };

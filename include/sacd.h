@@ -156,6 +156,9 @@ sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t 
 /* Copy factor `mode` out to / in from device memory (I_n x R row-major
  * FP32).  set_factor rejects negative or non-finite values (NUMERIC) and
  * recomputes that mode's Gram matrix.  Synchronises. */
+sacd_status sacd_get_factor(const sacd_model *m, int32_t mode, float *dst);
+sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src);
+
 /* Accuracy of the factorization (Sec. 6, evaluation criteria).
  * sacd_rmse: eq. 30, sqrt(sum (x - x_hat)^2 / n) over n entries, usually
  * held out of the factorised tensor.  idx: device, n x 3 int32 0-based
@@ -168,9 +171,6 @@ sacd_status sacd_run_until(sacd_model *m, double tol, int32_t max_iter, int32_t 
  * (no pair left: 0).  Computed from the factor's Gram matrix.  Synchronises. */
 sacd_status sacd_rmse(sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse);
 sacd_status sacd_pd(const sacd_model *m, int32_t mode, double *pd);
-
-sacd_status sacd_get_factor(const sacd_model *m, int32_t mode, float *dst);
-sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src);
 
 /* Selection state of one mode, for checkpoint / resume: zprev device
  * I_n x R FP32 (importance of the last sweep, Z^{k-1} of Alg. 1), ti_prev
@@ -225,9 +225,6 @@ sacd_status sacd_model_bytes(const sacd_model *m, int64_t *bytes);
 
 void sacd_destroy_model(sacd_model *m);
 
-/* ------------------------------------------------------------------------ */
-/* Misc                                                                      */
-/* ------------------------------------------------------------------------ */
 /* ------------------------------------------------------------------------
  * Serving: many independent jobs resident on one GPU.
  *
@@ -297,6 +294,9 @@ sacd_status sacd_server_release(sacd_server *s, int64_t ticket);
 sacd_status sacd_server_stats(const sacd_server *s, sacd_server_stats_t *out);
 void sacd_server_destroy(sacd_server *s);
 
+/* ------------------------------------------------------------------------ */
+/* Misc                                                                      */
+/* ------------------------------------------------------------------------ */
 const char *sacd_status_string(sacd_status s);
 const char *sacd_last_error(void);
 /* Library version, e.g. "0.1.0". */

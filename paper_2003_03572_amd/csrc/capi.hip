@@ -1288,8 +1288,8 @@ struct BatchGroup {
   ImpArgs *im[3] = {};
   UpdArgs *up[3] = {};
   GramArgs *gf[3] = {};
-  int4 *bm_mt[3] = {}, *bm_fx[3] = {}, *bm_im[3] = {}, *bm_gf[3] = {};
-  int nb_mt[3] = {}, nb_fx[3] = {}, nb_im[3] = {}, nb_gf[3] = {};
+  int4 *bm_mt[3] = {}, *bm_fx[3] = {}, *bm_im[3] = {}, *bm_up[3] = {}, *bm_gf[3] = {};
+  int nb_mt[3] = {}, nb_fx[3] = {}, nb_im[3] = {}, nb_up[3] = {}, nb_gf[3] = {};
 };
 
 }  // namespace
@@ -1408,18 +1408,19 @@ sacd_status rebuild_tables(sacd_server *S) {
   size_t total = al256(sizeof(ModeState *) * (J + 1)) + al256(sizeof(double) * (J + 1));
   for (BatchGroup &g : S->groups)
     for (int n = 0; n < 3; ++n) {
-      g.nb_mt[n] = g.nb_fx[n] = g.nb_im[n] = g.nb_gf[n] = 0;
+      g.nb_mt[n] = g.nb_fx[n] = g.nb_im[n] = g.nb_up[n] = g.nb_gf[n] = 0;
       for (int i : g.jobs) {
         const sacd_model *m = S->active[i].m;
         const int I = (int)m->t->dims[n];
         g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
         g.nb_fx[n] += fix_blocks(m->plan[n].nlong, I);
         g.nb_im[n] += importance_blocks(g.RP, I);
+        g.nb_up[n] += update_blocks(g.RP, I);
         g.nb_gf[n] += gram_final_blocks(g.RP);
       }
       const size_t nj = g.jobs.size();
       total += table_bytes<MttkrpArgs>(nj, g.nb_mt[n]) + table_bytes<FixArgs>(nj, g.nb_fx[n]) +
-               table_bytes<ImpArgs>(nj, g.nb_im[n]) + al256(sizeof(UpdArgs) * nj) +
+               table_bytes<ImpArgs>(nj, g.nb_im[n]) + table_bytes<UpdArgs>(nj, g.nb_up[n]) +
                table_bytes<GramArgs>(nj, g.nb_gf[n]);
     }
   if (total > S->h_stage_bytes) {
@@ -1453,7 +1454,8 @@ sacd_status rebuild_tables(sacd_server *S) {
       if (which == 0) nb = mttkrp_blocks(g.RP, m->plan[n].nunits);
       else if (which == 1) nb = fix_blocks(m->plan[n].nlong, I);
       else if (which == 2) nb = importance_blocks(g.RP, I);
-      else nb = gram_final_blocks(g.RP);
+      else if (which == 3) nb = gram_final_blocks(g.RP);
+      else nb = update_blocks(g.RP, I);
       for (int q = 0; q < nb; ++q) bm[b++] = make_int4((int)k, q, nb, 0);
     }
   };
@@ -1481,6 +1483,9 @@ sacd_status rebuild_tables(sacd_server *S) {
       carve(sizeof(UpdArgs) * nj, &h, &d);
       for (size_t k = 0; k < nj; ++k) ((UpdArgs *)h)[k] = upd_args(S->active[g.jobs[k]].m, n);
       g.up[n] = (UpdArgs *)d;
+      carve(sizeof(int4) * g.nb_up[n], &h, &d);
+      fill_map((int4 *)h, g, n, 4);
+      g.bm_up[n] = (int4 *)d;
       carve(sizeof(GramArgs) * nj, &h, &d);
       for (size_t k = 0; k < nj; ++k) ((GramArgs *)h)[k] = gram_args(S->active[g.jobs[k]].m, n, true);
       g.gf[n] = (GramArgs *)d;
@@ -1515,7 +1520,7 @@ sacd_status enqueue_batched_iteration(sacd_server *S) {
       HIP_TRY(launch_mttkrp_b(g.RP, g.mt[n], g.bm_mt[n], g.nb_mt[n], s));
       HIP_TRY(launch_mttkrp_fix_b(g.RP, g.fx[n], g.bm_fx[n], g.nb_fx[n], s));
       HIP_TRY(launch_importance_b(g.RP, bf, g.im[n], g.bm_im[n], g.nb_im[n], s));
-      HIP_TRY(launch_select_update_b(g.RP, bf, g.up[n], g.bm_im[n], g.nb_im[n], s));
+      HIP_TRY(launch_select_update_b(g.RP, bf, g.up[n], g.bm_up[n], g.nb_up[n], s));
       HIP_TRY(launch_gram_final_b(g.RP, g.gf[n], g.bm_gf[n], g.nb_gf[n], s));
     }
     HIP_TRY(hipEventRecord(S->ev_join[gi], s));

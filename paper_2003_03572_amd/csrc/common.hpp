@@ -196,7 +196,7 @@ struct GramArgs {
   unsigned *counter;    // arrival counter (zero between launches)
   ModeState *st;
 };
-int rows_per_block(int RP);
+int rows_per_block(int RP);  // rows per block of the update pass (Gram partials per block)
 int importance_blocks(int RP, int I);
 int update_blocks(int RP, int I);
 int gram_final_blocks(int RP);

@@ -23,13 +23,26 @@ namespace sacd {
 
 namespace {
 
+// Rows per block: the importance pass uses RB = 256 / 128 / 64 at
+// RP <= 32 / 64 / 128; the update pass uses 64 rows at RP = 64, so that four
+// lanes share each row's Gauss-Seidel chain (measured faster; at RP <= 32 the
+// larger Gram reduction of smaller blocks costs more than it saves).
 template <int RP>
+constexpr int imp_rows() {
+  return RP <= 32 ? 256 : (RP == 64 ? 128 : 64);
+}
+template <int RP>
+constexpr int upd_rows() {
+  return RP <= 32 ? 256 : 64;
+}
+
+template <int RP, int RB_>
 struct UCfg {
-  static constexpr int RB = RP <= 32 ? 256 : (RP == 64 ? 128 : 64);  // rows per block
-  static constexpr int STR = RP + 1;                                   // LDS row stride (floats)
-  static constexpr int TC = RP / 16;                                   // 16-column tiles
-  static constexpr int NT = (RB / 16) * TC;                            // 16x16 tiles per block
-  static constexpr int NTW = NT / 4;                                   // tiles per wave
+  static constexpr int RB = RB_;        // rows per block
+  static constexpr int STR = RP + 1;    // LDS row stride (floats)
+  static constexpr int TC = RP / 16;    // 16-column tiles
+  static constexpr int NT = (RB / 16) * TC;  // 16x16 tiles per block
+  static constexpr int NTW = NT / 4;    // tiles per wave
 };
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
@@ -62,9 +75,9 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
   return *p;
 }
 
-template <int RP>
+template <int RP, int RB>
 __device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, RB>;
   // all loads of the tile are issued before the first LDS store waits on one
   constexpr int N4 = Cf::RB * RP / 4 / kThreads;  // float4 per thread
   f32x4 v[N4];
@@ -111,9 +124,9 @@ __device__ __forceinline__ void load_h(float *sH, const float *__restrict__ H) {
 
 // C tile (16 x 16) of the block's rows times H: rows tr*16.., columns tc*16..
 // BF: operands rounded to BF16, FP32 accumulation.
-template <int RP, bool BF>
+template <int RP, int RB, bool BF>
 __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int tr, int tc, int lane) {
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, RB>;
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
   if constexpr (BF) {
 #pragma unroll
@@ -142,9 +155,9 @@ __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int t
 // sA^T sA), written to gp.  Four independent MFMA accumulation chains over
 // interleaved row groups, added in a fixed order at the end.  BF: operands
 // rounded to BF16, FP32 accumulation.
-template <int RP, bool BF>
+template <int RP, int RB, bool BF>
 __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, int lane) {
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, RB>;
   constexpr int n16 = RP / 16;
   for (int t = wv; t < n16 * n16; t += 4) {
     const int ti_ = t / n16, tj = t % n16;
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
   const HInfo *__restrict__ hi = args.hi;
   double *__restrict__ ti_part = args.ti_part;
   ModeState *st = args.st;
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, imp_rows<RP>()>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
   __shared__ double red[kThreads];
@@ -248,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
       mv[ti][v] = (q < I) ? M[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP>(sA, A, row0, I);
+  load_rows<RP, Cf::RB>(sA, A, row0, I);
   load_h<RP>(sH, H);
   __syncthreads();
   const float halfL = hi->halfL;
@@ -257,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP, BF>(sA, sH, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   double *__restrict__ inner_part = args.inner_part;
   int *__restrict__ cnt_part = args.cnt_part;
   uint8_t *__restrict__ selmask = args.selmask;
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, upd_rows<RP>()>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
       zpreg[ti][v] = (q < I) ? Z[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP>(sA, A, row0, I);
+  load_rows<RP, Cf::RB>(sA, A, row0, I);
   load_h<RP>(sH, H);
   for (int c = tid; c < RP; c += kThreads) sCnt[c] = 0;
   __syncthreads();
@@ -421,7 +434,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + 4 * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
-    const f32x4 ah = tile_AH<RP, BF>(sA, sH, tr, tc, lane);
+    const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   if (tid == 0) inner_part[blk] = bs;
   for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
-  gram_tiles<RP, BF>(sA, gpart + (long long)blk * RP * RP, wv, lane);
+  gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blk * RP * RP, wv, lane);
   } while (0);
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
@@ -492,12 +505,12 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
 template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *__restrict__ A,
                                                            float *__restrict__ gpart) {
-  using Cf = UCfg<RP>;
+  using Cf = UCfg<RP, upd_rows<RP>()>;
   __shared__ float sA[Cf::RB * Cf::STR];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  load_rows<RP>(sA, A, blockIdx.x * Cf::RB, I);
+  load_rows<RP, Cf::RB>(sA, A, blockIdx.x * Cf::RB, I);
   __syncthreads();
-  gram_tiles<RP, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
+  gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
 // Sum of the values base[p * stride], p = s, s + 16, s + 32, ... < n, in
@@ -817,10 +830,10 @@ inline int grid_for(long long n, int per_block = kThreads * 4, int cap = 65535 *
 
 int rows_per_block(int RP) {
   switch (RP) {
-    case 16: return UCfg<16>::RB;
-    case 32: return UCfg<32>::RB;
-    case 64: return UCfg<64>::RB;
-    case 128: return UCfg<128>::RB;
+    case 16: return upd_rows<16>();
+    case 32: return upd_rows<32>();
+    case 64: return upd_rows<64>();
+    case 128: return upd_rows<128>();
     default: return 0;
   }
 }
@@ -832,8 +845,11 @@ hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long
   return hipGetLastError();
 }
 
-int importance_blocks(int RP, int I) { return (I + rows_per_block(RP) - 1) / rows_per_block(RP); }
-int update_blocks(int RP, int I) { return importance_blocks(RP, I); }
+int importance_blocks(int RP, int I) {
+  const int rb = RP <= 16 ? imp_rows<16>() : RP <= 32 ? imp_rows<32>() : RP <= 64 ? imp_rows<64>() : imp_rows<128>();
+  return (I + rb - 1) / rb;
+}
+int update_blocks(int RP, int I) { return (I + rows_per_block(RP) - 1) / rows_per_block(RP); }
 int gram_final_blocks(int RP) { return 16 * (RP / 16) * (RP / 16 + 1) / 2 + RP / 16 + 1; }
 int gram_model_parts(int RP) { return 16 * (RP / 16) * (RP / 16 + 1) / 2; }
 

@@ -74,7 +74,7 @@ def lib():
         L.ora_model_set_tie_tol.restype = None
         L.ora_sweep.argtypes = [p, i32]
         L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p, p]
-        L.ora_sweep_alternatives.argtypes = [p, i32, p, p, p, p, p, p]
+        L.ora_row_outcome.argtypes = [p, i32, i64, p, p]
         L.ora_objective.argtypes = [p]
         L.ora_objective.restype = dbl
         L.ora_fit.argtypes = [p, p, p]
@@ -229,31 +229,12 @@ class Model:
                     L=sc[0], ti=sc[1], flip=bool(sc[2]), tie_global=bool(sc[3]), f=sc[4],
                     nsel=int(sc[5]), inner=sc[6], model=sc[7])
 
-    def alternatives(self, mode: int) -> dict:
-        """Valid outcomes of the rows holding tie elements in the last sweep
-        of `mode`: {row: (tie_cols, outcomes)} with outcomes an array of
-        shape (2^t, R); outcome c takes decision (c >> j) & 1 for tie_cols[j].
-        Rows with more than 6 tie elements map to (tie_cols, None)."""
-        nr, ne = C.c_int64(), C.c_int64()
-        _check(lib().ora_sweep_alternatives(self._h, mode, C.byref(nr), C.byref(ne), None, None,
-                                            None, None), "alternatives")
-        nr, ne = nr.value, ne.value
-        if nr == 0:
-            return {}
-        rows = np.empty(nr, np.int64)
-        ntie = np.empty(nr, np.int32)
-        cols = np.empty((nr, 6), np.int32)
-        vals = np.empty((max(ne, 1), self.R), np.float64)
-        _check(lib().ora_sweep_alternatives(self._h, mode, None, None, _ptr(rows), _ptr(ntie),
-                                            _ptr(cols), _ptr(vals)), "alternatives")
-        out, off = {}, 0
-        for k in range(nr):
-            t = int(ntie[k])
-            if t < 0:
-                out[int(rows[k])] = (None, None)
-                continue
-            out[int(rows[k])] = (cols[k, :t].copy(), vals[off:off + (1 << t)].copy())
-            off += 1 << t
+    def row_outcome(self, mode: int, q: int, sel: np.ndarray) -> np.ndarray:
+        """Row q of the last sweep of `mode` updated under decisions `sel`."""
+        sel = np.ascontiguousarray(sel, np.uint8).reshape(-1)
+        assert sel.shape[0] == self.R
+        out = np.empty(self.R, np.float64)
+        _check(lib().ora_row_outcome(self._h, mode, int(q), _ptr(sel), _ptr(out)), "row_outcome")
         return out
 
     def objective(self) -> float:

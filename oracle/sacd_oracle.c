@@ -255,15 +255,8 @@ struct ora_model {
   uint8_t *sel[3], *tie[3];
   double *H[3];
   double info[3][8];
-  /* valid outcomes of the rows holding tie elements (last sweep per mode) */
-  int64_t alt_nrows[3], alt_nent[3];
-  int64_t *alt_row[3];
-  int32_t *alt_ntie[3];
-  int32_t *alt_cols[3]; /* alt_nrows x ORA_MAX_TIE */
-  double *alt_vals[3];  /* alt_nent x R */
+  double *A_prev[3]; /* factor before the last sweep of the mode */
 };
-
-#define ORA_MAX_TIE 6
 
 void ora_model_destroy(ora_model *m) {
   if (!m) return;
@@ -271,7 +264,7 @@ void ora_model_destroy(ora_model *m) {
     free(m->A[n]); free(m->G[n]); free(m->zprev[n]);
     free(m->M[n]); free(m->G0[n]); free(m->z[n]);
     free(m->sel[n]); free(m->tie[n]); free(m->H[n]);
-    free(m->alt_row[n]); free(m->alt_ntie[n]); free(m->alt_cols[n]); free(m->alt_vals[n]);
+    free(m->A_prev[n]);
   }
   free(m);
 }
@@ -304,8 +297,9 @@ int ora_model_create(const ora_tensor *t, int R, uint64_t seed, int update_rule,
     m->sel[n] = (uint8_t *)calloc(IR, 1);
     m->tie[n] = (uint8_t *)calloc(IR, 1);
     m->H[n] = (double *)calloc((size_t)R * R, sizeof(double));
+    m->A_prev[n] = (double *)calloc(IR, sizeof(double));
     if (!m->A[n] || !m->G[n] || !m->zprev[n] || !m->M[n] || !m->G0[n] ||
-        !m->z[n] || !m->sel[n] || !m->tie[n] || !m->H[n]) {
+        !m->z[n] || !m->sel[n] || !m->tie[n] || !m->H[n] || !m->A_prev[n]) {
       free(raw); ora_model_destroy(m); return ORA_ENOMEM;
     }
     for (size_t i = 0; i < IR; ++i)
@@ -532,8 +526,16 @@ int ora_sweep(ora_model *m, int mode) {
       const double zz = ora_importance(G0[e], d, L);
       z[e] = (float)zz; /* the decision is taken on the FP32 value */
       ti += (double)z[e];
-      /* magnitude of the terms z is computed from: the width of the tie band */
-      scale[e] = fabs(d) * (fabs(M[e]) + ah_abs) + 0.5 * L * d * d;
+      /* Width of the tie band: how far z moves when G0 carries a rounding
+       * error relative to the terms it is formed from, |M| + sum |A H|
+       * (eq. 14).  z = -g d - (L/2) d^2 (eq. 20); with a clipped step
+       * (d = -a, eq. 12) dz/dg = -d, with an interior one (d = -g/h, eq. 11)
+       * dz/dg = -d + g/h + L d/h, so |dz/dg| <= |d| + (|g| + L|d|)/h.  The
+       * last term covers the rounding of (L/2) d^2 itself. */
+      const double h = H[r * R + r];
+      const int interior = h > 0.0 && A[e] - G0[e] / h > 0.0;
+      const double dzdg = fabs(d) + (interior ? (fabs(G0[e]) + L * fabs(d)) / h : 0.0);
+      scale[e] = dzdg * (fabs(M[e]) + ah_abs) + 0.5 * L * d * d;
       scale_sum += scale[e];
       /* a zero entry whose gradient is within rounding of zero */
       tie[e] = (A[e] == 0.0 && H[r * R + r] > 0.0 &&
@@ -561,57 +563,8 @@ int ora_sweep(ora_model *m, int mode) {
   memcpy(zprev, z, (size_t)I * R * sizeof(float));
   m->ti_prev[mode] = ti;
 
-  /* Valid outcomes of rows with tie elements: a decision inside the tie
-   * band may go either way, and rows are independent in step 9, so each such
-   * row's outcome is computed for every combination of its tie decisions. */
-  free(m->alt_row[mode]); free(m->alt_ntie[mode]); free(m->alt_cols[mode]); free(m->alt_vals[mode]);
-  m->alt_row[mode] = NULL; m->alt_ntie[mode] = NULL; m->alt_cols[mode] = NULL; m->alt_vals[mode] = NULL;
-  int64_t nrows = 0, nent = 0;
-  for (int64_t q = 0; q < I; ++q) {
-    int t = 0;
-    for (int r = 0; r < R; ++r) t += tie[q * R + r];
-    if (t > 0) {
-      ++nrows;
-      if (t <= ORA_MAX_TIE) nent += (int64_t)1 << t;
-    }
-  }
-  m->alt_nrows[mode] = nrows;
-  m->alt_nent[mode] = nent;
-  if (nrows > 0) {
-    m->alt_row[mode] = (int64_t *)malloc((size_t)nrows * sizeof(int64_t));
-    m->alt_ntie[mode] = (int32_t *)malloc((size_t)nrows * sizeof(int32_t));
-    m->alt_cols[mode] = (int32_t *)malloc((size_t)nrows * ORA_MAX_TIE * sizeof(int32_t));
-    m->alt_vals[mode] = (double *)malloc((size_t)(nent > 0 ? nent : 1) * R * sizeof(double));
-    uint8_t *sel2 = (uint8_t *)malloc((size_t)R);
-    if (!m->alt_row[mode] || !m->alt_ntie[mode] || !m->alt_cols[mode] || !m->alt_vals[mode] || !sel2) {
-      free(sel2); free(delta); free(scale); return ORA_ENOMEM;
-    }
-    int64_t k_row = 0, k_ent = 0;
-    for (int64_t q = 0; q < I; ++q) {
-      int t = 0;
-      int32_t *cols = m->alt_cols[mode] + k_row * ORA_MAX_TIE;
-      for (int r = 0; r < R; ++r)
-        if (tie[q * R + r]) {
-          if (t < ORA_MAX_TIE) cols[t] = r;
-          ++t;
-        }
-      if (t == 0) continue;
-      m->alt_row[mode][k_row] = q;
-      m->alt_ntie[mode][k_row] = (t <= ORA_MAX_TIE) ? t : -t;
-      if (t <= ORA_MAX_TIE) {
-        for (int64_t c = 0; c < ((int64_t)1 << t); ++c) {
-          double *out = m->alt_vals[mode] + k_ent * R;
-          memcpy(sel2, sel + q * R, (size_t)R);
-          for (int j = 0; j < t; ++j) sel2[cols[j]] = (uint8_t)((c >> j) & 1);
-          memcpy(out, A + q * R, (size_t)R * sizeof(double));
-          update_row(out, sel2, M + q * R, delta + q * R, H, R, m->update_rule);
-          ++k_ent;
-        }
-      }
-      ++k_row;
-    }
-    free(sel2);
-  }
+  /* the state before the update, for ora_row_outcome */
+  memcpy(m->A_prev[mode], A, (size_t)I * R * sizeof(double));
 
   /* 9 */
   for (int64_t q = 0; q < I; ++q)
@@ -640,17 +593,22 @@ int ora_sweep(ora_model *m, int mode) {
   return ORA_OK;
 }
 
-int ora_sweep_alternatives(const ora_model *m, int mode, int64_t *n_rows, int64_t *n_entries,
-                           int64_t *rows, int32_t *ntie, int32_t *cols, double *vals) {
-  if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
-  if (n_rows) *n_rows = m->alt_nrows[mode];
-  if (n_entries) *n_entries = m->alt_nent[mode];
-  const int64_t nr = m->alt_nrows[mode], ne = m->alt_nent[mode];
-  if (nr == 0) return ORA_OK;
-  if (rows) memcpy(rows, m->alt_row[mode], (size_t)nr * sizeof(int64_t));
-  if (ntie) memcpy(ntie, m->alt_ntie[mode], (size_t)nr * sizeof(int32_t));
-  if (cols) memcpy(cols, m->alt_cols[mode], (size_t)nr * ORA_MAX_TIE * sizeof(int32_t));
-  if (vals && ne > 0) memcpy(vals, m->alt_vals[mode], (size_t)ne * m->R * sizeof(double));
+/* Step 9 for one row of the last sweep of `mode` under the given decisions:
+ * a decision inside the tie band may go either way, and rows are independent
+ * in step 9, so this is the oracle's row for any valid set of decisions. */
+int ora_row_outcome(const ora_model *m, int mode, int64_t q, const uint8_t *sel, double *out) {
+  if (!m || mode < 0 || mode > 2 || !sel || !out) return ORA_EINVAL;
+  const int R = m->R;
+  if (q < 0 || q >= m->t->dims[mode]) return ORA_ERANGE;
+  const double *a_prev = m->A_prev[mode] + q * R;
+  const double *G0 = m->G0[mode] + q * R;
+  const double *H = m->H[mode];
+  double *delta = (double *)malloc((size_t)R * sizeof(double));
+  if (!delta) return ORA_ENOMEM;
+  for (int r = 0; r < R; ++r) delta[r] = ora_cd_delta(a_prev[r], G0[r], H[r * R + r]);
+  memcpy(out, a_prev, (size_t)R * sizeof(double));
+  update_row(out, sel, m->M[mode] + q * R, delta, H, R, m->update_rule);
+  free(delta);
   return ORA_OK;
 }
 

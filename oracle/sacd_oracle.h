@@ -73,7 +73,10 @@ int ora_model_set_state(ora_model *m, int mode, const float *zprev,
 /* force_flip: -1 = decide from ti (normal), 0 / 1 = force the eq. 27 branch
  * off / on (used to enumerate both outcomes at a total-importance tie). */
 void ora_model_force_flip(ora_model *m, int force_flip);
-/* Relative width of the tie band used for the diagnostics (default 1e-6). */
+/* Relative width of the tie band used for the diagnostics (default 1e-6):
+ * an element is a tie when its selection margin is at most tau times the
+ * change of z that a relative error tau in the terms of its gradient would
+ * cause (see ora_sweep). */
 void ora_model_set_tie_tol(ora_model *m, double tau);
 
 /* One SaCD sweep of mode n (Alg. 1 body for one factor matrix). */
@@ -87,14 +90,10 @@ int ora_sweep_info(const ora_model *m, int mode, double *M, double *G0,
                    float *z, uint8_t *sel, uint8_t *tie, double *H,
                    double *scalars /* [L, ti, flip, tie_global, f, nsel, inner, model] */);
 
-/* Valid outcomes of the last sweep's rows that hold tie elements.  For row
- * rows[k] with ntie[k] = t tie elements at columns cols[k*6 .. k*6+t-1]
- * (t <= 6; a negative ntie means more than 6, outcomes not enumerated), the
- * 2^t rows of vals (R values each, consecutive over k) are the updated row
- * for decision combination c = 0 .. 2^t - 1 (bit j: decision of tie j).
- * Call first with NULL arrays to get n_rows / n_entries. */
-int ora_sweep_alternatives(const ora_model *m, int mode, int64_t *n_rows, int64_t *n_entries,
-                           int64_t *rows, int32_t *ntie, int32_t *cols, double *vals);
+/* The update (step 9 of ora_sweep) of row q of the last sweep of `mode`
+ * under the decisions sel (R bytes, 1 = selected), from the state before that
+ * sweep: the oracle's row for any valid choice at tie elements. */
+int ora_row_outcome(const ora_model *m, int mode, int64_t q, const uint8_t *sel, double *out);
 
 /* Objective eq. 6 (full-tensor least squares) and fit 1 - sqrt(f)/||X||. */
 double ora_objective(const ora_model *m);

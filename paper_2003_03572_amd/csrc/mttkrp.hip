@@ -7,8 +7,8 @@
 // one lane group (LPN lanes, W columns each) from start to end, so the inner
 // loop never meets a slice boundary.  Units are ordered longest first, so the
 // groups of a wave run for about the same number of entries.  Entries are
-// sorted by (i_n, i_a, i_b): a run sharing (i_n, i_a) -- a fibre -- multiplies
-// its A_a row once, after the fibre sum  sum x * A_b[i_b, :]  is formed.
+// sorted by (i_n, i_a, i_b): a run sharing (i_n, i_a) -- a fibre -- gathers
+// its A_a row once (A_b rows are gathered per entry).
 // A slice held by one unit is written directly; the units of a longer slice
 // write partial sums that the fix-up kernel adds in a fixed tree order, one
 // block per such slice.  The fix-up also zeroes empty slices.  No atomics:

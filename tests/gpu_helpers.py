@@ -9,8 +9,8 @@ Comparison rules (parity contract):
     from); a global tie of the total importance is resolved by re-running the
     oracle with the branch the GPU took;
   * factors: rows with no selected element are bit-identical; a row holding
-    tie elements must match the oracle's outcome for the GPU's decisions on
-    those elements (the oracle enumerates every combination); otherwise
+    tie elements must match the oracle's update of that row under the GPU's
+    decisions on those elements; otherwise
     |A_gpu - A_oracle| <= 1e-5 * s_q, where s_q is the largest magnitude of
     the terms of the row's Newton steps, (|M_qr| + sum_s |A_qs| H_sr) / H_rr:
     the step is the small difference of FP32 terms of that size;
@@ -79,13 +79,9 @@ def compare_sweep(gm, om, mode, A_old, where=""):
     # the valid outcome that matches the GPU's decisions on tie elements
     A_o = om.factor(mode)
     A_valid = A_o.copy()
-    alts = om.alternatives(mode)
     changed_rows = np.nonzero((sel_g != sel_o).any(axis=1))[0]
     for q in changed_rows:
-        cols, outs = alts[int(q)]
-        assert cols is not None, f"{where} row {q}: too many tie elements to enumerate"
-        c = sum(int(sel_g[q, col]) << j for j, col in enumerate(cols))
-        A_valid[q] = outs[c]
+        A_valid[q] = om.row_outcome(mode, int(q), sel_g[q].astype(np.uint8))
 
     A_g = to_np(gm.factor(mode)).astype(np.float64)
     H = info["H"]

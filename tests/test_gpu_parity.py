@@ -325,3 +325,41 @@ def test_hot_slice_spanning_many_chunks(sacd, oracle_mod):
         for n_ in range(3):
             load_oracle_state_into_gpu(gm, om)
             step_parity(gm, om, n_, where=f"hot R={R}")
+
+
+def test_rank_one_and_jacobi_split_rows(sacd, oracle_mod):
+    """R = 1 (one real column, fifteen padded ones) and the Jacobi rule on the
+    split-lane row update (R = 64: four lanes per row)."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    T_o = oracle_mod.Tensor(dims, idx, vals)
+    for R, upd in ((1, sacd.UPDATE_GS), (64, sacd.UPDATE_JACOBI), (128, sacd.UPDATE_JACOBI)):
+        gm = sacd.Model(T_g, R, seed=5, update=upd)
+        gm.set_diagnostics(True)
+        om = oracle_mod.Model(T_o, R, seed=5, update=upd)
+        for it in range(3):
+            for n in range(3):
+                load_oracle_state_into_gpu(gm, om)
+                step_parity(gm, om, n, where=f"R={R} upd={upd} iter {it}")
+
+
+@pytest.mark.slow
+def test_step_parity_full_size_zipf(sacd, oracle_mod):
+    """The bench tensor at its full size (1e7 entries, R = 32): after two
+    iterations run as the bench runs them (graph replay), one sweep of every
+    mode on both sides from the same state, compared element by element."""
+    w = gen.ZIPF_UIT
+    dims, idx, vals = gen.make(w)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    gm = sacd.Model(T_g, w.rank, seed=w.init_seed)
+    gm.iterate(2)
+    T_o = oracle_mod.Tensor(dims, idx, vals)
+    om = oracle_mod.Model(T_o, w.rank, seed=w.init_seed)
+    gm.set_diagnostics(True)
+    for n in range(3):
+        for k_ in range(3):  # the GPU's state, FP32 values, into the oracle
+            om.set_factor(k_, to_np(gm.factor(k_)).astype(np.float64))
+            zp, ti, k = gm.state(k_)
+            om.set_state(k_, to_np(zp), ti, k)
+        r = step_parity(gm, om, n, where=f"full size mode {n}")
+        print(f"mode {n}: {r}")

@@ -423,3 +423,21 @@ def test_pattern_distinctiveness_closed_forms(oracle_mod):
     assert math.isclose(m.pd(2), 0.5, rel_tol=1e-14)
     m.set_factor(2, np.zeros((4, 3)))
     assert m.pd(2) == 0.0
+
+
+def test_row_outcome_reproduces_the_sweep(oracle_mod):
+    """ora_row_outcome under the sweep's own decisions is the swept row; with
+    no element selected the row keeps its previous value."""
+    dims, idx, vals = _tiny(4, dims=(6, 5, 4), nnz=40)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    for upd in (oracle_mod.UPDATE_GS, oracle_mod.UPDATE_JACOBI):
+        m = oracle_mod.Model(T, 3, seed=4, update=upd)
+        m.sweep(0)
+        m.sweep(1)
+        A_prev = m.factor(1)
+        m.sweep(1)
+        info = m.info(1)
+        A = m.factor(1)
+        for q in range(dims[1]):
+            np.testing.assert_array_equal(m.row_outcome(1, q, info["sel"][q]), A[q])
+            np.testing.assert_array_equal(m.row_outcome(1, q, np.zeros(3, np.uint8)), A_prev[q])

@@ -363,3 +363,25 @@ def test_step_parity_full_size_zipf(sacd, oracle_mod):
             om.set_state(k_, to_np(zp), ti, k)
         r = step_parity(gm, om, n, where=f"full size mode {n}")
         print(f"mode {n}: {r}")
+
+
+@pytest.mark.slow
+def test_step_parity_full_size_uniform_r128(sacd, oracle_mod):
+    """The 2e7-entry uniform tensor at R = 128, full size: after one
+    iteration (graph replay), one sweep of modes 0 and 2 on both sides from
+    the GPU's state."""
+    w = gen.UNIFORM_20M_R128
+    dims, idx, vals = gen.make(w)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    gm = sacd.Model(T_g, w.rank, seed=w.init_seed)
+    gm.iterate(1)
+    T_o = oracle_mod.Tensor(dims, idx, vals)
+    om = oracle_mod.Model(T_o, w.rank, seed=w.init_seed)
+    gm.set_diagnostics(True)
+    for n in (0, 2):
+        for k_ in range(3):
+            om.set_factor(k_, to_np(gm.factor(k_)).astype(np.float64))
+            zp, ti, k = gm.state(k_)
+            om.set_state(k_, to_np(zp), ti, k)
+        r = step_parity(gm, om, n, where=f"full size R=128 mode {n}")
+        print(f"mode {n}: {r}", flush=True)

@@ -618,9 +618,11 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
   const long long u = hcnt;
   t->nnz = u;
   for (int m = 0; m < 3; ++m) {
-    TMP_TRY(t->mem.get_t(u > 0 ? u : 1, &t->keys[m]));
-    TMP_TRY(t->mem.get_t(u > 0 ? u : 1, &t->vals[m]));
+    TMP_TRY(t->mem.get_t((size_t)u + kKeySlack, &t->keys[m]));
+    TMP_TRY(t->mem.get_t((size_t)u + kKeySlack, &t->vals[m]));
     TMP_TRY(t->mem.get_t((size_t)dims[m] + 1, &t->ptr[m]));
+    TMP_HIP(hipMemsetAsync(t->keys[m] + u, 0, sizeof(unsigned long long) * kKeySlack, s));
+    TMP_HIP(hipMemsetAsync(t->vals[m] + u, 0, sizeof(float) * kKeySlack, s));
   }
   if (u > 0) {
     TMP_HIP(hipMemcpyAsync(t->keys[0], kd, sizeof(unsigned long long) * u, hipMemcpyDeviceToDevice, s));
@@ -1182,7 +1184,7 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int
     maxI = std::max(maxI, I);
     const int64_t units = nnz / kSegment + I + 2;
     maxunits = std::max(maxunits, units);
-    ten += al256(8 * nnz) + al256(4 * nnz) + al256(4 * (I + 1)) + al256(16 * units) + al256(16 * (I + 2));
+    ten += al256(8 * (nnz + kKeySlack)) + al256(4 * (nnz + kKeySlack)) + al256(4 * (I + 1)) + al256(16 * units) + al256(16 * (I + 2));
     mod += 3 * al256(4 * I * RP) + al256(I * RP) + 2 * al256(4 * RP * RP) + al256(8 * RP * RP) +
            al256(sizeof(HInfo)) + al256(8 * RP);
   }

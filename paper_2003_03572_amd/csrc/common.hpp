@@ -118,6 +118,9 @@ hipError_t launch_export_coo(const unsigned long long *keys, const float *vals, 
 // Static work plan of one mode (built once per tensor from the slice
 // pointers): every slice cut into segments of at most kSegment entries.
 constexpr int kSegment = 256;
+// Zeroed entries kept after the end of every mode's key and value arrays, so
+// that the MTTKRP can load the keys of a next batch without a bounds test.
+constexpr int kKeySlack = 16;
 constexpr int kGatherBuckets = 64;  // i_a ranges that order the full-length segments
 struct MttkrpPlan {
   long long nnz;

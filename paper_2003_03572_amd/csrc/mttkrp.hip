@@ -26,11 +26,8 @@ namespace {
 #ifndef SACD_MT_U
 #define SACD_MT_U 8
 #endif
-// 1: per fibre, sum x * A_b rows and multiply by the A_a row once; 0: keep the
-// fibre's A_a row and add x * (A_a .* A_b) per entry.
-#ifndef SACD_MT_FIBRE
-#define SACD_MT_FIBRE 0
-#endif
+
+static_assert(SACD_MT_U <= kKeySlack, "the next-batch key loads may run U - 1 entries past the last entry");
 
 template <int RP>
 struct MCfg {
@@ -89,88 +86,104 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
   const int len = unit.z;
 
   f32x4 acc[NV], arow[NV];
-#if SACD_MT_FIBRE
-  f32x4 facc[NV];
-#endif
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
     arow[j] = acc[j];
-#if SACD_MT_FIBRE
-    facc[j] = acc[j];
-#endif
   }
-  unsigned long long fib = ~0ull;  // (i_n, i_a) of the current fibre
-  // software pipeline: the keys of batch k + 1 are loaded while batch k's
-  // rows are gathered, so gather addresses never wait on a load issued
-  // after another gather (loads complete in order)
+  // A unit lies in one slice, so its fibres are told apart by i_a alone.
+  // Both row indices are decoded in 32 bits: i_b is the low field and i_a is
+  // read across the word boundary by a funnel shift (sh_a < 32, and both
+  // fields are narrower than 32 bits).
+  const unsigned mb = (unsigned)lay.mask_b, ma = (unsigned)lay.mask_a, sha = (unsigned)lay.sh_a;
+  const char *__restrict__ Ab_l = (const char *)(Ab + 4 * sub);
+  const char *__restrict__ Aa_l = (const char *)(Aa + 4 * sub);
+  constexpr int kRowShift = RP == 16 ? 6 : (RP == 32 ? 7 : (RP == 64 ? 8 : 9));  // log2 of a row's bytes
+  static_assert((1 << kRowShift) == 4 * RP, "row size");
+  unsigned fa = ~0u;  // i_a of the current fibre (never a valid index)
+  // Software pipeline: the keys of batch k + 1 are loaded while batch k's
+  // rows are gathered.  The key arrays carry kKeySlack zeroed entries past
+  // their end, so these loads need no bounds test and merge into wide loads;
+  // keys past the unit are never used.
   unsigned long long kn[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) kn[u] = (u < len) ? keys[p0 + u] : 0ull;
-  for (int e = 0; e < len; e += U) {
-    unsigned long long kk[U];
-    float xv[U];
-    bool ok[U];
+  for (int u = 0; u < U; ++u) kn[u] = keys[p0 + u];
+  int e = 0;
+  // full batches: no per-entry predicate on the entry stream
+  for (; e + U <= len; e += U) {
+    unsigned ib[U], ia[U];
+    bool nf[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      ok[u] = e + u < len;
-      kk[u] = kn[u];
+      const unsigned lo = (unsigned)kn[u], hi = (unsigned)(kn[u] >> 32);
+      ib[u] = lo & mb;
+      ia[u] = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;
+      nf[u] = ia[u] != fa;
+      fa = ia[u];
     }
     f32x4 bv[U][NV], av[U][NV];
-    bool nf[U];
-    unsigned long long pf = fib;
+    float xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const unsigned long long f = kk[u] >> lay.sh_a;
-      nf[u] = ok[u] && f != pf;
-      if (ok[u]) pf = f;
-      const float *pb = Ab + (long long)(kk[u] & lay.mask_b) * RP + 4 * sub;
-      if (ok[u]) {
+      const float *pb = (const float *)(Ab_l + ((size_t)ib[u] << kRowShift));
 #pragma unroll
-        for (int j = 0; j < NV; ++j) bv[u][j] = ld4(pb + 4 * LPN * j);
-      }
-      const float *pa = Aa + (long long)(f & lay.mask_a) * RP + 4 * sub;
-      if (nf[u]) {
+      for (int j = 0; j < NV; ++j) bv[u][j] = ld4(pb + 4 * LPN * j);
+      if (nf[u]) {  // the A_a row is gathered once per fibre
+        const float *pa = (const float *)(Aa_l + ((size_t)ia[u] << kRowShift));
 #pragma unroll
         for (int j = 0; j < NV; ++j) av[u][j] = ld4(pa + 4 * LPN * j);
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = ok[u] ? vals[p0 + e + u] : 0.0f;
+    for (int u = 0; u < U; ++u) xv[u] = vals[p0 + e + u];
 #pragma unroll
-    for (int u = 0; u < U; ++u) kn[u] = (e + U + u < len) ? keys[p0 + e + U + u] : 0ull;
+    for (int u = 0; u < U; ++u) kn[u] = keys[p0 + e + U + u];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-#if SACD_MT_FIBRE
-      if (nf[u]) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-          acc[j] = arow[j] * facc[j] + acc[j];
-          arow[j] = av[u][j];
-          facc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
-      }
-      if (ok[u]) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) facc[j] = xv[u] * bv[u][j] + facc[j];
-      }
-#else
       if (nf[u]) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) arow[j] = av[u][j];
       }
-      if (ok[u]) {
+#pragma unroll
+      for (int j = 0; j < NV; ++j) acc[j] = xv[u] * (arow[j] * bv[u][j]) + acc[j];
+    }
+  }
+  // the last, partial batch (fewer than U entries), predicated per entry
+  if (e < len) {
+    f32x4 bv[U][NV], av[U][NV];
+    float xv[U];
+    bool nf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u < len;
+      const unsigned lo = (unsigned)kn[u], hi = (unsigned)(kn[u] >> 32);
+      const unsigned ibu = lo & mb, iau = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;
+      nf[u] = ok && iau != fa;
+      if (ok) fa = iau;
+      if (ok) {
+        const float *pb = (const float *)(Ab_l + ((size_t)ibu << kRowShift));
+#pragma unroll
+        for (int j = 0; j < NV; ++j) bv[u][j] = ld4(pb + 4 * LPN * j);
+      }
+      if (nf[u]) {
+        const float *pa = (const float *)(Aa_l + ((size_t)iau << kRowShift));
+#pragma unroll
+        for (int j = 0; j < NV; ++j) av[u][j] = ld4(pa + 4 * LPN * j);
+      }
+      xv[u] = ok ? vals[p0 + e + u] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (nf[u]) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) arow[j] = av[u][j];
+      }
+      if (e + u < len) {
 #pragma unroll
         for (int j = 0; j < NV; ++j) acc[j] = xv[u] * (arow[j] * bv[u][j]) + acc[j];
       }
-#endif
     }
-    fib = pf;
   }
-#if SACD_MT_FIBRE
-#pragma unroll
-  for (int j = 0; j < NV; ++j) acc[j] = arow[j] * facc[j] + acc[j];
-#endif
   // A whole slice goes straight to M.  Segments of split slices are first
   // added up inside the block: consecutive units with the same partial slot
   // (the plan gives each such run of one slice its own slot) are summed in

@@ -27,8 +27,6 @@ namespace {
 #define SACD_MT_U 8
 #endif
 
-static_assert(SACD_MT_U <= kKeySlack, "the next-batch key loads may run U - 1 entries past the last entry");
-
 template <int RP>
 struct MCfg {
   static constexpr int W = SACD_MT_W < RP ? SACD_MT_W : RP;  // columns per lane
@@ -101,28 +99,58 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
   constexpr int kRowShift = RP == 16 ? 6 : (RP == 32 ? 7 : (RP == 64 ? 8 : 9));  // log2 of a row's bytes
   static_assert((1 << kRowShift) == 4 * RP, "row size");
   unsigned fa = ~0u;  // i_a of the current fibre (never a valid index)
-  // Software pipeline: the keys of batch k + 1 are loaded while batch k's
-  // rows are gathered.  The key arrays carry kKeySlack zeroed entries past
-  // their end, so these loads need no bounds test and merge into wide loads;
-  // keys past the unit are never used.
-  unsigned long long kn[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) kn[u] = keys[p0 + u];
+  // Each entry's key and value are loaded and decoded by one lane of the
+  // group and handed to the group's other lanes through the LDS crossbar
+  // (ds_bpermute), so the copies do not take vector-memory return cycles.
+  // Lane sub owns entries sub, sub + LPN, ... of a batch.  Pipeline: the
+  // raw entries of batch k + 1 are in flight while batch k's rows are
+  // gathered and multiplied; then batch k + 1 is decoded and shared and the
+  // raw entries of batch k + 2 are loaded.  The key and value arrays carry
+  // kKeySlack zeroed entries past their end, so these loads need no bounds
+  // test; entries past the unit are never used.
+  constexpr int KPL = (U + LPN - 1) / LPN;  // entries loaded per lane and batch
+  static_assert(2 * U <= kKeySlack, "raw loads run up to 2U - 1 entries past the unit");
+  const int gb4 = (int)((threadIdx.x & 63u) & ~(unsigned)(LPN - 1)) * 4;  // group's first lane, bytes
+  unsigned long long rk[KPL];
+  float rx[KPL];
+  unsigned ib[U], ia[U];
+  float xv[U];
+#define SACD_MT_LOAD_RAW(q)                                              \
+  _Pragma("unroll") for (int k = 0; k < KPL; ++k) {                      \
+    if (sub + LPN * k < U) {                                             \
+      rk[k] = keys[p0 + (q) + sub + LPN * k];                            \
+      rx[k] = vals[p0 + (q) + sub + LPN * k];                            \
+    }                                                                    \
+  }
+#define SACD_MT_SHARE_RAW()                                                              \
+  {                                                                                      \
+    unsigned dib[KPL], dia[KPL];                                                         \
+    _Pragma("unroll") for (int k = 0; k < KPL; ++k) {                                    \
+      const unsigned lo = (unsigned)rk[k], hi = (unsigned)(rk[k] >> 32);                 \
+      dib[k] = lo & mb;                                                                  \
+      dia[k] = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;                              \
+    }                                                                                    \
+    _Pragma("unroll") for (int u = 0; u < U; ++u) {                                      \
+      const int src = gb4 + 4 * (u % LPN);                                               \
+      ib[u] = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)dib[u / LPN]);            \
+      ia[u] = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)dia[u / LPN]);            \
+      xv[u] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(rx[u / LPN]))); \
+    }                                                                                    \
+  }
+  SACD_MT_LOAD_RAW(0)
+  SACD_MT_SHARE_RAW()
+  SACD_MT_LOAD_RAW(U)
   int e = 0;
   // full batches: no per-entry predicate on the entry stream
   for (; e + U <= len; e += U) {
-    unsigned ib[U], ia[U];
     bool nf[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const unsigned lo = (unsigned)kn[u], hi = (unsigned)(kn[u] >> 32);
-      ib[u] = lo & mb;
-      ia[u] = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;
       nf[u] = ia[u] != fa;
       fa = ia[u];
     }
     f32x4 bv[U][NV], av[U][NV];
-    float xv[U];
+    float xc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const float *pb = (const float *)(Ab_l + ((size_t)ib[u] << kRowShift));
@@ -133,11 +161,8 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
 #pragma unroll
         for (int j = 0; j < NV; ++j) av[u][j] = ld4(pa + 4 * LPN * j);
       }
+      xc[u] = xv[u];
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) xv[u] = vals[p0 + e + u];
-#pragma unroll
-    for (int u = 0; u < U; ++u) kn[u] = keys[p0 + e + U + u];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (nf[u]) {
@@ -145,32 +170,34 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
         for (int j = 0; j < NV; ++j) arow[j] = av[u][j];
       }
 #pragma unroll
-      for (int j = 0; j < NV; ++j) acc[j] = xv[u] * (arow[j] * bv[u][j]) + acc[j];
+      for (int j = 0; j < NV; ++j) acc[j] = xc[u] * (arow[j] * bv[u][j]) + acc[j];
     }
+    // batch k + 1 is shared after the products of batch k: sharing it
+    // before them keeps its registers live across them and costs a wave
+    SACD_MT_SHARE_RAW()
+    SACD_MT_LOAD_RAW(e + 2 * U)
   }
+#undef SACD_MT_LOAD_RAW
+#undef SACD_MT_SHARE_RAW
   // the last, partial batch (fewer than U entries), predicated per entry
   if (e < len) {
     f32x4 bv[U][NV], av[U][NV];
-    float xv[U];
     bool nf[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = e + u < len;
-      const unsigned lo = (unsigned)kn[u], hi = (unsigned)(kn[u] >> 32);
-      const unsigned ibu = lo & mb, iau = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;
-      nf[u] = ok && iau != fa;
-      if (ok) fa = iau;
+      nf[u] = ok && ia[u] != fa;
+      if (ok) fa = ia[u];
       if (ok) {
-        const float *pb = (const float *)(Ab_l + ((size_t)ibu << kRowShift));
+        const float *pb = (const float *)(Ab_l + ((size_t)ib[u] << kRowShift));
 #pragma unroll
         for (int j = 0; j < NV; ++j) bv[u][j] = ld4(pb + 4 * LPN * j);
       }
       if (nf[u]) {
-        const float *pa = (const float *)(Aa_l + ((size_t)iau << kRowShift));
+        const float *pa = (const float *)(Aa_l + ((size_t)ia[u] << kRowShift));
 #pragma unroll
         for (int j = 0; j < NV; ++j) av[u][j] = ld4(pa + 4 * LPN * j);
       }
-      xv[u] = ok ? vals[p0 + e + u] : 0.0f;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {

@@ -767,7 +767,8 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   SACD_TRY(A.get_t(3, &m->st));
   SACD_TRY(A.get_t((size_t)maxslots * RP, &m->part));
   SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart));
-  SACD_TRY(A.get_t((size_t)maxparts, &m->ti_part));
+  // one importance partial per importance block (blocks of its own size)
+  SACD_TRY(A.get_t((size_t)std::max(maxparts, importance_blocks(RP, (int)maxI)), &m->ti_part));
   SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
   SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
   SACD_TRY(A.get_t((size_t)gram_model_parts(RP), &m->mpart));
@@ -1189,8 +1190,9 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int
            al256(sizeof(HInfo)) + al256(8 * RP);
   }
   const int64_t parts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
+  const int64_t iparts = std::max(parts, (int64_t)importance_blocks(RP, (int)maxI));
   mod += al256(3 * sizeof(ModeState)) + al256(4 * maxunits * RP) + al256(4 * parts * RP * RP) +
-         2 * al256(8 * parts) + al256(4 * parts * RP) + al256(8 * gram_model_parts(RP)) + al256(8 * 1024) +
+         al256(8 * iparts) + al256(8 * parts) + al256(4 * parts * RP) + al256(8 * gram_model_parts(RP)) + al256(8 * 1024) +
          6 * 256;
   int64_t tb = (int64_t)radix_sort_temp_bytes(nnz);
   tb = std::max(tb, (int64_t)dedup_temp_bytes(nnz));

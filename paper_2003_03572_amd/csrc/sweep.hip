@@ -24,9 +24,11 @@ namespace sacd {
 namespace {
 
 // Rows per block: the importance pass uses RB = 256 / 128 / 64 at
-// RP <= 32 / 64 / 128; the update pass uses 64 rows at RP = 64, so that four
-// lanes share each row's Gauss-Seidel chain (measured faster; at RP <= 32 the
-// larger Gram reduction of smaller blocks costs more than it saves).
+// RP <= 32 / 64 / 128; the update pass uses 256 rows at RP <= 32 and 64 rows
+// above.  With the thread counts below, 4 (RP <= 32) or 8 lanes share each
+// row's Gauss-Seidel chain.  Smaller row blocks at RP <= 32 were measured
+// slower: the Gram reduction over more partial blocks costs more than they
+// save.
 template <int RP>
 constexpr int imp_rows() {
   return RP <= 32 ? 256 : (RP == 64 ? 128 : 64);
@@ -35,14 +37,27 @@ template <int RP>
 constexpr int upd_rows() {
   return RP <= 32 ? 256 : 64;
 }
+// Threads per block of the importance and update passes.  The row blocks
+// above fix which rows' partial sums are added together; the thread count
+// sets how many waves work on a block's chain of dependent steps (and the
+// tree of its FP64 block sums, the same in the solo and job-batched forms).
+// 1024 at RP <= 32 and 512 above were measured fastest; 1024 at RP = 128
+// would spill in the job-batched BF16 form.
+template <int RP>
+constexpr int elem_threads() {
+  return RP <= 32 ? 1024 : 512;
+}
 
-template <int RP, int RB_>
+template <int RP, int RB_, int NTH_ = kThreads>
 struct UCfg {
   static constexpr int RB = RB_;        // rows per block
+  static constexpr int NTH = NTH_;      // threads per block
+  static constexpr int W = NTH / 64;    // waves per block
   static constexpr int STR = RP + 1;    // LDS row stride (floats)
   static constexpr int TC = RP / 16;    // 16-column tiles
   static constexpr int NT = (RB / 16) * TC;  // 16x16 tiles per block
-  static constexpr int NTW = NT / 4;    // tiles per wave
+  static constexpr int NTW = NT / W;    // tiles per wave
+  static_assert(NT % W == 0, "tiles must divide evenly over the waves");
 };
 
 __device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
@@ -75,22 +90,23 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
   return *p;
 }
 
-template <int RP, int RB>
+template <int RP, int RB, int NTH = kThreads>
 __device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
-  using Cf = UCfg<RP, RB>;
+  using Cf = UCfg<RP, RB, NTH>;
   // all loads of the tile are issued before the first LDS store waits on one
-  constexpr int N4 = Cf::RB * RP / 4 / kThreads;  // float4 per thread
+  static_assert((Cf::RB * RP / 4) % NTH == 0, "whole float4 per thread");
+  constexpr int N4 = Cf::RB * RP / 4 / NTH;  // float4 per thread
   f32x4 v[N4];
 #pragma unroll
   for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * kThreads) * 4;
+    const int i = (threadIdx.x + k * NTH) * 4;
     const int r = i / RP;
     v[k] = (row0 + r < I) ? *(const f32x4 *)(A + (long long)(row0 + r) * RP + i % RP)
                           : f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
   for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * kThreads) * 4;
+    const int i = (threadIdx.x + k * NTH) * 4;
     float *d = sA + (i / RP) * Cf::STR + i % RP;
     d[0] = v[k][0];
     d[1] = v[k][1];
@@ -100,18 +116,18 @@ __device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A
 }
 
 // Stage H (RP x RP, row stride RP + 1) in LDS.
-template <int RP>
+template <int RP, int NTH = kThreads>
 __device__ __forceinline__ void load_h(float *sH, const float *__restrict__ H) {
-  constexpr int N4 = (RP * RP / 4 + kThreads - 1) / kThreads;
+  constexpr int N4 = (RP * RP / 4 + NTH - 1) / NTH;
   f32x4 v[N4];
 #pragma unroll
   for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * kThreads) * 4;
+    const int i = (threadIdx.x + k * NTH) * 4;
     v[k] = (i < RP * RP) ? *(const f32x4 *)(H + i) : f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll
   for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * kThreads) * 4;
+    const int i = (threadIdx.x + k * NTH) * 4;
     if (i < RP * RP) {
       float *d = sH + (i / RP) * (RP + 1) + i % RP;
       d[0] = v[k][0];
@@ -155,11 +171,11 @@ __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int t
 // sA^T sA), written to gp.  Four independent MFMA accumulation chains over
 // interleaved row groups, added in a fixed order at the end.  BF: operands
 // rounded to BF16, FP32 accumulation.
-template <int RP, int RB, bool BF>
+template <int RP, int RB, bool BF, int W = 4>
 __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, int lane) {
   using Cf = UCfg<RP, RB>;
   constexpr int n16 = RP / 16;
-  for (int t = wv; t < n16 * n16; t += 4) {
+  for (int t = wv; t < n16 * n16; t += W) {
     const int ti_ = t / n16, tj = t % n16;
     if (ti_ > tj) continue;
     f32x4 acc[4];
@@ -197,11 +213,12 @@ __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, i
   }
 }
 
-// Block-wide FP64 sum in a fixed tree order (all threads call; result in red[0]).
+// Block-wide FP64 sum in a fixed tree order (all NTH threads call; result in red[0]).
+template <int NTH = kThreads>
 __device__ __forceinline__ double block_sum(double v, double *red) {
   red[threadIdx.x] = v;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = NTH / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -216,7 +233,7 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // (job in `jobs`, block of the job, blocks of the job).  The body sits in the
 // kernel itself (see k_mttkrp).
 template <int RP, bool BF, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const ImpArgs *__restrict__ jobs,
+__global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo, const ImpArgs *__restrict__ jobs,
                                                          const int4 *__restrict__ bmap, int nb) {
  for (int item = blockIdx.x;; item += gridDim.x) {
   ImpArgs args;
@@ -240,10 +257,10 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
   const HInfo *__restrict__ hi = args.hi;
   double *__restrict__ ti_part = args.ti_part;
   ModeState *st = args.st;
-  using Cf = UCfg<RP, imp_rows<RP>()>;
+  using Cf = UCfg<RP, imp_rows<RP>(), elem_threads<RP>()>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
-  __shared__ double red[kThreads];
+  __shared__ double red[Cf::NTH];
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
   float mv[Cf::NTW][4];
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
-    const int t = wv + 4 * ti;
+    const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const int cc = tc * 16 + (lane & 15);
 #pragma unroll
@@ -261,14 +278,14 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
       mv[ti][v] = (q < I) ? M[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP, Cf::RB>(sA, A, row0, I);
-  load_h<RP>(sH, H);
+  load_rows<RP, Cf::RB, Cf::NTH>(sA, A, row0, I);
+  load_h<RP, Cf::NTH>(sH, H);
   __syncthreads();
   const float halfL = hi->halfL;
   double zs = 0.0;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
-    const int t = wv + 4 * ti;
+    const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
@@ -284,7 +301,7 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
       }
     }
   }
-  const double bs = block_sum(zs, red);
+  const double bs = block_sum<Cf::NTH>(zs, red);
   if (tid == 0) {
     ti_part[blk] = bs;
     __threadfence();
@@ -295,8 +312,8 @@ __global__ __launch_bounds__(kThreads) void k_importance(ImpArgs solo, const Imp
   if (!s_last) break;
   __threadfence();
   double s = 0.0;
-  for (int i = tid; i < nblk; i += kThreads) s += ld_coherent(&ti_part[i]);
-  const double ti = block_sum(s, red);
+  for (int i = tid; i < nblk; i += Cf::NTH) s += ld_coherent(&ti_part[i]);
+  const double ti = block_sum<Cf::NTH>(s, red);
   if (tid == 0) {
     const long long k = st->k + 1;
     const int first = (k == 1);
@@ -374,7 +391,7 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
 // Block blk of the selection / update pass of one sweep.
 // Selection / update pass of one sweep (solo or job-batched, as k_importance).
 template <int RP, int UPD, bool DIAG, bool BF, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const UpdArgs *__restrict__ jobs,
+__global__ __launch_bounds__(elem_threads<RP>()) void k_select_update(UpdArgs solo, const UpdArgs *__restrict__ jobs,
                                                             const int4 *__restrict__ bmap, int nb) {
  for (int item = blockIdx.x;; item += gridDim.x) {
   UpdArgs args;
@@ -400,12 +417,12 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   double *__restrict__ inner_part = args.inner_part;
   int *__restrict__ cnt_part = args.cnt_part;
   uint8_t *__restrict__ selmask = args.selmask;
-  using Cf = UCfg<RP, upd_rows<RP>()>;
+  using Cf = UCfg<RP, upd_rows<RP>(), elem_threads<RP>()>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
   __shared__ unsigned short sSel[Cf::RB * (RP / 16)];  // selection bits, 16 columns a word
-  __shared__ double red[kThreads];
+  __shared__ double red[Cf::NTH];
   __shared__ int sCnt[RP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
@@ -414,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   float mreg[Cf::NTW][4], zpreg[Cf::NTW][4];
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
-    const int t = wv + 4 * ti;
+    const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const int cc = tc * 16 + (lane & 15);
 #pragma unroll
@@ -424,15 +441,15 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
       zpreg[ti][v] = (q < I) ? Z[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP, Cf::RB>(sA, A, row0, I);
-  load_h<RP>(sH, H);
-  for (int c = tid; c < RP; c += kThreads) sCnt[c] = 0;
+  load_rows<RP, Cf::RB, Cf::NTH>(sA, A, row0, I);
+  load_h<RP, Cf::NTH>(sH, H);
+  for (int c = tid; c < RP; c += Cf::NTH) sCnt[c] = 0;
   __syncthreads();
   const int first = st->first, flip = st->flip;
   const float halfL = hi->halfL;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
-    const int t = wv + 4 * ti;
+    const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
@@ -466,14 +483,14 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   }
   __syncthreads();
   {
-    constexpr int LPR = kThreads / Cf::RB;  // lanes per row: 1, 2 or 4
+    constexpr int LPR = Cf::NTH / Cf::RB;  // lanes per row
     const int row = tid / LPR;
     if (row0 + row < I)  // the same for all lanes of a row
       update_row<RP, UPD, LPR>(sA + row * Cf::STR, sG + row * Cf::STR, sSel + row * (RP / 16), sH, hi,
                                tid % LPR);
   }
   __syncthreads();
-  for (int i = tid; i < Cf::RB * RP; i += kThreads) {
+  for (int i = tid; i < Cf::RB * RP; i += Cf::NTH) {
     const int r = i / RP, c = i % RP;
     if (row0 + r < I) A[(long long)(row0 + r) * RP + c] = sA[r * Cf::STR + c];
   }
@@ -481,7 +498,7 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
   double inner = 0.0;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
-    const int t = wv + 4 * ti;
+    const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const int cc = tc * 16 + (lane & 15);
 #pragma unroll
@@ -490,11 +507,11 @@ __global__ __launch_bounds__(kThreads) void k_select_update(UpdArgs solo, const 
       inner += (double)mreg[ti][v] * (double)sA[rr * Cf::STR + cc];
     }
   }
-  const double bs = block_sum(inner, red);
+  const double bs = block_sum<Cf::NTH>(inner, red);
   if (tid == 0) inner_part[blk] = bs;
-  for (int c = tid; c < RP; c += kThreads) cnt_part[(long long)blk * RP + c] = sCnt[c];
+  for (int c = tid; c < RP; c += Cf::NTH) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
-  gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blk * RP * RP, wv, lane);
+  gram_tiles<RP, Cf::RB, BF, Cf::W>(sA, gpart + (long long)blk * RP * RP, wv, lane);
   } while (0);
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
@@ -872,8 +889,8 @@ struct ImpL {
   static hipError_t run(bool bf, const ImpArgs &a, hipStream_t s) {
     const int nb = importance_blocks(RP, a.I);
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_importance<RP, true, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr, nullptr, 0);
-    else hipLaunchKernelGGL((k_importance<RP, false, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr, nullptr, 0);
+    if (bf) hipLaunchKernelGGL((k_importance<RP, true, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
+    else hipLaunchKernelGGL((k_importance<RP, false, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -883,10 +900,10 @@ struct ImpBL {
   static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (bf)
-      hipLaunchKernelGGL((k_importance<RP, true, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
+      hipLaunchKernelGGL((k_importance<RP, true, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s, ImpArgs{},
                          jobs, bmap, nb);
     else
-      hipLaunchKernelGGL((k_importance<RP, false, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
+      hipLaunchKernelGGL((k_importance<RP, false, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s, ImpArgs{},
                          jobs, bmap, nb);
     return hipGetLastError();
   }
@@ -895,10 +912,10 @@ struct ImpBL {
 template <int RP, int UPD, bool DIAG>
 hipError_t upd_launch(bool bf, const UpdArgs &a, int nb, hipStream_t s) {
   if (bf)
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
                        nullptr, 0);
   else
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false>), dim3(nb), dim3(kThreads), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
                        nullptr, 0);
   return hipGetLastError();
 }
@@ -919,10 +936,10 @@ struct UpdBL {
   static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (bf)
-      hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s,
                          UpdArgs{}, jobs, bmap, nb);
     else
-      hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s,
                          UpdArgs{}, jobs, bmap, nb);
     return hipGetLastError();
   }

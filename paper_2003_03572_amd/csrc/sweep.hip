@@ -39,10 +39,12 @@ constexpr int upd_rows() {
 }
 // Threads per block of the importance and update passes.  The row blocks
 // above fix which rows' partial sums are added together; the thread count
-// sets how many waves work on a block's chain of dependent steps (and the
-// tree of its FP64 block sums, the same in the solo and job-batched forms).
-// 1024 at RP <= 32 and 512 above were measured fastest; 1024 at RP = 128
-// would spill in the job-batched BF16 form.
+// only sets how many waves work on a block's chain of dependent steps, and
+// no result depends on it (tiles are summed per wave in a fixed order, see
+// tile_sums_total).  A job alone takes 1024 threads at RP <= 32 and 512
+// above (measured fastest: the chain, not bandwidth, bounds these passes);
+// the job-batched forms take 256, which suits many small jobs resident at
+// once.
 template <int RP>
 constexpr int elem_threads() {
   return RP <= 32 ? 1024 : 512;
@@ -213,18 +215,38 @@ __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, i
   }
 }
 
-// Block-wide FP64 sum in a fixed tree order (all NTH threads call; result in red[0]).
+// Block-wide FP64 sum in a fixed order (all NTH threads call and all get the
+// sum): a butterfly of lane exchanges inside each wave, whose lane-0 total is
+// kept, then the wave totals added in wave order.  red holds NTH / 64 values.
+// FP64 sum over the 64 lanes of a wave by a butterfly of lane exchanges;
+// lane 0's value is the one used (its order of additions is fixed).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 template <int NTH = kThreads>
 __device__ __forceinline__ double block_sum(double v, double *red) {
-  red[threadIdx.x] = v;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = NTH / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int k = 0; k < NTH / 64; ++k) r += red[k];
+  __syncthreads();  // red may be written again right after
   return r;
+}
+
+// Total of the per-tile sums sT[0..NT) in tile order (thread 0 calls it after
+// a barrier).  Each tile's sum is formed by the wave that holds the tile --
+// its lanes' values in row order, then wave_sum -- so the total does not
+// depend on how many waves share the block's tiles.
+template <int NT>
+__device__ __forceinline__ double tile_sums_total(const double *sT) {
+  double t = 0.0;
+  for (int k = 0; k < NT; ++k) t += sT[k];
+  return t;
 }
 
 // Block blk (of nblk) of the importance pass of one sweep.
@@ -232,8 +254,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 // Job-batched form: a persistent grid loops over the block map's entries
 // (job in `jobs`, block of the job, blocks of the job).  The body sits in the
 // kernel itself (see k_mttkrp).
-template <int RP, bool BF, bool BATCHED>
-__global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo, const ImpArgs *__restrict__ jobs,
+template <int RP, bool BF, bool BATCHED, int NTH>
+__global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs *__restrict__ jobs,
                                                          const int4 *__restrict__ bmap, int nb) {
  for (int item = blockIdx.x;; item += gridDim.x) {
   ImpArgs args;
@@ -257,10 +279,11 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo,
   const HInfo *__restrict__ hi = args.hi;
   double *__restrict__ ti_part = args.ti_part;
   ModeState *st = args.st;
-  using Cf = UCfg<RP, imp_rows<RP>(), elem_threads<RP>()>;
+  using Cf = UCfg<RP, imp_rows<RP>(), NTH>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
-  __shared__ double red[Cf::NTH];
+  __shared__ double red[Cf::W];
+  __shared__ double sT[Cf::NT];  // per-tile sums
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
@@ -282,7 +305,6 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo,
   load_h<RP, Cf::NTH>(sH, H);
   __syncthreads();
   const float halfL = hi->halfL;
-  double zs = 0.0;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + Cf::W * ti;
@@ -291,6 +313,7 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo,
     const int cc = tc * 16 + (lane & 15);
     const float h = hi->hdiag[cc];
     const int nz = hi->nearzero[cc];
+    double zs = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rr = tr * 16 + 4 * (lane >> 4) + v;
@@ -300,10 +323,12 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo,
         zs += (double)z;
       }
     }
+    zs = wave_sum(zs);
+    if (lane == 0) sT[t] = zs;
   }
-  const double bs = block_sum<Cf::NTH>(zs, red);
+  __syncthreads();
   if (tid == 0) {
-    ti_part[blk] = bs;
+    ti_part[blk] = tile_sums_total<Cf::NT>(sT);
     __threadfence();
     const unsigned prev = atomicAdd(&st->cnt_imp, 1u);
     s_last = (prev == (unsigned)nblk - 1);
@@ -311,8 +336,11 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_importance(ImpArgs solo,
   __syncthreads();
   if (!s_last) break;
   __threadfence();
+  // the block partials in a fixed 256-lane pattern whatever the block size
+  // (extra waves add exact zeros at the end)
   double s = 0.0;
-  for (int i = tid; i < nblk; i += Cf::NTH) s += ld_coherent(&ti_part[i]);
+  if (tid < kThreads)
+    for (int i = tid; i < nblk; i += kThreads) s += ld_coherent(&ti_part[i]);
   const double ti = block_sum<Cf::NTH>(s, red);
   if (tid == 0) {
     const long long k = st->k + 1;
@@ -390,8 +418,8 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
 
 // Block blk of the selection / update pass of one sweep.
 // Selection / update pass of one sweep (solo or job-batched, as k_importance).
-template <int RP, int UPD, bool DIAG, bool BF, bool BATCHED>
-__global__ __launch_bounds__(elem_threads<RP>()) void k_select_update(UpdArgs solo, const UpdArgs *__restrict__ jobs,
+template <int RP, int UPD, bool DIAG, bool BF, bool BATCHED, int NTH>
+__global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdArgs *__restrict__ jobs,
                                                             const int4 *__restrict__ bmap, int nb) {
  for (int item = blockIdx.x;; item += gridDim.x) {
   UpdArgs args;
@@ -417,12 +445,12 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_select_update(UpdArgs so
   double *__restrict__ inner_part = args.inner_part;
   int *__restrict__ cnt_part = args.cnt_part;
   uint8_t *__restrict__ selmask = args.selmask;
-  using Cf = UCfg<RP, upd_rows<RP>(), elem_threads<RP>()>;
+  using Cf = UCfg<RP, upd_rows<RP>(), NTH>;
   __shared__ float sA[Cf::RB * Cf::STR];
   __shared__ float sG[Cf::RB * Cf::STR];
   __shared__ float sH[RP * (RP + 1)];
   __shared__ unsigned short sSel[Cf::RB * (RP / 16)];  // selection bits, 16 columns a word
-  __shared__ double red[Cf::NTH];
+  __shared__ double sT[Cf::NT];  // per-tile sums
   __shared__ int sCnt[RP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
@@ -494,21 +522,23 @@ __global__ __launch_bounds__(elem_threads<RP>()) void k_select_update(UpdArgs so
     const int r = i / RP, c = i % RP;
     if (row0 + r < I) A[(long long)(row0 + r) * RP + c] = sA[r * Cf::STR + c];
   }
-  // <M, A_n> over the block, FP64
-  double inner = 0.0;
+  // <M, A_n> over the block, FP64, tile by tile
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const int cc = tc * 16 + (lane & 15);
+    double inner = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int rr = tr * 16 + 4 * (lane >> 4) + v;
       inner += (double)mreg[ti][v] * (double)sA[rr * Cf::STR + cc];
     }
+    inner = wave_sum(inner);
+    if (lane == 0) sT[t] = inner;
   }
-  const double bs = block_sum<Cf::NTH>(inner, red);
-  if (tid == 0) inner_part[blk] = bs;
+  __syncthreads();
+  if (tid == 0) inner_part[blk] = tile_sums_total<Cf::NT>(sT);
   for (int c = tid; c < RP; c += Cf::NTH) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
   gram_tiles<RP, Cf::RB, BF, Cf::W>(sA, gpart + (long long)blk * RP * RP, wv, lane);
@@ -530,16 +560,24 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *_
   gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
 }
 
-// Sum of the values base[p * stride], p = s, s + 16, s + 32, ... < n, in
-// index order, sixteen loads in flight at a time.
+// Threads per block of the Gram reduction: 16 entries x kGramStripes.  One
+// block size serves a job alone and the job-batched form (the stripes fix
+// the order of additions); 256 suits the many small jobs of the batched form,
+// 512 would save about 1 us per launch on a 1e7-entry tensor.
+constexpr int kGramThreads = 256;
+constexpr int kGramStripes = kGramThreads / 16;
+
+// Sum of the values base[p * stride], p = s, s + S, s + 2S, ... < n (S =
+// kGramStripes), in index order, sixteen loads in flight at a time.
 template <typename Acc, typename T>
 __device__ __forceinline__ Acc stripe_sum(const T *base, long long stride, int s, int n) {
+  constexpr int S = kGramStripes;
   Acc acc = 0;
-  for (int p0 = s; p0 < n; p0 += 16 * 16) {
+  for (int p0 = s; p0 < n; p0 += 16 * S) {
     T v[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int p = p0 + 16 * k;
+      const int p = p0 + S * k;
       v[k] = (p < n) ? base[(long long)p * stride] : (T)0;
     }
 #pragma unroll
@@ -548,15 +586,24 @@ __device__ __forceinline__ Acc stripe_sum(const T *base, long long stride, int s
   return acc;
 }
 
-// Adds red[tid] over the 16 stripes s = tid / 16 in a fixed tree order;
-// the sum for entry e = tid % 16 ends in red[e].
+// Sum of v over the kGramStripes stripes s = tid / 16 of entry e = tid % 16,
+// in a fixed order: the four stripes of a wave by lane exchanges, then the
+// waves in order.  Threads 0..15 get their entry's sum.  red holds
+// kGramThreads / 4 values.
 template <typename T>
-__device__ __forceinline__ void stripe_tree(T *red) {
+__device__ __forceinline__ T stripe_tree(T v, T *red) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane < 16) red[wv * 16 + lane] = v;
   __syncthreads();
-  for (int w = 8; w > 0; w >>= 1) {
-    if ((int)(threadIdx.x >> 4) < w) red[threadIdx.x] += red[threadIdx.x + 16 * w];
-    __syncthreads();
+  T t = 0;
+  if (threadIdx.x < 16) {
+#pragma unroll
+    for (int k = 0; k < kGramThreads / 64; ++k) t += red[k * 16 + threadIdx.x];
   }
+  __syncthreads();
+  return t;
 }
 
 // Number of 16-entry strips of the upper 16x16 tiles of an RP x RP matrix.
@@ -578,7 +625,7 @@ constexpr int gram_strips() {
 //   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
 // and the total selection count.
 template <int RP, bool BATCHED>
-__global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const GramArgs *__restrict__ jobs,
+__global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, const GramArgs *__restrict__ jobs,
                                                          const int4 *__restrict__ bmap, int nb) {
  for (int item = blockIdx.x;; item += gridDim.x) {
   GramArgs args;
@@ -609,8 +656,8 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const Gr
   unsigned *counter = args.counter;
   ModeState *st = args.st;
   constexpr int RR = RP * RP, n16 = RP / 16, NS = gram_strips<RP>();
-  __shared__ double red[kThreads];
-  __shared__ long long redl[kThreads];
+  __shared__ double red[kGramThreads / 4];
+  __shared__ long long redl[kGramThreads / 4];
   __shared__ int s_last;
   const int tid = threadIdx.x, e = tid & 15, s = tid >> 4;
   const int b = blk;
@@ -625,10 +672,9 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const Gr
     const int x = i * RP + j;
     double wab = 0.0;
     if (with_f && s == 0) wab = (ti == tj ? 1.0 : 2.0) * Ga[x] * Gb[x];  // issued early
-    red[tid] = stripe_sum<double>(gpart + x, RR, s, nparts);
-    stripe_tree(red);
+    const double tot = stripe_tree(stripe_sum<double>(gpart + x, RR, s, nparts), red);
     if (s == 0) {
-      const double v = red[e];
+      const double v = tot;
       Gn[x] = v;
       Gn[j * RP + i] = v;
       if (with_f) red[tid] = v * wab;
@@ -644,21 +690,20 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const Gr
   } else if (b < NS + n16) {
     if (cnt_part) {
       const int c = (b - NS) * 16 + e;
-      redl[tid] = stripe_sum<long long>(cnt_part + c, RP, s, nparts);
-      stripe_tree(redl);
-      if (s == 0) colcnt[c] = redl[e];
+      const long long tot = stripe_tree(stripe_sum<long long>(cnt_part + c, RP, s, nparts), redl);
+      if (s == 0) colcnt[c] = tot;
     }
   } else {
     if (inner_part) {
       double v = 0.0;
-      for (int p0 = tid; p0 < nparts; p0 += 4 * kThreads) {
+      for (int p0 = tid; p0 < nparts; p0 += 4 * kGramThreads) {
         double w[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = (p0 + k * kThreads < nparts) ? inner_part[p0 + k * kThreads] : 0.0;
+        for (int k = 0; k < 4; ++k) w[k] = (p0 + k * kGramThreads < nparts) ? inner_part[p0 + k * kGramThreads] : 0.0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) v += w[k];
       }
-      const double in = block_sum(v, red);
+      const double in = block_sum<kGramThreads>(v, red);
       if (tid == 0) st->inner = in;
     }
   }
@@ -673,16 +718,16 @@ __global__ __launch_bounds__(kThreads) void k_gram_final(GramArgs solo, const Gr
   __threadfence();
   double mv = 0.0;
   long long cv = 0;
-  for (int k = tid; k < NS; k += kThreads)
+  for (int k = tid; k < NS; k += kGramThreads)
     if (with_f) mv += ld_coherent(&mpart[k]);
   if (cnt_part && tid < RP) cv = ld_coherent(&colcnt[tid]);
   const double inner = with_f ? ld_coherent(&st->inner) : 0.0;
   if (with_f) {
-    const double model = block_sum(mv, red);
+    const double model = block_sum<kGramThreads>(mv, red);
     if (tid == 0) st->f = normX2 - 2.0 * inner + model;
   }
   if (cnt_part) {
-    const double all = block_sum((double)cv, red);
+    const double all = block_sum<kGramThreads>((double)cv, red);
     if (tid == 0) st->nsel = (long long)all;
   }
   if (tid == 0) *counter = 0;
@@ -889,8 +934,8 @@ struct ImpL {
   static hipError_t run(bool bf, const ImpArgs &a, hipStream_t s) {
     const int nb = importance_blocks(RP, a.I);
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_importance<RP, true, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
-    else hipLaunchKernelGGL((k_importance<RP, false, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
+    if (bf) hipLaunchKernelGGL((k_importance<RP, true, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
+    else hipLaunchKernelGGL((k_importance<RP, false, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -900,10 +945,10 @@ struct ImpBL {
   static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (bf)
-      hipLaunchKernelGGL((k_importance<RP, true, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s, ImpArgs{},
+      hipLaunchKernelGGL((k_importance<RP, true, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
                          jobs, bmap, nb);
     else
-      hipLaunchKernelGGL((k_importance<RP, false, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s, ImpArgs{},
+      hipLaunchKernelGGL((k_importance<RP, false, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
                          jobs, bmap, nb);
     return hipGetLastError();
   }
@@ -912,10 +957,10 @@ struct ImpBL {
 template <int RP, int UPD, bool DIAG>
 hipError_t upd_launch(bool bf, const UpdArgs &a, int nb, hipStream_t s) {
   if (bf)
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
                        nullptr, 0);
   else
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
                        nullptr, 0);
   return hipGetLastError();
 }
@@ -936,10 +981,10 @@ struct UpdBL {
   static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (bf)
-      hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s,
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
                          UpdArgs{}, jobs, bmap, nb);
     else
-      hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true>), dim3(persistent_grid(nb)), dim3(elem_threads<RP>()), 0, s,
+      hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
                          UpdArgs{}, jobs, bmap, nb);
     return hipGetLastError();
   }
@@ -959,7 +1004,7 @@ struct GpL {
 template <int RP>
 struct GfL {
   static hipError_t run(const GramArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_gram_final<RP, false>), dim3(gram_final_blocks(RP)), dim3(kThreads), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_gram_final<RP, false>), dim3(gram_final_blocks(RP)), dim3(kGramThreads), 0, s, a, nullptr,
                        nullptr, 0);
     return hipGetLastError();
   }
@@ -969,7 +1014,7 @@ template <int RP>
 struct GfBL {
   static hipError_t run(const GramArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gram_final<RP, true>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, GramArgs{}, jobs,
+    hipLaunchKernelGGL((k_gram_final<RP, true>), dim3(persistent_grid(nb)), dim3(kGramThreads), 0, s, GramArgs{}, jobs,
                        bmap, nb);
     return hipGetLastError();
   }

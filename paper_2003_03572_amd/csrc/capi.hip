@@ -236,15 +236,12 @@ MttkrpArgs mttkrp_args(const sacd_model *m, int n) {
 }
 
 FixArgs fix_args(const sacd_model *m, int n) {
-  const sacd_tensor *t = m->t;
   int a, b;
   other_modes(n, &a, &b);
   FixArgs x;
   x.longs = m->plan[n].longs;
   x.nlong = m->plan[n].nlong;
   x.part = m->part;
-  x.ptr = t->ptr[n];
-  x.I = (int)t->dims[n];
   x.M = m->M[n];
   x.Ga = m->G64[a];
   x.Gb = m->G64[b];
@@ -789,6 +786,7 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
     HIP_TRY(launch_init_factor(m->A[n], I, m->R, RP, seed, off, s));
     off += (unsigned long long)I * m->R;
     HIP_TRY(hipMemsetAsync(m->Z[n], 0, sizeof(float) * I * RP, s));
+    // empty slices are never written by the MTTKRP: their rows stay zero
     HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * I * RP, s));
     HIP_TRY(hipMemsetAsync(m->selmask[n], 0, (size_t)I * RP, s));
     HIP_TRY(hipMemsetAsync(m->colcnt[n], 0, sizeof(long long) * RP, s));
@@ -1417,7 +1415,7 @@ sacd_status rebuild_tables(sacd_server *S) {
         const sacd_model *m = S->active[i].m;
         const int I = (int)m->t->dims[n];
         g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
-        g.nb_fx[n] += fix_blocks(m->plan[n].nlong, I);
+        g.nb_fx[n] += fix_blocks(m->plan[n].nlong);
         g.nb_im[n] += importance_blocks(g.RP, I);
         g.nb_up[n] += update_blocks(g.RP, I);
         g.nb_gf[n] += gram_final_blocks(g.RP);
@@ -1456,7 +1454,7 @@ sacd_status rebuild_tables(sacd_server *S) {
       const int I = (int)m->t->dims[n];
       int nb = 0;
       if (which == 0) nb = mttkrp_blocks(g.RP, m->plan[n].nunits);
-      else if (which == 1) nb = fix_blocks(m->plan[n].nlong, I);
+      else if (which == 1) nb = fix_blocks(m->plan[n].nlong);
       else if (which == 2) nb = importance_blocks(g.RP, I);
       else if (which == 3) nb = gram_final_blocks(g.RP);
       else nb = update_blocks(g.RP, I);

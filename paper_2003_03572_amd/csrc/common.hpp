@@ -132,8 +132,7 @@ struct MttkrpPlan {
 };
 int mttkrp_units_per_block(int RP);
 int mttkrp_blocks(int RP, int nunits);
-__host__ __device__ inline int fix_row_blocks(int I) { return (I + kThreads - 1) / kThreads; }
-int fix_blocks(int nlong, int I);
+int fix_blocks(int nlong);
 struct MttkrpArgs {
   const unsigned long long *keys;
   const float *vals;
@@ -147,8 +146,6 @@ struct FixArgs {
   const int4 *longs;
   int nlong;
   const float *part;
-  const int *ptr;
-  int I;
   float *M;
   const double *Ga, *Gb;
   float *H;

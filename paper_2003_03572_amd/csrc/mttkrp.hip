@@ -11,8 +11,8 @@
 // its A_a row once (A_b rows are gathered per entry).
 // A slice held by one unit is written directly; the units of a longer slice
 // write partial sums that the fix-up kernel adds in a fixed tree order, one
-// block per such slice.  The fix-up also zeroes empty slices.  No atomics:
-// results are deterministic for a given tensor.
+// block per such slice.  Empty slices are never written (M is zeroed when the
+// model is set up).  No atomics: results are deterministic for a given tensor.
 #include "common.hpp"
 
 namespace sacd {
@@ -258,9 +258,13 @@ int mttkrp_units_per_block(int RP) {
 namespace {
 
 // Fix-up: blocks [0, nlong) add the partial sums of one split slice in a
-// fixed tree order; the next row_blocks blocks zero empty slices; the last
-// block forms H = Gram_a * Gram_b, L = ||H||_F and the diagonal of H for the
-// element kernels of this sweep (eq. 10, eq. 15, Alg. 1).
+// fixed tree order; the last block forms H = Gram_a * Gram_b, L = ||H||_F
+// and the diagonal of H for the element kernels of this sweep (eq. 10,
+// eq. 15, Alg. 1).  Empty slices are never written: M is zeroed when the
+// model is set up.  The slice sums need every MTTKRP block to have finished,
+// which the kernel boundary provides; done inside the MTTKRP, each block
+// would need a device-scope fence, which writes back and invalidates the L2
+// that the row gathers rely on (measured 5-8x slower).
 template <int RP, bool BATCHED>
 __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const FixArgs *__restrict__ jobs,
                                                          const int4 *__restrict__ bmap, int nb) {
@@ -280,10 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const Fix
   const int4 *__restrict__ longs = args.longs;
   const int nlong = args.nlong;
   const float *__restrict__ part = args.part;
-  const int *__restrict__ ptr = args.ptr;
-  const int I = args.I;
   float *__restrict__ M = args.M;
-  const int row_blocks = fix_row_blocks(I);
   const double *__restrict__ Ga = args.Ga;
   const double *__restrict__ Gb = args.Gb;
   float *__restrict__ H = args.H;
@@ -305,15 +306,6 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const Fix
       __syncthreads();
     }
     if (slot == 0) st4(M + (long long)L.x * RP + 4 * q, red[0][q]);
-    break;
-  }
-  if (b < nlong + row_blocks) {
-    const int r = (b - nlong) * kThreads + tid;
-    if (r < I && ptr[r] == ptr[r + 1]) {
-      float *dst = M + (long long)r * RP;
-#pragma unroll
-      for (int c = 0; c < RP; c += 4) st4(dst + c, f32x4{0.f, 0.f, 0.f, 0.f});
-    }
     break;
   }
   // H, L, diagonal
@@ -393,7 +385,7 @@ struct MtBL {
 template <int RP>
 struct FxL {
   static hipError_t run(const FixArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_mttkrp_fix<RP, false>), dim3(fix_blocks(a.nlong, a.I)), dim3(kThreads), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_mttkrp_fix<RP, false>), dim3(fix_blocks(a.nlong)), dim3(kThreads), 0, s, a, nullptr,
                        nullptr, 0);
     return hipGetLastError();
   }
@@ -415,7 +407,7 @@ int mttkrp_blocks(int RP, int nunits) {
   const int upb = mttkrp_units_per_block(RP);
   return (nunits + upb - 1) / upb;
 }
-int fix_blocks(int nlong, int I) { return nlong + fix_row_blocks(I) + 1; }
+int fix_blocks(int nlong) { return nlong + 1; }
 
 hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s) { return rp_dispatch<MtL>(RP, a, s); }
 hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {

@@ -170,35 +170,46 @@ __device__ __forceinline__ f32x4 tile_AH(const float *sA, const float *sH, int t
 }
 
 // Partial Gram matrix of the block's rows (the upper 16x16 tiles of
-// sA^T sA), written to gp.  Four independent MFMA accumulation chains over
-// interleaved row groups, added in a fixed order at the end.  BF: operands
-// rounded to BF16, FP32 accumulation.
+// sA^T sA), written to gp.  Each tile is split into P = RB / 64 row quarters
+// of 64 rows; a quarter is four independent MFMA accumulation chains over
+// interleaved row groups, added as (c0 + c1) + (c2 + c3), and a tile's
+// quarters are added in order, ((q0 + q1) + (q2 + q3)).  The (tile, quarter)
+// items are spread over the W waves, so with many waves the quarters run in
+// parallel; the arithmetic of every item, and so the result, does not depend
+// on W.  scratch: P x (upper tiles) x 256 floats of LDS, used when P > 1.
+// BF: operands rounded to BF16, FP32 accumulation.
 template <int RP, int RB, bool BF, int W = 4>
-__device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, int lane) {
+__device__ __forceinline__ void gram_tiles(const float *sA, float *gp, float *scratch, int wv, int lane) {
   using Cf = UCfg<RP, RB>;
-  constexpr int n16 = RP / 16;
-  for (int t = wv; t < n16 * n16; t += W) {
-    const int ti_ = t / n16, tj = t % n16;
-    if (ti_ > tj) continue;
+  constexpr int n16 = RP / 16, NUT = n16 * (n16 + 1) / 2, P = RB / 64;
+  static_assert(RB % 64 == 0 && (P == 1 || P == 2 || P == 4), "row quarters of 64 rows");
+  for (int it = wv; it < NUT * P; it += W) {
+    const int u = it / P, p = it % P;
+    int ti_ = 0, rem = u;
+    while (rem >= n16 - ti_) {
+      rem -= n16 - ti_;
+      ++ti_;
+    }
+    const int tj = ti_ + rem;
     f32x4 acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int r0 = p * 64;
     if constexpr (BF) {
-      for (int k0 = 0; k0 < Cf::RB; k0 += 64) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          bf16x4 a, b;
+      for (int c = 0; c < 4; ++c) {
+        bf16x4 a, b;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int row = k0 + 16 * c + 4 * (lane >> 4) + j;
-            a[j] = to_bf16(sA[row * Cf::STR + ti_ * 16 + (lane & 15)]);
-            b[j] = to_bf16(sA[row * Cf::STR + tj * 16 + (lane & 15)]);
-          }
-          acc[c] = mfma_bf16(a, b, acc[c]);
+        for (int j = 0; j < 4; ++j) {
+          const int row = r0 + 16 * c + 4 * (lane >> 4) + j;
+          a[j] = to_bf16(sA[row * Cf::STR + ti_ * 16 + (lane & 15)]);
+          b[j] = to_bf16(sA[row * Cf::STR + tj * 16 + (lane & 15)]);
         }
+        acc[c] = mfma_bf16(a, b, acc[c]);
       }
     } else {
-      for (int k0 = 0; k0 < Cf::RB; k0 += 16) {
+#pragma unroll
+      for (int k0 = r0; k0 < r0 + 64; k0 += 16) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int row = k0 + 4 * c + (lane >> 4);
@@ -208,16 +219,37 @@ __device__ __forceinline__ void gram_tiles(const float *sA, float *gp, int wv, i
         }
       }
     }
-    const f32x4 tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    const f32x4 q = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    if constexpr (P == 1) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = tot[v];
+      for (int v = 0; v < 4; ++v)
+        gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = q[v];
+    } else {
+      *(f32x4 *)(scratch + (size_t)it * 256 + 4 * lane) = q;
+    }
+  }
+  if constexpr (P > 1) {
+    __syncthreads();
+    for (int u = wv; u < NUT; u += W) {
+      int ti_ = 0, rem = u;
+      while (rem >= n16 - ti_) {
+        rem -= n16 - ti_;
+        ++ti_;
+      }
+      const int tj = ti_ + rem;
+      f32x4 q[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) q[p] = *(const f32x4 *)(scratch + (size_t)(u * P + p) * 256 + 4 * lane);
+      f32x4 tot;
+      if constexpr (P == 4) tot = (q[0] + q[1]) + (q[2] + q[3]);
+      else tot = q[0] + q[1];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        gp[(ti_ * 16 + 4 * (lane >> 4) + v) * RP + tj * 16 + (lane & 15)] = tot[v];
+    }
   }
 }
 
-// Block-wide FP64 sum in a fixed order (all NTH threads call and all get the
-// sum): a butterfly of lane exchanges inside each wave, whose lane-0 total is
-// kept, then the wave totals added in wave order.  red holds NTH / 64 values.
 // FP64 sum over the 64 lanes of a wave by a butterfly of lane exchanges;
 // lane 0's value is the one used (its order of additions is fixed).
 __device__ __forceinline__ double wave_sum(double v) {
@@ -447,7 +479,9 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
   uint8_t *__restrict__ selmask = args.selmask;
   using Cf = UCfg<RP, upd_rows<RP>(), NTH>;
   __shared__ float sA[Cf::RB * Cf::STR];
-  __shared__ float sG[Cf::RB * Cf::STR];
+  __shared__ __align__(16) float sG[Cf::RB * Cf::STR];  // gradients, then the Gram tiles' scratch
+  static_assert((Cf::RB / 64 > 1 ? (Cf::RB / 64) * (RP / 16) * (RP / 16 + 1) / 2 * 256 : 0) <= Cf::RB * Cf::STR,
+                "Gram scratch fits in sG");
   __shared__ float sH[RP * (RP + 1)];
   __shared__ unsigned short sSel[Cf::RB * (RP / 16)];  // selection bits, 16 columns a word
   __shared__ double sT[Cf::NT];  // per-tile sums
@@ -541,7 +575,8 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
   if (tid == 0) inner_part[blk] = tile_sums_total<Cf::NT>(sT);
   for (int c = tid; c < RP; c += Cf::NTH) cnt_part[(long long)blk * RP + c] = sCnt[c];
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
-  gram_tiles<RP, Cf::RB, BF, Cf::W>(sA, gpart + (long long)blk * RP * RP, wv, lane);
+  // (sG is free again: it serves as the tiles' LDS scratch)
+  gram_tiles<RP, Cf::RB, BF, Cf::W>(sA, gpart + (long long)blk * RP * RP, sG, wv, lane);
   } while (0);
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
@@ -553,11 +588,13 @@ template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *__restrict__ A,
                                                            float *__restrict__ gpart) {
   using Cf = UCfg<RP, upd_rows<RP>()>;
+  constexpr int NUT = (RP / 16) * (RP / 16 + 1) / 2, P = Cf::RB / 64;
   __shared__ float sA[Cf::RB * Cf::STR];
+  __shared__ __align__(16) float scratch[P > 1 ? P * NUT * 256 : 4];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   load_rows<RP, Cf::RB>(sA, A, blockIdx.x * Cf::RB, I);
   __syncthreads();
-  gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, wv, lane);
+  gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, scratch, wv, lane);
 }
 
 // Threads per block of the Gram reduction: 16 entries x kGramStripes.  One

@@ -62,8 +62,21 @@ def cpu_baseline(w, dims, idx, vals, budget_s: float):
         "cores": 1,
         "kind": "oracle",
         "sample": f"{iters} outer iteration(s) of the full tensor ({T.nnz} entries, R={w.rank}), "
-                  f"FP64 C oracle, single thread, ingest excluded; {per_iter:.3f} s/iteration",
+                  f"FP64 C oracle, single thread, ingest excluded; {per_iter:.3f} s/iteration; "
+                  f"host {host_cpu()}, {os.cpu_count()} hardware threads",
     }
+
+
+def host_cpu() -> str:
+    """The host CPU model (from /proc/cpuinfo), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
 
 
 def mixed_vs_fp32(sacd, T, w, m_mixed, iters: int):

@@ -80,6 +80,22 @@ def test_results_same_alone_and_in_the_mix(sacd, precision):
     assert S.stats()["graph_launches"] > 0
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed_bf16"])
+def test_rank_128_served_equals_alone(sacd, precision):
+    """Padded rank 128: a job alone runs the importance and update passes with
+    512 threads per block, the job-batched form with 256.  No result may depend
+    on that, so a job served in a mix is still bit-identical to the job alone."""
+    jobs = _small_jobs(2, ranks=[128, 100])
+    S, tickets, served, trace, _ = _serve(sacd, jobs, budget=1 << 32, precision=precision)
+    assert max(s["running"] for s in trace) == len(jobs)
+    for t, (seed, dims, idx, vals, R) in zip(tickets, jobs):
+        it, fit, A = _alone(sacd, dims, idx, vals, R, seed, precision)
+        it_s, fit_s, A_s = served[t]
+        assert it_s == it and fit_s == fit, (t, it, it_s, fit, fit_s)
+        for n in range(3):
+            np.testing.assert_array_equal(A_s[n].view(np.uint32), A[n].view(np.uint32))
+
+
 def test_admission_by_budget(sacd):
     jobs = _small_jobs(8)
     sizes = [sum(sacd.job_bytes(j[1], j[2].shape[0], j[4])) for j in jobs]

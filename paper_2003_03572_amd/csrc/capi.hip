@@ -1292,6 +1292,7 @@ struct BatchGroup {
   GramArgs *gf[3] = {};
   int4 *bm_mt[3] = {}, *bm_fx[3] = {}, *bm_im[3] = {}, *bm_up[3] = {}, *bm_gf[3] = {};
   int nb_mt[3] = {}, nb_fx[3] = {}, nb_im[3] = {}, nb_up[3] = {}, nb_gf[3] = {};
+  bool big = false;  // element passes in 1024-thread blocks (few row blocks in all)
 };
 
 }  // namespace
@@ -1425,6 +1426,11 @@ sacd_status rebuild_tables(sacd_server *S) {
                table_bytes<ImpArgs>(nj, g.nb_im[n]) + table_bytes<UpdArgs>(nj, g.nb_up[n]) +
                table_bytes<GramArgs>(nj, g.nb_gf[n]);
     }
+  // With few row blocks in all (at most one per compute unit), the element
+  // passes run in 1024-thread blocks, which shorten each block's chain; with
+  // many resident jobs, 256-thread blocks keep more of them in flight.
+  for (BatchGroup &g : S->groups)
+    g.big = g.RP <= 32 && std::max(g.nb_up[0], std::max(g.nb_up[1], g.nb_up[2])) <= 256;
   if (total > S->h_stage_bytes) {
     if (S->h_stage) (void)hipHostFree(S->h_stage);
     S->h_stage = nullptr;
@@ -1521,8 +1527,8 @@ sacd_status enqueue_batched_iteration(sacd_server *S) {
     for (int n = 0; n < 3; ++n) {
       HIP_TRY(launch_mttkrp_b(g.RP, g.mt[n], g.bm_mt[n], g.nb_mt[n], s));
       HIP_TRY(launch_mttkrp_fix_b(g.RP, g.fx[n], g.bm_fx[n], g.nb_fx[n], s));
-      HIP_TRY(launch_importance_b(g.RP, bf, g.im[n], g.bm_im[n], g.nb_im[n], s));
-      HIP_TRY(launch_select_update_b(g.RP, bf, g.up[n], g.bm_up[n], g.nb_up[n], s));
+      HIP_TRY(launch_importance_b(g.RP, bf, g.big, g.im[n], g.bm_im[n], g.nb_im[n], s));
+      HIP_TRY(launch_select_update_b(g.RP, bf, g.big, g.up[n], g.bm_up[n], g.nb_up[n], s));
       HIP_TRY(launch_gram_final_b(g.RP, g.gf[n], g.bm_gf[n], g.nb_gf[n], s));
     }
     HIP_TRY(hipEventRecord(S->ev_join[gi], s));

@@ -204,10 +204,12 @@ int gram_model_parts(int RP);
 hipError_t launch_init_factor(float *A, int I, int R, int RP, unsigned long long seed,
                               unsigned long long offset, hipStream_t s);
 hipError_t launch_importance(int RP, bool bf, const ImpArgs &a, hipStream_t s);
-hipError_t launch_importance_b(int RP, bool bf, const ImpArgs *jobs, const int4 *bmap, int nblocks,
+// big: at RP <= 32, blocks of 1024 threads instead of 256 (no result depends
+// on the block size); for launches whose jobs have few row blocks in all.
+hipError_t launch_importance_b(int RP, bool bf, bool big, const ImpArgs *jobs, const int4 *bmap, int nblocks,
                                hipStream_t s);
 hipError_t launch_select_update(int RP, int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s);
-hipError_t launch_select_update_b(int RP, bool bf, const UpdArgs *jobs, const int4 *bmap, int nblocks,
+hipError_t launch_select_update_b(int RP, bool bf, bool big, const UpdArgs *jobs, const int4 *bmap, int nblocks,
                                   hipStream_t s);
 hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s);
 hipError_t launch_gram_final(int RP, const GramArgs &a, hipStream_t s);

@@ -44,7 +44,8 @@ constexpr int upd_rows() {
 // tile_sums_total).  A job alone takes 1024 threads at RP <= 32 and 512
 // above (measured fastest: the chain, not bandwidth, bounds these passes);
 // the job-batched forms take 256, which suits many small jobs resident at
-// once.
+// once, or, at RP <= 32, 1024 when the jobs of a launch have few row blocks
+// in all (the caller's choice, `big`).
 template <int RP>
 constexpr int elem_threads() {
   return RP <= 32 ? 1024 : 512;
@@ -979,8 +980,20 @@ struct ImpL {
 
 template <int RP>
 struct ImpBL {
-  static hipError_t run(bool bf, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+  static hipError_t run(bool bf, bool big, const ImpArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
+    if constexpr (RP <= 32) {
+      if (big) {
+        constexpr int T = elem_threads<RP>();
+        if (bf)
+          hipLaunchKernelGGL((k_importance<RP, true, true, T>), dim3(persistent_grid(nb)), dim3(T), 0, s, ImpArgs{},
+                             jobs, bmap, nb);
+        else
+          hipLaunchKernelGGL((k_importance<RP, false, true, T>), dim3(persistent_grid(nb)), dim3(T), 0, s, ImpArgs{},
+                             jobs, bmap, nb);
+        return hipGetLastError();
+      }
+    }
     if (bf)
       hipLaunchKernelGGL((k_importance<RP, true, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s, ImpArgs{},
                          jobs, bmap, nb);
@@ -1015,8 +1028,20 @@ struct UpdL {
 
 template <int RP>
 struct UpdBL {
-  static hipError_t run(bool bf, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
+  static hipError_t run(bool bf, bool big, const UpdArgs *jobs, const int4 *bmap, int nb, hipStream_t s) {
     if (nb == 0) return hipSuccess;
+    if constexpr (RP <= 32) {
+      if (big) {
+        constexpr int T = elem_threads<RP>();
+        if (bf)
+          hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true, T>), dim3(persistent_grid(nb)), dim3(T), 0,
+                             s, UpdArgs{}, jobs, bmap, nb);
+        else
+          hipLaunchKernelGGL((k_select_update<RP, 0, false, false, true, T>), dim3(persistent_grid(nb)), dim3(T), 0,
+                             s, UpdArgs{}, jobs, bmap, nb);
+        return hipGetLastError();
+      }
+    }
     if (bf)
       hipLaunchKernelGGL((k_select_update<RP, 0, false, true, true, kThreads>), dim3(persistent_grid(nb)), dim3(kThreads), 0, s,
                          UpdArgs{}, jobs, bmap, nb);
@@ -1062,16 +1087,16 @@ struct GfBL {
 hipError_t launch_importance(int RP, bool bf, const ImpArgs &a, hipStream_t s) {
   return rp_dispatch<ImpL>(RP, bf, a, s);
 }
-hipError_t launch_importance_b(int RP, bool bf, const ImpArgs *jobs, const int4 *bmap, int nblocks,
+hipError_t launch_importance_b(int RP, bool bf, bool big, const ImpArgs *jobs, const int4 *bmap, int nblocks,
                                hipStream_t s) {
-  return rp_dispatch<ImpBL>(RP, bf, jobs, bmap, nblocks, s);
+  return rp_dispatch<ImpBL>(RP, bf, big, jobs, bmap, nblocks, s);
 }
 hipError_t launch_select_update(int RP, int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s) {
   return rp_dispatch<UpdL>(RP, update, diag, bf, a, s);
 }
-hipError_t launch_select_update_b(int RP, bool bf, const UpdArgs *jobs, const int4 *bmap, int nblocks,
+hipError_t launch_select_update_b(int RP, bool bf, bool big, const UpdArgs *jobs, const int4 *bmap, int nblocks,
                                   hipStream_t s) {
-  return rp_dispatch<UpdBL>(RP, bf, jobs, bmap, nblocks, s);
+  return rp_dispatch<UpdBL>(RP, bf, big, jobs, bmap, nblocks, s);
 }
 hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s) {
   return rp_dispatch<GpL>(RP, bf, I, A, gpart, s);

@@ -14,9 +14,11 @@
 //   k_gram_final     reduces the Gram partials in FP64 in a fixed order; the
 //                    last block forms the objective eq. 6 in FP64.
 //
-// Rows are split into blocks of RB rows (RB lanes x columns = 256 x 32 at
-// most); a block keeps its rows of A_n and H in LDS (row stride RP + 1
-// floats: conflict-free for the row-wise update).
+// Rows are split into blocks of RB rows (256 at RP <= 32, fewer above); a
+// block keeps its rows of A_n and H in LDS (row stride RP + 1 floats:
+// conflict-free for the row-wise update).  The row blocks fix every partial
+// sum; the number of threads working on a block (256 to 1024) changes no
+// result.
 #include "common.hpp"
 
 namespace sacd {

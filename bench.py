@@ -403,6 +403,9 @@ def main():
         ktimes[("mttkrp", n)] = mt_avg_us[n] * 1e-3
     for (name, n), ms in ktimes.items():
         log(f"[bench] kernel {name} mode {n}: {1e3 * ms:.1f} us")
+    which_of = {"mttkrp": 0, "select_update": 1, "importance": 2}
+    kernel_gbps = {f"{name}_mode{n}": round(m.kernel_bytes(which_of[name], n) / (ms * 1e-3) / 1e9, 1)
+                   for (name, n), ms in ktimes.items()}
     traffic = measured_traffic(w.name)
 
     # the same iterations replayed from the captured graph (reference only)
@@ -430,7 +433,9 @@ def main():
                    "step": "one outer iteration (sweeps of modes 0, 1, 2) incl. FP64 objective",
                    "gpu_event_ms_per_step": gpu_ms / args.steps,
                    "graph_replay_ms_per_step": graph_ms,
-                   "kernel_us": {f"{k[0]}_mode{k[1]}": round(1e3 * v, 2) for k, v in ktimes.items()}},
+                   "kernel_us": {f"{k[0]}_mode{k[1]}": round(1e3 * v, 2) for k, v in ktimes.items()},
+                   # algorithmic bytes of each launch over its measured time
+                   "kernel_gbps_algorithmic": kernel_gbps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_mttkrp (3 launches per step, one per mode, averaged)",

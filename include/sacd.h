@@ -123,7 +123,9 @@ void sacd_destroy_tensor(sacd_tensor *t);
 /* ------------------------------------------------------------------------ */
 
 /* Create a model of rank R in [1, 128] over tensor t (Alg. 1 inputs: tensor,
- * randomly initialised factors, rank).  Factors A0, A1, A2 are filled in that
+ * randomly initialised factors, rank).  The cap of 128 is this library's: the
+ * element kernels keep a block's rows of A_n and the R x R matrix H in LDS,
+ * and at R = 256 H alone (256 KB in FP32) exceeds a CU's 160 KB.  Factors A0, A1, A2 are filled in that
  * order, row-major with R columns, from consecutive outputs of SplitMix64
  * seeded with `seed`, each output x mapped to (x >> 40) * 2^-24 in [0, 1).
  * Z = empty (no sweep done).  The tensor must outlive the model.
@@ -183,6 +185,13 @@ sacd_status sacd_set_state(sacd_model *m, int32_t mode, const float *zprev, doub
 
 /* Statistics of the last sweep of `mode` (host struct).  Synchronises. */
 sacd_status sacd_get_stats(const sacd_model *m, int32_t mode, sacd_sweep_stats *out);
+
+/* Per-column counts |e_r| of the last sweep of `mode`: counts (host, R
+ * int64) receives, for every column r, the number of elements of column r
+ * selected for update (Alg. 1, the column-wise element update of Sec. 4.3 and
+ * Alg. 2); their sum is n_selected of sacd_get_stats.  Zeros before the first
+ * sweep of the mode.  Synchronises.  Errors: INVALID_ARG (NULL, mode), DEVICE. */
+sacd_status sacd_get_column_counts(const sacd_model *m, int32_t mode, int64_t *counts);
 
 /* Diagnostics of the last sweep of `mode`, for parity tests:
  *   mttkrp     device I_n x R FP32, the MTTKRP M of eq. 9;

@@ -24,10 +24,11 @@ UPDATE_JACOBI = 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math; OpenMP for the
+    loops whose iterations are independent)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                                "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -59,7 +60,7 @@ def lib():
         L.ora_cd_delta.restype = dbl
         L.ora_importance.argtypes = [dbl, dbl, dbl]
         L.ora_importance.restype = dbl
-        L.ora_select.argtypes = [i64, C.c_float, C.c_float, i32]
+        L.ora_select.argtypes = [i64, dbl, dbl, i32]
         L.ora_select.restype = i32
         L.ora_model_create.argtypes = [p, i32, C.c_uint64, i32, C.POINTER(p)]
         L.ora_model_destroy.argtypes = [p]
@@ -73,7 +74,11 @@ def lib():
         L.ora_model_set_tie_tol.argtypes = [p, dbl]
         L.ora_model_set_tie_tol.restype = None
         L.ora_sweep.argtypes = [p, i32]
-        L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p, p]
+        L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p]
+        L.ora_sweep_band.argtypes = [p, i32, p, p, p]
+        L.ora_sweep_undo.argtypes = [p, i32]
+        L.ora_set_threads.argtypes = [i32]
+        L.ora_set_threads.restype = i32
         L.ora_row_outcome.argtypes = [p, i32, i64, p, p]
         L.ora_objective.argtypes = [p]
         L.ora_objective.restype = dbl
@@ -115,8 +120,11 @@ class Tensor:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().ora_tensor_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.ora_tensor_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     @property
@@ -164,6 +172,12 @@ def select(k: int, z: float, zprev: float, flip: bool) -> bool:
     return bool(lib().ora_select(k, z, zprev, int(flip)))
 
 
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's parallel loops (n < 1: unchanged); returns the
+    count in use.  Results are bit-identical for any count."""
+    return int(lib().ora_set_threads(int(n)))
+
+
 class Model:
     """SaCD state for one tensor (Alg. 1): factors, Grams, Z^{k-1}, ti^{k-1}, k."""
 
@@ -177,8 +191,11 @@ class Model:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().ora_model_destroy(h)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.ora_model_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def factor(self, mode: int) -> np.ndarray:
@@ -192,7 +209,7 @@ class Model:
         _check(lib().ora_model_set_factor(self._h, mode, _ptr(A)), "set_factor")
 
     def state(self, mode: int):
-        zp = np.empty((self.t.dims[mode], self.R), np.float32)
+        zp = np.empty((self.t.dims[mode], self.R), np.float64)
         ti = C.c_double()
         k = C.c_int64()
         _check(lib().ora_model_get_state(self._h, mode, _ptr(zp), C.byref(ti), C.byref(k)),
@@ -200,7 +217,7 @@ class Model:
         return zp, ti.value, k.value
 
     def set_state(self, mode: int, zprev: np.ndarray, ti_prev: float, k: int):
-        zp = np.ascontiguousarray(zprev, dtype=np.float32)
+        zp = np.ascontiguousarray(zprev, dtype=np.float64)
         assert zp.shape == (self.t.dims[mode], self.R)
         _check(lib().ora_model_set_state(self._h, mode, _ptr(zp), float(ti_prev), int(k)),
                "set_state")
@@ -214,20 +231,33 @@ class Model:
     def sweep(self, mode: int):
         _check(lib().ora_sweep(self._h, mode), "ora_sweep")
 
+    def undo_sweep(self, mode: int):
+        """Restore the state before the last sweep of `mode` (factor, Gram,
+        Z^{k-1}, ti^{k-1}, k and the band of Z^{k-1})."""
+        _check(lib().ora_sweep_undo(self._h, mode), "ora_sweep_undo")
+
     def info(self, mode: int) -> dict:
+        """Record of the last sweep of `mode` with its tie band.  kind: 0
+        decided, 1 exact zero (decided), 2 zero-gradient tie, 3 margin tie;
+        tie = kind >= 2."""
         I, R = self.t.dims[mode], self.R
         M = np.empty((I, R), np.float64)
         G0 = np.empty((I, R), np.float64)
-        z = np.empty((I, R), np.float32)
+        z = np.empty((I, R), np.float64)
         sel = np.empty((I, R), np.uint8)
-        tie = np.empty((I, R), np.uint8)
         H = np.empty((R, R), np.float64)
         sc = np.empty(8, np.float64)
         _check(lib().ora_sweep_info(self._h, mode, _ptr(M), _ptr(G0), _ptr(z), _ptr(sel),
-                                    _ptr(tie), _ptr(H), _ptr(sc)), "sweep_info")
-        return dict(M=M, G0=G0, z=z, sel=sel.astype(bool), tie=tie.astype(bool), H=H,
-                    L=sc[0], ti=sc[1], flip=bool(sc[2]), tie_global=bool(sc[3]), f=sc[4],
-                    nsel=int(sc[5]), inner=sc[6], model=sc[7])
+                                    _ptr(H), _ptr(sc)), "sweep_info")
+        band = np.empty((I, R), np.float64)
+        kind = np.empty((I, R), np.uint8)
+        bs = np.empty(5, np.float64)
+        _check(lib().ora_sweep_band(self._h, mode, _ptr(band), _ptr(kind), _ptr(bs)), "sweep_band")
+        return dict(M=M, G0=G0, z=z, sel=sel.astype(bool), H=H,
+                    L=sc[0], ti=sc[1], flip=bool(sc[2]), ti_prev=sc[3], f=sc[4],
+                    nsel=int(sc[5]), inner=sc[6], model=sc[7],
+                    band=band, kind=kind, tie=kind >= 2, band_ti=bs[0], tie_global=bool(bs[1]),
+                    n_exact_zero=int(bs[2]), n_zero_grad=int(bs[3]), n_margin=int(bs[4]))
 
     def row_outcome(self, mode: int, q: int, sel: np.ndarray) -> np.ndarray:
         """Row q of the last sweep of `mode` updated under decisions `sel`."""

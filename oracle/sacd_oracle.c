@@ -7,12 +7,21 @@
  * Written to be read against the paper, not to be fast: plain loops, FP64
  * arithmetic, the steps of Algorithm 1 in the paper's order.  Readings of the
  * paper where its text is ambiguous are marked "Reading:".
+ *
+ * Loops whose iterations are independent (rows, slices, Gram entries) carry an
+ * OpenMP "parallel for" so that the oracle can also be timed on all host
+ * cores.  No loop that adds across iterations is parallelised: every sum is
+ * formed in the same order for any thread count, so results are bit-identical
+ * with 1 or many threads.
  */
 #include "sacd_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_OK 0
 #define ORA_EINVAL (-1)
@@ -173,23 +182,40 @@ int ora_mttkrp(const ora_tensor *t, int mode, int R, const double *A0,
   memset(M, 0, (size_t)t->dims[mode] * (size_t)R * sizeof(double));
   const int32_t *c = t->coords[mode];
   const float *v = t->vals[mode];
-  for (int64_t p = 0; p < t->nnz; ++p) {
-    const int64_t in = c[3 * p], ia = c[3 * p + 1], ib = c[3 * p + 2];
-    const double x = (double)v[p];
-    for (int r = 0; r < R; ++r)
-      M[in * R + r] += x * F[a][ia * R + r] * F[b][ib * R + r];
+  const int64_t *ptr = t->ptr[mode];
+  /* slice by slice (row i_n of M only receives its slice's entries, which
+   * are added in their sorted order) */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < t->dims[mode]; ++i) {
+    for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p) {
+      const int64_t ia = c[3 * p + 1], ib = c[3 * p + 2];
+      const double x = (double)v[p];
+      for (int r = 0; r < R; ++r)
+        M[i * R + r] += x * F[a][ia * R + r] * F[b][ib * R + r];
+    }
   }
   return ORA_OK;
 }
 
 /* Gram matrix A^T A (R x R). */
 static void gram(const double *A, int64_t I, int R, double *G) {
+#pragma omp parallel for schedule(dynamic, 1)
   for (int r = 0; r < R; ++r)
     for (int s = 0; s < R; ++s) {
       double acc = 0.0;
       for (int64_t q = 0; q < I; ++q) acc += A[q * R + r] * A[q * R + s];
       G[r * R + s] = acc;
     }
+}
+
+int ora_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */
@@ -224,14 +250,14 @@ double ora_importance(double g, double delta, double L) {
   return -(g * delta) - 0.5 * L * delta * delta;
 }
 
+
 /* Alg. 1 selection.  First sweep: update iff z > 0.  Later sweeps: the
  * saturation point is z - zprev (eq. 24), or zprev - z when the total
- * importance grew (eq. 27); update iff it is > 0.  Comparisons are strict and
- * are taken on the FP32 values the GPU stores. */
-int ora_select(int64_t k, float z, float zprev, int flip) {
-  if (k <= 1) return z > 0.0f;
-  float sp = flip ? (zprev - z) : (z - zprev);
-  return sp > 0.0f;
+ * importance grew (eq. 27); update iff it is > 0.  Comparisons are strict. */
+int ora_select(int64_t k, double z, double zprev, int flip) {
+  if (k <= 1) return z > 0.0;
+  const double sp = flip ? (zprev - z) : (z - zprev);
+  return sp > 0.0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -244,18 +270,25 @@ struct ora_model {
   int update_rule;
   int force_flip;
   double tau;
+  /* state of Alg. 1 */
   double *A[3];
   double *G[3];      /* Gram matrices A_n^T A_n */
-  float *zprev[3];   /* Z^{k-1} (FP32) */
-  double ti_prev[3];
+  double *zprev[3];  /* Z^{k-1} */
+  double ti_prev[3]; /* ti^{k-1} */
   int64_t k[3];
-  /* diagnostics of the last sweep of each mode */
-  double *M[3], *G0[3];
-  float *z[3];
-  uint8_t *sel[3], *tie[3];
+  /* record of the last sweep of each mode (for the tests) */
+  double *M[3], *G0[3], *z[3];
+  uint8_t *sel[3];
   double *H[3];
   double info[3][8];
-  double *A_prev[3]; /* factor before the last sweep of the mode */
+  double *A_prev[3];     /* factor before the sweep */
+  double *zprev_used[3]; /* Z^{k-1} the selection compared with */
+  int undo_ok[3];        /* the record above holds the state before the last sweep */
+  /* tie band (diagnostics, see ora_sweep_band) */
+  double *band[3];       /* band of z of the last sweep */
+  double *band_used[3];  /* band of the Z^{k-1} that sweep compared with */
+  uint8_t *kind[3];
+  double band_info[3][5];
 };
 
 void ora_model_destroy(ora_model *m) {
@@ -263,8 +296,9 @@ void ora_model_destroy(ora_model *m) {
   for (int n = 0; n < 3; ++n) {
     free(m->A[n]); free(m->G[n]); free(m->zprev[n]);
     free(m->M[n]); free(m->G0[n]); free(m->z[n]);
-    free(m->sel[n]); free(m->tie[n]); free(m->H[n]);
-    free(m->A_prev[n]);
+    free(m->sel[n]); free(m->H[n]); free(m->A_prev[n]);
+    free(m->zprev_used[n]); free(m->band[n]); free(m->band_used[n]);
+    free(m->kind[n]);
   }
   free(m);
 }
@@ -290,16 +324,20 @@ int ora_model_create(const ora_tensor *t, int R, uint64_t seed, int update_rule,
     const size_t IR = (size_t)t->dims[n] * (size_t)R;
     m->A[n] = (double *)malloc(IR * sizeof(double));
     m->G[n] = (double *)malloc((size_t)R * R * sizeof(double));
-    m->zprev[n] = (float *)calloc(IR, sizeof(float));
+    m->zprev[n] = (double *)calloc(IR, sizeof(double));
     m->M[n] = (double *)calloc(IR, sizeof(double));
     m->G0[n] = (double *)calloc(IR, sizeof(double));
-    m->z[n] = (float *)calloc(IR, sizeof(float));
+    m->z[n] = (double *)calloc(IR, sizeof(double));
     m->sel[n] = (uint8_t *)calloc(IR, 1);
-    m->tie[n] = (uint8_t *)calloc(IR, 1);
     m->H[n] = (double *)calloc((size_t)R * R, sizeof(double));
     m->A_prev[n] = (double *)calloc(IR, sizeof(double));
-    if (!m->A[n] || !m->G[n] || !m->zprev[n] || !m->M[n] || !m->G0[n] ||
-        !m->z[n] || !m->sel[n] || !m->tie[n] || !m->H[n] || !m->A_prev[n]) {
+    m->zprev_used[n] = (double *)calloc(IR, sizeof(double));
+    m->band[n] = (double *)calloc(IR, sizeof(double));
+    m->band_used[n] = (double *)calloc(IR, sizeof(double));
+    m->kind[n] = (uint8_t *)calloc(IR, 1);
+    if (!m->A[n] || !m->G[n] || !m->zprev[n] || !m->M[n] || !m->G0[n] || !m->z[n] ||
+        !m->sel[n] || !m->H[n] || !m->A_prev[n] || !m->zprev_used[n] || !m->band[n] ||
+        !m->band_used[n] || !m->kind[n]) {
       free(raw); ora_model_destroy(m); return ORA_ENOMEM;
     }
     for (size_t i = 0; i < IR; ++i)
@@ -330,21 +368,24 @@ int ora_model_set_factor(ora_model *m, int mode, const double *src) {
   return ORA_OK;
 }
 
-int ora_model_get_state(const ora_model *m, int mode, float *zprev,
+int ora_model_get_state(const ora_model *m, int mode, double *zprev,
                         double *ti_prev, int64_t *k) {
   if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
-  if (zprev) memcpy(zprev, m->zprev[mode], (size_t)m->t->dims[mode] * m->R * sizeof(float));
+  if (zprev) memcpy(zprev, m->zprev[mode], (size_t)m->t->dims[mode] * m->R * sizeof(double));
   if (ti_prev) *ti_prev = m->ti_prev[mode];
   if (k) *k = m->k[mode];
   return ORA_OK;
 }
 
-int ora_model_set_state(ora_model *m, int mode, const float *zprev,
+int ora_model_set_state(ora_model *m, int mode, const double *zprev,
                         double ti_prev, int64_t k) {
   if (!m || mode < 0 || mode > 2 || k < 0) return ORA_EINVAL;
-  if (zprev) memcpy(m->zprev[mode], zprev, (size_t)m->t->dims[mode] * m->R * sizeof(float));
+  const size_t IR = (size_t)m->t->dims[mode] * m->R;
+  if (zprev) memcpy(m->zprev[mode], zprev, IR * sizeof(double));
+  memset(m->band[mode], 0, IR * sizeof(double)); /* the given Z^{k-1} is exact */
   m->ti_prev[mode] = ti_prev;
   m->k[mode] = k;
+  m->undo_ok[mode] = 0;
   return ORA_OK;
 }
 
@@ -449,6 +490,8 @@ static void update_row(double *a, const uint8_t *sel, const double *M, const dou
   }
 }
 
+static void record_tie_band(ora_model *m, int mode);
+
 /*
  * One sweep of mode n: the body of Alg. 1 for one factor matrix.
  *
@@ -458,7 +501,7 @@ static void update_row(double *a, const uint8_t *sel, const double *M, const dou
  *  3. M = sparse MTTKRP (eq. 9 first term).
  *  4. G0 = -M + A_n H, the gradient computed once per sweep (eq. 9, eq. 14).
  *  5. For every element: step delta (eq. 11-12) and importance z (eq. 20).
- *  6. Total importance ti = sum z (eq. 25).
+ *  6. Total importance ti = sum z over all elements (eq. 25).
  *  7. Selection (Alg. 1, eq. 24 / eq. 27).
  *  8. Z^{k-1} <- z for every element, ti^{k-1} <- ti (Alg. 1; eq. 26).
  *  9. Update of the selected elements by eq. 13.
@@ -474,23 +517,26 @@ static void update_row(double *a, const uint8_t *sel, const double *M, const dou
  * 10. Gram_n = A_n^T A_n.
  * 11. f = ||X||^2 - 2 <M, A_n> + sum (Gram_0 * Gram_1 * Gram_2), which equals
  *     eq. 6 because M does not depend on A_n.
+ * The tie band of the sweep is recorded afterwards (not a step of Alg. 1).
  */
 int ora_sweep(ora_model *m, int mode) {
   if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
   const ora_tensor *t = m->t;
   const int R = m->R;
   const int64_t I = t->dims[mode];
+  const size_t IR = (size_t)I * R;
   int a, b;
   other_modes(mode, &a, &b);
   double *A = m->A[mode];
   double *H = m->H[mode];
   double *M = m->M[mode];
   double *G0 = m->G0[mode];
-  float *z = m->z[mode];
-  float *zprev = m->zprev[mode];
+  double *z = m->z[mode];
+  double *zprev = m->zprev[mode];
   uint8_t *sel = m->sel[mode];
-  uint8_t *tie = m->tie[mode];
-  const double tau = m->tau;
+  double *delta = (double *)malloc((IR > 0 ? IR : 1) * sizeof(double));
+  if (!delta) return ORA_ENOMEM;
+  memcpy(m->A_prev[mode], A, IR * sizeof(double));
 
   /* 1 */
   m->k[mode] += 1;
@@ -507,77 +553,53 @@ int ora_sweep(ora_model *m, int mode) {
   /* 3 */
   ora_mttkrp(t, mode, R, m->A[0], m->A[1], m->A[2], M);
 
-  /* 4, 5, 6 */
-  double ti = 0.0, scale_sum = 0.0;
-  double *delta = (double *)malloc((size_t)I * R * sizeof(double));
-  double *scale = (double *)malloc((size_t)I * R * sizeof(double));
-  if (!delta || !scale) { free(delta); free(scale); return ORA_ENOMEM; }
+  /* 4, 5 */
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < I; ++q) {
     for (int r = 0; r < R; ++r) {
-      double ah = 0.0, ah_abs = 0.0;
-      for (int s = 0; s < R; ++s) {
-        ah += A[q * R + s] * H[s * R + r];
-        ah_abs += fabs(A[q * R + s] * H[s * R + r]);
-      }
+      double ah = 0.0;
+      for (int s = 0; s < R; ++s) ah += A[q * R + s] * H[s * R + r];
       const int64_t e = q * R + r;
       G0[e] = -M[e] + ah;
-      const double d = ora_cd_delta(A[e], G0[e], H[r * R + r]);
-      delta[e] = d;
-      const double zz = ora_importance(G0[e], d, L);
-      z[e] = (float)zz; /* the decision is taken on the FP32 value */
-      ti += (double)z[e];
-      /* Width of the tie band: how far z moves when G0 carries a rounding
-       * error relative to the terms it is formed from, |M| + sum |A H|
-       * (eq. 14).  z = -g d - (L/2) d^2 (eq. 20); with a clipped step
-       * (d = -a, eq. 12) dz/dg = -d, with an interior one (d = -g/h, eq. 11)
-       * dz/dg = -d + g/h + L d/h, so |dz/dg| <= |d| + (|g| + L|d|)/h.  The
-       * last term covers the rounding of (L/2) d^2 itself. */
-      const double h = H[r * R + r];
-      const int interior = h > 0.0 && A[e] - G0[e] / h > 0.0;
-      const double dzdg = fabs(d) + (interior ? (fabs(G0[e]) + L * fabs(d)) / h : 0.0);
-      scale[e] = dzdg * (fabs(M[e]) + ah_abs) + 0.5 * L * d * d;
-      scale_sum += scale[e];
-      /* a zero entry whose gradient is within rounding of zero */
-      tie[e] = (A[e] == 0.0 && H[r * R + r] > 0.0 &&
-                fabs(G0[e]) <= tau * (fabs(M[e]) + ah_abs)) ? 1 : 0;
+      delta[e] = ora_cd_delta(A[e], G0[e], H[r * R + r]);
+      z[e] = ora_importance(G0[e], delta[e], L);
     }
   }
 
+  /* 6 */
+  double ti = 0.0;
+  for (size_t e = 0; e < IR; ++e) ti += z[e];
+
   /* 7 */
   int flip = 0;
-  int tie_global = 0;
   if (k >= 2) {
     flip = ti > m->ti_prev[mode]; /* "more than" (eq. 27 condition) */
-    tie_global = fabs(ti - m->ti_prev[mode]) <= tau * scale_sum;
     if (m->force_flip == 0 || m->force_flip == 1) flip = m->force_flip;
   }
   int64_t nsel = 0;
-  for (int64_t e = 0; e < I * R; ++e) {
+  for (size_t e = 0; e < IR; ++e) {
     sel[e] = (uint8_t)ora_select(k, z[e], zprev[e], flip);
     nsel += sel[e];
-    const double margin = (k <= 1) ? (double)z[e] : (double)z[e] - (double)zprev[e];
-    if (scale[e] > 0.0 && fabs(margin) <= tau * scale[e]) tie[e] = 1;
   }
 
   /* 8 */
-  memcpy(zprev, z, (size_t)I * R * sizeof(float));
+  const double ti_used = m->ti_prev[mode];
+  memcpy(m->zprev_used[mode], zprev, IR * sizeof(double));
+  memcpy(zprev, z, IR * sizeof(double));
   m->ti_prev[mode] = ti;
 
-  /* the state before the update, for ora_row_outcome */
-  memcpy(m->A_prev[mode], A, (size_t)I * R * sizeof(double));
-
   /* 9 */
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < I; ++q)
     update_row(A + q * R, sel + q * R, M + q * R, delta + q * R, H, R, m->update_rule);
   free(delta);
-  free(scale);
 
   /* 10 */
   gram(A, I, R, m->G[mode]);
 
   /* 11 */
   double inner = 0.0;
-  for (int64_t e = 0; e < I * R; ++e) inner += M[e] * A[e];
+  for (size_t e = 0; e < IR; ++e) inner += M[e] * A[e];
   double model = 0.0;
   for (int i = 0; i < R * R; ++i) model += m->G[0][i] * m->G[1][i] * m->G[2][i];
   const double f = t->norm2 - 2.0 * inner + model;
@@ -585,11 +607,106 @@ int ora_sweep(ora_model *m, int mode) {
   m->info[mode][0] = L;
   m->info[mode][1] = ti;
   m->info[mode][2] = (double)flip;
-  m->info[mode][3] = (double)tie_global;
+  m->info[mode][3] = ti_used;
   m->info[mode][4] = f;
   m->info[mode][5] = (double)nsel;
   m->info[mode][6] = inner;
   m->info[mode][7] = model;
+  record_tie_band(m, mode);
+  m->undo_ok[mode] = 1;
+  return ORA_OK;
+}
+
+int ora_sweep_undo(ora_model *m, int mode) {
+  if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
+  if (!m->undo_ok[mode]) return ORA_ESTATE;
+  const int64_t I = m->t->dims[mode];
+  const size_t IR = (size_t)I * m->R;
+  memcpy(m->A[mode], m->A_prev[mode], IR * sizeof(double));
+  gram(m->A[mode], I, m->R, m->G[mode]);
+  memcpy(m->zprev[mode], m->zprev_used[mode], IR * sizeof(double));
+  memcpy(m->band[mode], m->band_used[mode], IR * sizeof(double));
+  m->ti_prev[mode] = m->info[mode][3];
+  m->k[mode] -= 1;
+  m->undo_ok[mode] = 0;
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tie band (diagnostics of the tests; no step of the method reads it).      */
+/* ------------------------------------------------------------------------ */
+
+/* See ora_sweep_band in the header.  Sensitivity of z = -g d - (L/2) d^2
+ * (eq. 20) to its gradient g: with a clipped step (d = -a, eq. 12) dz/dg = a
+ * = |d|; with an interior one (d = -g/h, eq. 11) dz/dg = -d + g/h + L d/h, so
+ * |dz/dg| <= 2|d| + L|d|/h.  An interior z is quadratic in g, and near
+ * g = 0 its first-order term vanishes: an error e of g moves the step by up
+ * to |e|/h, so z may move by (tau T / h)^2 (h + L/2) as well; that
+ * second-order term is added to the band of every interior step.  A clipped
+ * step is linear in g (and exactly zero when a = 0), so it has none.  A
+ * zero-gradient tie (a = 0, g within tau T of zero) has z = 0 on one side of
+ * zero and that interior step on the other. */
+static void record_tie_band(ora_model *m, int mode) {
+  const int R = m->R;
+  const int64_t I = m->t->dims[mode];
+  const size_t IR = (size_t)I * R;
+  const double tau = m->tau, L = m->info[mode][0];
+  const int64_t k = m->k[mode];
+  const double *A = m->A_prev[mode], *H = m->H[mode], *M = m->M[mode], *G0 = m->G0[mode];
+  const double *z = m->z[mode], *zp = m->zprev_used[mode];
+  double *band = m->band[mode], *band_used = m->band_used[mode];
+  uint8_t *kind = m->kind[mode];
+  memcpy(band_used, band, IR * sizeof(double)); /* band of the Z^{k-1} just used */
+  double sum_band = 0.0, sum_used = 0.0;
+  int64_t n_zero = 0, n_grad = 0, n_margin = 0;
+  for (int64_t q = 0; q < I; ++q) {
+    for (int r = 0; r < R; ++r) {
+      const int64_t e = q * R + r;
+      const double h = H[r * R + r];
+      double T = fabs(M[e]);
+      for (int s = 0; s < R; ++s) T += fabs(A[q * R + s] * H[s * R + r]);
+      const double d = ora_cd_delta(A[e], G0[e], h);
+      const int interior = h > 0.0 && A[e] - G0[e] / h > 0.0;
+      const double dzdg = fabs(d) + (interior ? (fabs(G0[e]) + L * fabs(d)) / h : 0.0);
+      double bz = tau * (dzdg * T + 0.5 * L * d * d);
+      const int zero_grad = A[e] == 0.0 && h > 0.0 && T > 0.0 && fabs(G0[e]) <= tau * T;
+      if (interior || zero_grad) {
+        const double dd = tau * T / h;
+        bz += dd * dd * (h + 0.5 * L);
+      }
+      band[e] = bz;
+      const double margin = (k <= 1) ? z[e] : z[e] - zp[e];
+      const double width = (k <= 1) ? bz : bz + band_used[e];
+      if (zero_grad) {
+        kind[e] = 2;
+        ++n_grad;
+      } else if (width > 0.0 && fabs(margin) <= width) {
+        kind[e] = 3;
+        ++n_margin;
+      } else if (margin == 0.0) {
+        kind[e] = 1;
+        ++n_zero;
+      } else {
+        kind[e] = 0;
+      }
+      sum_band += bz;
+      sum_used += band_used[e];
+    }
+  }
+  const double band_ti = sum_band + sum_used;
+  m->band_info[mode][0] = band_ti;
+  m->band_info[mode][1] = (k >= 2 && fabs(m->info[mode][1] - m->info[mode][3]) <= band_ti) ? 1.0 : 0.0;
+  m->band_info[mode][2] = (double)n_zero;
+  m->band_info[mode][3] = (double)n_grad;
+  m->band_info[mode][4] = (double)n_margin;
+}
+
+int ora_sweep_band(const ora_model *m, int mode, double *band, uint8_t *kind, double *scalars) {
+  if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
+  const size_t IR = (size_t)m->t->dims[mode] * m->R;
+  if (band) memcpy(band, m->band[mode], IR * sizeof(double));
+  if (kind) memcpy(kind, m->kind[mode], IR);
+  if (scalars) memcpy(scalars, m->band_info[mode], sizeof(m->band_info[mode]));
   return ORA_OK;
 }
 
@@ -613,15 +730,13 @@ int ora_row_outcome(const ora_model *m, int mode, int64_t q, const uint8_t *sel,
 }
 
 int ora_sweep_info(const ora_model *m, int mode, double *M, double *G0,
-                   float *z, uint8_t *sel, uint8_t *tie, double *H,
-                   double *scalars) {
+                   double *z, uint8_t *sel, double *H, double *scalars) {
   if (!m || mode < 0 || mode > 2) return ORA_EINVAL;
   const size_t IR = (size_t)m->t->dims[mode] * m->R;
   if (M) memcpy(M, m->M[mode], IR * sizeof(double));
   if (G0) memcpy(G0, m->G0[mode], IR * sizeof(double));
-  if (z) memcpy(z, m->z[mode], IR * sizeof(float));
+  if (z) memcpy(z, m->z[mode], IR * sizeof(double));
   if (sel) memcpy(sel, m->sel[mode], IR);
-  if (tie) memcpy(tie, m->tie[mode], IR);
   if (H) memcpy(H, m->H[mode], (size_t)m->R * m->R * sizeof(double));
   if (scalars) memcpy(scalars, m->info[mode], sizeof(m->info[mode]));
   return ORA_OK;

@@ -53,7 +53,7 @@ void ora_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
 /* Single-coordinate pieces, exposed for the pins. */
 double ora_cd_delta(double a, double g, double h);          /* eq. 11-12 */
 double ora_importance(double g, double delta, double L);    /* eq. 20 */
-int ora_select(int64_t k, float z, float zprev, int flip);  /* eq. 24-27, Alg. 1 */
+int ora_select(int64_t k, double z, double zprev, int flip); /* eq. 24-27, Alg. 1 */
 
 enum { ORA_UPDATE_GS = 0, ORA_UPDATE_JACOBI = 1 };
 
@@ -64,31 +64,62 @@ int ora_model_create(const ora_tensor *t, int R, uint64_t seed, int update_rule,
 void ora_model_destroy(ora_model *m);
 int ora_model_get_factor(const ora_model *m, int mode, double *dst);
 int ora_model_set_factor(ora_model *m, int mode, const double *src);
-/* Selection state of one mode: previous importances (FP32, I_n x R), the
- * previous total importance and the per-mode sweep counter k. */
-int ora_model_get_state(const ora_model *m, int mode, float *zprev,
+/* Selection state of one mode: previous importances Z^{k-1} (I_n x R), the
+ * previous total importance ti^{k-1} and the per-mode sweep counter k.
+ * set_state takes the given Z^{k-1} as exact (its tie band is zero). */
+int ora_model_get_state(const ora_model *m, int mode, double *zprev,
                         double *ti_prev, int64_t *k);
-int ora_model_set_state(ora_model *m, int mode, const float *zprev,
+int ora_model_set_state(ora_model *m, int mode, const double *zprev,
                         double ti_prev, int64_t k);
 /* force_flip: -1 = decide from ti (normal), 0 / 1 = force the eq. 27 branch
  * off / on (used to enumerate both outcomes at a total-importance tie). */
 void ora_model_force_flip(ora_model *m, int force_flip);
-/* Relative width of the tie band used for the diagnostics (default 1e-6):
- * an element is a tie when its selection margin is at most tau times the
- * change of z that a relative error tau in the terms of its gradient would
- * cause (see ora_sweep). */
+/* Relative width tau of the tie band (default 1e-6), see ora_sweep_band. */
 void ora_model_set_tie_tol(ora_model *m, double tau);
+
+/* Threads of the oracle's parallel loops (OpenMP; loops whose iterations are
+ * independent, so every result is bit-identical for any thread count).
+ * n < 1 leaves the count unchanged.  Returns the count now in use (1 when
+ * built without OpenMP). */
+int ora_set_threads(int n);
 
 /* One SaCD sweep of mode n (Alg. 1 body for one factor matrix). */
 int ora_sweep(ora_model *m, int mode);
 
-/* Diagnostics of the last sweep of `mode`.  Any pointer may be NULL.
- * M, G0 (I_n x R FP64), z (FP32 as used in the decision), sel / tie (uint8
- * I_n x R), H (R x R), scalars: L, ti, flip, tie_global, f (objective after
- * the sweep), nsel. */
+/* Record of the last sweep of `mode`.  Any pointer may be NULL.
+ * M, G0, z (I_n x R), sel (uint8 I_n x R), H (R x R), scalars: L, ti, flip,
+ * ti_prev (the ti^{k-1} the selection compared with), f (objective after the
+ * sweep), nsel, inner <M, A_n>, model sum (G0 * G1 * G2). */
 int ora_sweep_info(const ora_model *m, int mode, double *M, double *G0,
-                   float *z, uint8_t *sel, uint8_t *tie, double *H,
-                   double *scalars /* [L, ti, flip, tie_global, f, nsel, inner, model] */);
+                   double *z, uint8_t *sel, double *H,
+                   double *scalars /* [L, ti, flip, ti_prev, f, nsel, inner, model] */);
+
+/* Tie band of the last sweep of `mode` (a diagnostic of the oracle, not part
+ * of the method).  The selection turns the sign of a difference of rounded
+ * values into a decision; where an implementation in lower precision may
+ * take either decision, both are correct.  For every element:
+ *   band   tau (|dz/dg| T + (L/2) d^2) + (tau T / h)^2 (h + L/2): how far
+ *          z moves when its gradient g carries an error of tau T, T = |M| +
+ *          sum_s |A_s H_sr| the terms g is formed from (eq. 14), d the step
+ *          (eq. 11-12); (L/2) d^2 covers the rounding of that term of z
+ *          (eq. 20), the last term (interior steps and zero-gradient ties
+ *          only) the second-order move of z near g = 0.
+ *   kind   0 decided (margin outside the band), 1 exact zero (z and Z^{k-1}
+ *          structurally zero: decided), 2 zero-gradient tie (a = 0 and
+ *          |g| <= tau T: the step is zero or not by the sign of g),
+ *          3 margin tie (|margin| <= band + band of Z^{k-1}).
+ * scalars: [band_ti = sum band + sum band of Z^{k-1}, tie_global (k >= 2 and
+ *           |ti - ti^{k-1}| <= band_ti), n_exact_zero, n_zero_grad,
+ *           n_margin]. */
+int ora_sweep_band(const ora_model *m, int mode, double *band, uint8_t *kind,
+                   double *scalars /* [5] */);
+
+/* Undo the last sweep of `mode`: restore the factor, its Gram matrix, Z^{k-1},
+ * ti^{k-1}, k and the tie band of Z^{k-1} to their values before that sweep
+ * (used to re-run a sweep with the other eq. 27 branch at a tie of the total
+ * importance).  BAD_STATE if the mode has not been swept since its state was
+ * last set. */
+int ora_sweep_undo(ora_model *m, int mode);
 
 /* The update (step 9 of ora_sweep) of row q of the last sweep of `mode`
  * under the decisions sel (R bytes, 1 = selected), from the state before that

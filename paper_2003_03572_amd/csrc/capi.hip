@@ -1040,6 +1040,17 @@ sacd_status sacd_get_stats(const sacd_model *m, int32_t mode, sacd_sweep_stats *
   return SACD_OK;
 }
 
+sacd_status sacd_get_column_counts(const sacd_model *m, int32_t mode, int64_t *counts) {
+  SACD_TRY(check_mode(m, mode));
+  if (!counts) return fail(SACD_ERR_INVALID_ARG, "counts is NULL");
+  SACD_TRY(enter(m->t->dev));
+  std::vector<long long> c((size_t)m->RP);
+  HIP_TRY(hipMemcpyAsync(c.data(), m->colcnt[mode], sizeof(long long) * m->RP, hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  for (int r = 0; r < m->R; ++r) counts[r] = (int64_t)c[(size_t)r];
+  return SACD_OK;
+}
+
 sacd_status sacd_get_diagnostics(const sacd_model *m, int32_t mode, float *mttkrp, uint8_t *selection,
                                  double *gram) {
   SACD_TRY(check_mode(m, mode));

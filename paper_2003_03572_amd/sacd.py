@@ -90,6 +90,7 @@ def lib():
             "sacd_get_state": [p, i32, p, p, p],
             "sacd_set_state": [p, i32, p, dbl, i64],
             "sacd_get_stats": [p, i32, p],
+            "sacd_get_column_counts": [p, i32, p],
             "sacd_get_diagnostics": [p, i32, p, p, p],
             "sacd_set_diagnostics": [p, i32],
             "sacd_time_kernel": [p, i32, i32, i32, p],
@@ -305,6 +306,13 @@ class Model:
         _check(lib().sacd_get_stats(self._h, mode, C.byref(s)), "sacd_get_stats")
         return dict(k=s.k, L=s.lipschitz, ti=s.ti, flip=bool(s.flip), nsel=s.n_selected,
                     f=s.objective)
+
+    def column_counts(self, mode: int) -> np.ndarray:
+        """|e_r|: elements of each column selected in the last sweep of `mode`."""
+        out = np.zeros(self.R, np.int64)
+        _check(lib().sacd_get_column_counts(self._h, mode, out.ctypes.data_as(C.c_void_p)),
+               "sacd_get_column_counts")
+        return out
 
     def set_diagnostics(self, on: bool):
         _check(lib().sacd_set_diagnostics(self._h, int(bool(on))), "sacd_set_diagnostics")

@@ -4,13 +4,19 @@ oracle on the same seeded inputs and compare them.
 Comparison rules (parity contract):
   * sort / slice pointers / initial factors: bit-exact;
   * MTTKRP: |M_gpu - M_oracle| <= 1e-5 |M_oracle| per entry;
-  * selection: equal on every element outside the oracle's tie band (the
-    decision margin within 1e-6 of the magnitude of the terms it is computed
-    from); a global tie of the total importance is resolved by re-running the
-    oracle with the branch the GPU took;
+  * the sweep counter k: exact; L = ||H||_F: within 1e-6 relative;
+  * importance z (eq. 20), element by element: within the oracle's tie band
+    of that element (the change of z that a relative error of 1e-6 in the
+    terms of its gradient causes; exact where the band is zero);
+  * total importance ti (eq. 25): within the sum of the elements' bands;
+  * selection: equal on every element the oracle does not mark as a tie
+    (zero-gradient or margin tie); at a global tie of ti both eq. 24 and
+    eq. 27 are valid and the oracle is re-run with the branch the GPU took;
+  * per-column selected counts |e_r|: equal to the column sums of the GPU's
+    selection;
   * factors: rows with no selected element are bit-identical; a row holding
-    tie elements must match the oracle's update of that row under the GPU's
-    decisions on those elements; otherwise
+    elements decided the other way inside the band must match the oracle's
+    update of that row under the GPU's decisions; otherwise
     |A_gpu - A_oracle| <= 1e-5 * s_q, where s_q is the largest magnitude of
     the terms of the row's Newton steps, (|M_qr| + sum_s |A_qs| H_sr) / H_rr:
     the step is the small difference of FP32 terms of that size;
@@ -25,6 +31,7 @@ RTOL_M = 1e-5
 RTOL_F = 1e-5
 RTOL_F_TERMS = 1e-6
 RTOL_A = 1e-5
+RTOL_L = 1e-6
 
 
 def gpu_tensor(sacd, dims, idx, vals):
@@ -36,31 +43,55 @@ def to_np(t: torch.Tensor) -> np.ndarray:
 
 
 def load_oracle_state_into_gpu(gm, om, modes=(0, 1, 2)):
-    """Round the oracle's factors to FP32, use them on both sides, and copy the
-    oracle's selection state (Z^{k-1}, ti^{k-1}, k) to the GPU model."""
+    """Round the oracle's factors and Z^{k-1} to FP32, use them on both
+    sides, and copy the oracle's ti^{k-1} and k to the GPU model."""
     for n in modes:
         A32 = om.factor(n).astype(np.float32)
         om.set_factor(n, A32.astype(np.float64))
         gm.set_factor(n, torch.from_numpy(A32).cuda())
         zp, ti, k = om.state(n)
-        gm.set_state(n, torch.from_numpy(zp).cuda(), ti, k)
+        zp32 = zp.astype(np.float32)
+        om.set_state(n, zp32.astype(np.float64), ti, k)
+        gm.set_state(n, torch.from_numpy(zp32).cuda(), ti, k)
 
 
-def snapshot(om, mode):
-    return [om.factor(n) for n in range(3)], om.state(mode)
+def load_gpu_factors_into_oracle(gm, om, modes=(0, 1, 2)):
+    """The GPU's factors into the oracle; the oracle keeps its own Z^{k-1},
+    ti^{k-1} and k."""
+    for n in modes:
+        om.set_factor(n, to_np(gm.factor(n)).astype(np.float64))
 
 
-def restore(om, snap, mode):
-    for n in range(3):
-        om.set_factor(n, snap[0][n])
-    zp, ti, k = snap[1]
-    om.set_state(mode, zp, ti, k)
+def load_gpu_state_into_oracle(gm, om, modes=(0, 1, 2), state_modes=(0, 1, 2)):
+    """The GPU's factors (all `modes`) and selection state (`state_modes`)
+    into the oracle."""
+    load_gpu_factors_into_oracle(gm, om, modes)
+    for n in state_modes:
+        zp, ti, k = gm.state(n)
+        om.set_state(n, to_np(zp).astype(np.float64), ti, k)
 
 
-def compare_sweep(gm, om, mode, A_old, where=""):
-    """Compare the last sweep of `mode` on both sides (A_old: the factor
-    before the sweep); returns counts for reporting."""
+def _rule(k, z, zp, flip):
+    """Alg. 1 selection (eq. 24 / eq. 27) on given values."""
+    if k <= 1:
+        return z > 0
+    return (zp - z > 0) if flip else (z - zp > 0)
+
+
+def compare_sweep(gm, om, mode, before, where=""):
+    """Compare the last sweep of `mode` on both sides (`before`: from
+    sweep_both, the factor and both sides' Z^{k-1} before the sweep).
+    Returns the tie and tolerance figures of the sweep."""
+    A_old, zp_o, zp_g = before
     info = om.info(mode)
+    st = gm.stats(mode)
+    I, R = A_old.shape
+    # sweep counter and Lipschitz constant
+    k_o = om.state(mode)[2]
+    assert st["k"] == k_o, f"{where} k mode {mode}: gpu {st['k']} oracle {k_o}"
+    assert abs(st["L"] - info["L"]) <= RTOL_L * info["L"], (
+        f"{where} L mode {mode}: {st['L']} vs {info['L']}")
+    # MTTKRP
     M_g, sel_g, G_g = gm.diagnostics(mode)
     M_g, sel_g = to_np(M_g).astype(np.float64), to_np(sel_g)
     M_o = info["M"]
@@ -68,18 +99,41 @@ def compare_sweep(gm, om, mode, A_old, where=""):
     bad = err > RTOL_M * np.abs(M_o) + 1e-30
     assert not bad.any(), (f"{where} MTTKRP mode {mode}: {bad.sum()} entries off, "
                            f"max rel {np.max(err / np.maximum(np.abs(M_o), 1e-300))}")
-    st = gm.stats(mode)
-    assert st["flip"] == info["flip"], f"{where} flip differs on mode {mode}"
-    tie, sel_o = info["tie"], info["sel"]
+    # importance z, element by element, within its band; ti within the sum
+    band = info["band"]
+    z_g = to_np(gm.state(mode)[0]).astype(np.float64)  # Z^{k-1} <- z of this sweep
+    dz = np.abs(z_g - info["z"])
+    badz = dz > band
+    assert not badz.any(), (
+        f"{where} importance mode {mode}: {int(badz.sum())} elements outside their band, first at "
+        f"{np.argwhere(badz)[:3].tolist()} (gpu {z_g[badz][:3]}, oracle {info['z'][badz][:3]}, "
+        f"band {band[badz][:3]})")
+    nzb = band > 0
+    z_ratio = float(np.max(dz[nzb] / band[nzb])) if nzb.any() else 0.0
+    ti_tol = float(np.sum(band)) + 1e-12 * float(np.sum(np.abs(info["z"])))
+    assert abs(st["ti"] - info["ti"]) <= ti_tol, (
+        f"{where} ti mode {mode}: gpu {st['ti']} oracle {info['ti']} (band {ti_tol})")
+    # eq. 27 branch and selection
+    if not info["tie_global"]:
+        assert st["flip"] == info["flip"], f"{where} flip differs on mode {mode}"
+    tie, sel_o, kind = info["tie"], info["sel"], info["kind"]
     diff = (sel_g != sel_o) & ~tie
     assert not diff.any(), (f"{where} selection mode {mode}: {diff.sum()} elements differ "
                             f"outside the tie band (first at {np.argwhere(diff)[:3].tolist()})")
+    # every GPU decision, ties included, is the rule on the GPU's own values
+    own = _rule(st["k"], z_g.astype(np.float32), zp_g.astype(np.float32), st["flip"])
+    assert np.array_equal(own, sel_g.astype(bool)), (
+        f"{where} selection mode {mode}: {int((own != sel_g.astype(bool)).sum())} GPU decisions "
+        f"differ from Alg. 1 on the GPU's own importances")
     assert st["nsel"] == int(sel_g.sum())
+    np.testing.assert_array_equal(gm.column_counts(mode), sel_g.sum(axis=0).astype(np.int64),
+                                  err_msg=f"{where} per-column counts mode {mode}")
 
     # the valid outcome that matches the GPU's decisions on tie elements
     A_o = om.factor(mode)
     A_valid = A_o.copy()
-    changed_rows = np.nonzero((sel_g != sel_o).any(axis=1))[0]
+    other = sel_g != sel_o
+    changed_rows = np.nonzero(other.any(axis=1))[0]
     for q in changed_rows:
         A_valid[q] = om.row_outcome(mode, int(q), sel_g[q].astype(np.uint8))
 
@@ -97,6 +151,15 @@ def compare_sweep(gm, om, mode, A_old, where=""):
     assert not badA.any(), (f"{where} factor mode {mode}: {badA.sum()} entries off, "
                             f"worst {np.max(errA / np.maximum(s_row[:, None], 1e-300))}")
     assert A_g.min() >= 0.0
+    # how the row bound compares with the bound relative to each column's max
+    colmax = np.max(np.abs(A_valid), axis=0)
+    moved = sel_g.any(axis=1)
+    sq_over_colmax = 0.0
+    colmax_ok = True
+    if moved.any() and colmax.max() > 0:
+        ratio = s_row[moved][:, None] / np.where(colmax > 0, colmax, np.inf)[None, :]
+        sq_over_colmax = float(np.max(ratio[np.isfinite(ratio)])) if np.isfinite(ratio).any() else 0.0
+        colmax_ok = bool(np.all(errA <= RTOL_A * colmax[None, :] + 1e-30))
 
     if len(changed_rows):
         om.set_factor(mode, A_valid)
@@ -109,23 +172,68 @@ def compare_sweep(gm, om, mode, A_old, where=""):
         f"{where} objective mode {mode}: {st['f']} vs {f_ref} (terms {S})")
     G_o = A_valid.T @ A_valid
     np.testing.assert_allclose(G_g, G_o, rtol=1e-5, atol=1e-6 * np.abs(G_o).max() + 1e-30)
-    return dict(ties=int(tie.sum()), tie_global=bool(info["tie_global"]),
-                tie_rows_other_outcome=int(len(changed_rows)))
+    # how far the importances moved since the previous sweep (median relative
+    # change over the elements where either is nonzero; k = 1: 1)
+    if st["k"] >= 2:
+        nz = (info["z"] != 0) | (zp_o != 0)
+        rel = np.abs(info["z"] - zp_o)[nz] / np.maximum(np.abs(info["z"]), np.abs(zp_o))[nz]
+        moved = float(np.median(rel)) if rel.size else 0.0
+    else:
+        moved = 1.0
+    return dict(elements=int(I * R), rows=int(I), ties=int(tie.sum()), z_moved=moved,
+                exact_zero=info["n_exact_zero"], zero_grad=info["n_zero_grad"],
+                margin=info["n_margin"], tie_global=bool(info["tie_global"]),
+                elements_other_decision=int(other.sum()),
+                tie_rows_other_outcome=int(len(changed_rows)),
+                z_over_band_max=z_ratio, sq_over_colmax=sq_over_colmax, colmax_bound_ok=colmax_ok,
+                f_rel=abs(st["f"] - f_ref) / max(abs(f_ref), 1e-300))
 
 
-def step_parity(gm, om, mode, where=""):
-    """One sweep of `mode` on both sides from the same state, then compare.
-    At a total-importance tie (both branches valid) the oracle is re-run with
-    the branch the GPU took."""
-    snap = snapshot(om, mode)
-    A_old = snap[0][mode]
+def sweep_both(gm, om, mode):
+    """One sweep of `mode` on both sides from their current states.  At a
+    global tie of the total importance (both branches valid) the oracle's
+    sweep is undone and re-run with the branch the GPU took.  Returns what
+    compare_sweep needs from before the sweep."""
+    A_old = om.factor(mode)
+    zp_o = om.state(mode)[0]
+    zp_g = to_np(gm.state(mode)[0])
     om.sweep(mode)
     gm.sweep(mode)
     info = om.info(mode)
     st = gm.stats(mode)
     if info["tie_global"] and st["flip"] != info["flip"]:
-        restore(om, snap, mode)
+        om.undo_sweep(mode)
         om.force_flip(int(st["flip"]))
         om.sweep(mode)
         om.force_flip(-1)
-    return compare_sweep(gm, om, mode, A_old, where)
+    return A_old, zp_o, zp_g
+
+
+def step_parity(gm, om, mode, where=""):
+    """One sweep of `mode` on both sides from the same state, then compare."""
+    before = sweep_both(gm, om, mode)
+    return compare_sweep(gm, om, mode, before, where)
+
+
+# Bounds on the figures of one sweep.
+#
+# Which elements are ties is a property of the iterate, computed by the
+# oracle alone: a margin tie is an element whose importance moved by less
+# than its band (1e-6 of the terms of z) since the previous sweep.  In a
+# moving iterate that is rare (a few elements per sweep); it becomes common
+# where the importance stands still -- after a sweep that selected almost
+# nothing (the importances then move by ~1e-6 relative), or in a column whose
+# h_rr has shrunk far below L, where z is dominated by (L/2) a^2 and moves with
+# L alone.  There the FP32 z cannot resolve the comparison of eq. 24 / eq. 27
+# and either decision is correct.  So the tie fraction is bounded loosely (it
+# stays below half of a mode in every workload measured) and reported.  What
+# depends on the GPU is how many ties it decides the other way: its error of z
+# must exceed the tie's margin, and that error stays below 0.7 of the band in
+# every test.
+MAX_TIE_FRACTION = 0.5          # tie elements / elements of the mode
+MAX_OTHER_OF_TIES = 0.30        # elements decided the other way / tie elements (+2)
+
+
+def assert_tie_bounds(rep, where=""):
+    assert rep["ties"] <= MAX_TIE_FRACTION * rep["elements"], (where, rep)
+    assert rep["elements_other_decision"] <= MAX_OTHER_OF_TIES * rep["ties"] + 2, (where, rep)

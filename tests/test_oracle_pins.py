@@ -441,3 +441,117 @@ def test_row_outcome_reproduces_the_sweep(oracle_mod):
         for q in range(dims[1]):
             np.testing.assert_array_equal(m.row_outcome(1, q, info["sel"][q]), A[q])
             np.testing.assert_array_equal(m.row_outcome(1, q, np.zeros(3, np.uint8)), A_prev[q])
+
+
+# ----------------------------------------- saturation state across sweeps --
+
+def _three_sweep_setup(O, update=0):
+    with open(os.path.join(GOLDEN, "saturation_three_sweeps.json")) as fh:
+        g = json.load(fh)
+    su = g["setup"]
+    idx = np.array([e[0] for e in su["entries"]], np.int32)
+    vals = np.array([e[1] for e in su["entries"]], np.float32)
+    T = O.Tensor(tuple(su["dims"]), idx, vals)
+    m = O.Model(T, su["R"], seed=0, update=update)
+    m.set_factor(0, np.array(su["U0"]))
+    m.set_factor(1, np.array(su["V"]))
+    return g, T, m
+
+
+def test_three_sweeps_carry_saturation_state(oracle_mod):
+    """Hand-worked three sweeps of one mode from the model's own state
+    (Alg. 1 with eq. 24-27; no state set from outside): z, ti, the eq. 27
+    branch, the selected set, the factor, the carried Z^{k-1}, ti^{k-1} and k,
+    and the objective, all exact (dyadic values)."""
+    g, T, m = _three_sweep_setup(oracle_mod)
+    for sw in g["sweeps"]:
+        m.set_factor(2, np.array(sw["W"]))
+        m.sweep(0)
+        info = m.info(0)
+        assert info["L"] == sw["L"]
+        np.testing.assert_array_equal(info["G0"], sw["G0"])
+        np.testing.assert_array_equal(info["z"], sw["z"])
+        assert info["ti"] == sw["ti"]
+        assert info["flip"] == sw["flip"]
+        np.testing.assert_array_equal(info["sel"].astype(int), sw["sel"])
+        np.testing.assert_array_equal(m.factor(0), sw["U"])
+        assert info["f"] == sw["f"]
+        zp, ti_prev, k = m.state(0)
+        assert k == sw["k"]
+        np.testing.assert_array_equal(zp, sw["z"])  # Z^{k-1} <- z for every element
+        assert ti_prev == sw["ti"]                   # ti^{k-1} <- ti (eq. 26)
+        assert info["nsel"] == int(np.sum(sw["sel"]))
+
+
+def test_state_carry_equals_resume_from_exported_state(oracle_mod):
+    """Sweeping from the model's own carry equals sweeping a fresh model given
+    the exported (Z^{k-1}, ti^{k-1}, k) and factors: the carry is the whole
+    state."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    a = oracle_mod.Model(T, 8, seed=42)
+    for it in range(3):
+        for n in range(3):
+            a.sweep(n)
+    b = oracle_mod.Model(T, 8, seed=1)
+    for n in range(3):
+        b.set_factor(n, a.factor(n))
+        zp, ti, k = a.state(n)
+        b.set_state(n, zp, ti, k)
+    for it in range(2):
+        for n in range(3):
+            a.sweep(n)
+            b.sweep(n)
+            np.testing.assert_array_equal(a.factor(n), b.factor(n))
+            assert a.info(n)["flip"] == b.info(n)["flip"]
+
+
+def test_threads_do_not_change_results(oracle_mod):
+    """The parallel loops add nothing across iterations: 1 thread and all
+    threads give bit-identical factors, importances and objectives."""
+    dims, idx, vals = gen.make(gen.ZIPF_UIT, scale=0.002)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    nthreads = oracle_mod.set_threads(0)
+    out = []
+    for nt in (1, max(nthreads, 2)):
+        oracle_mod.set_threads(nt)
+        m = oracle_mod.Model(T, 16, seed=5)
+        for it in range(2):
+            for n in range(3):
+                m.sweep(n)
+        out.append(([m.factor(n) for n in range(3)], m.info(2)["z"], m.info(2)["f"]))
+    oracle_mod.set_threads(nthreads)
+    for n in range(3):
+        np.testing.assert_array_equal(out[0][0][n], out[1][0][n])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][2] == out[1][2]
+
+
+def test_undo_sweep_restores_the_state(oracle_mod):
+    """Undoing a sweep and sweeping again gives the same sweep; undoing and
+    re-running with the other eq. 27 branch changes only the selection's
+    branch (used at a global tie of the total importance)."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    m = oracle_mod.Model(T, 8, seed=42)
+    for n in range(3):
+        m.sweep(n)
+    m.sweep(0)
+    a = (m.factor(0), m.state(0), m.info(0))
+    m.undo_sweep(0)
+    with pytest.raises(oracle_mod.OracleError):
+        m.undo_sweep(0)  # only the last sweep can be undone
+    assert m.state(0)[2] == 1
+    m.sweep(0)
+    b = (m.factor(0), m.state(0), m.info(0))
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1][0], b[1][0])
+    assert a[1][1:] == b[1][1:]
+    np.testing.assert_array_equal(a[2]["band"], b[2]["band"])
+    m.undo_sweep(0)
+    m.force_flip(int(not a[2]["flip"]))
+    m.sweep(0)
+    m.force_flip(-1)
+    c = m.info(0)
+    assert c["flip"] != a[2]["flip"]
+    np.testing.assert_array_equal(c["z"], a[2]["z"])

@@ -199,7 +199,7 @@ def run_many(args):
         return
     # serving
     rates = [float(x) for x in args.rates.split(",")]
-    sizes = [sum(sacd.job_bytes(dims, idx.shape[0], sp.rank)) for sp, dims, idx, vals in pool]
+    sizes = [sum(sacd.job_bytes(dims, idx.shape[0], sp.rank, prec)) for sp, dims, idx, vals in pool]
     budget = int(args.budget_mb * 2**20) if args.budget_mb > 0 else int(24 * np.mean(sizes))
     per_rate = {}
     for lam in rates:

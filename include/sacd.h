@@ -45,8 +45,11 @@ typedef enum {
 } sacd_status;
 
 /* Arithmetic of the dense R x R products (Gram matrices and A_n * H).
- * FP32: everything in FP32 (objective in FP64).  MIXED_BF16: Gram and A_n * H
- * on BF16 MFMA with FP32 accumulation; MTTKRP and updates stay FP32. */
+ * FP32: everything in FP32 (objective in FP64).  MIXED_BF16: the Grams that
+ * form H and the product A_n * H on BF16 MFMA with FP32 accumulation; MTTKRP
+ * and updates stay FP32; the objective (eq. 6) is formed in FP64 from Grams of
+ * FP32 operands, so the reported objective and fit are those of the factors
+ * as they are. */
 typedef enum { SACD_PREC_FP32 = 0, SACD_PREC_MIXED_BF16 = 1 } sacd_precision;
 
 /* Update of the selected elements (eq. 13).  GS: each selected element takes
@@ -274,10 +277,11 @@ typedef struct {
   double sec_admit, sec_tables, sec_iterate, sec_retire;
 } sacd_server_stats_t;
 
-/* Upper bounds of the device bytes of a job of this shape (host only, no GPU
- * call): *resident while it runs, *transient extra during its ingest. */
-sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, int64_t *resident,
-                           int64_t *transient);
+/* Upper bounds of the device bytes of a job of this shape and precision
+ * (host only, no GPU call): *resident while it runs, *transient extra during
+ * its ingest.  Errors: INVALID_ARG (sizes, rank, precision). */
+sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, sacd_precision prec,
+                           int64_t *resident, int64_t *transient);
 /* alloc, stream: as for sacd_create_tensor (every job's buffers come from
  * alloc; all work runs on the stream). */
 sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocator *alloc, void *stream,

@@ -171,6 +171,10 @@ struct sacd_model {
   bool diag = false;
   float *A[3] = {}, *Z[3] = {}, *M[3] = {}, *H[3] = {};
   double *G64[3] = {};
+  // mixed form: the objective's Grams (FP32 operands) beside the BF16 ones
+  // that form H; in the FP32 form G64o[n] == G64[n]
+  double *G64o[3] = {};
+  float *gpart_obj = nullptr;
   HInfo *hinfo[3] = {};
   ModeState *st = nullptr;  // 3 entries
   long long *colcnt[3] = {};
@@ -273,6 +277,7 @@ UpdArgs upd_args(const sacd_model *m, int n) {
   x.hi = m->hinfo[n];
   x.st = m->st + n;
   x.gpart = m->gpart;
+  x.gpart_obj = m->gpart_obj;
   x.inner_part = m->inner_part;
   x.cnt_part = m->cnt_part;
   x.selmask = m->selmask[n];
@@ -291,6 +296,10 @@ GramArgs gram_args(const sacd_model *m, int n, bool with_f) {
   x.Gn = m->G64[n];
   x.Ga = with_f ? m->G64[a] : nullptr;
   x.Gb = with_f ? m->G64[b] : nullptr;
+  x.gpart_obj = m->gpart_obj;
+  x.Gn_obj = m->gpart_obj ? m->G64o[n] : nullptr;
+  x.Ga_obj = m->gpart_obj && with_f ? m->G64o[a] : nullptr;
+  x.Gb_obj = m->gpart_obj && with_f ? m->G64o[b] : nullptr;
   x.inner_part = with_f ? m->inner_part : nullptr;
   x.cnt_part = with_f ? m->cnt_part : nullptr;
   x.colcnt = with_f ? m->colcnt[n] : nullptr;
@@ -320,7 +329,7 @@ sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr
 
 sacd_status recompute_gram(sacd_model *m, int n) {
   const int I = (int)m->t->dims[n];
-  HIP_TRY(launch_gram_partial(m->RP, is_bf16(m), I, m->A[n], m->gpart, m->s));
+  HIP_TRY(launch_gram_partial(m->RP, is_bf16(m), I, m->A[n], m->gpart, m->gpart_obj, m->s));
   HIP_TRY(launch_gram_final(m->RP, gram_args(m, n, false), m->s));
   return SACD_OK;
 }
@@ -375,7 +384,7 @@ sacd_status objective_full(sacd_model *m, double *f) {
   std::vector<double> G((size_t)3 * RP * RP);
   double inner = 0.0;
   for (int n = 0; n < 3; ++n)
-    HIP_TRY(hipMemcpyAsync(G.data() + (size_t)n * RP * RP, m->G64[n], sizeof(double) * RP * RP,
+    HIP_TRY(hipMemcpyAsync(G.data() + (size_t)n * RP * RP, m->G64o[n], sizeof(double) * RP * RP,
                            hipMemcpyDeviceToHost, m->s));
   HIP_TRY(hipMemcpyAsync(&inner, m->full_out, sizeof(double), hipMemcpyDeviceToHost, m->s));
   HIP_TRY(hipStreamSynchronize(m->s));
@@ -756,6 +765,8 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
     SACD_TRY(A.get_t((size_t)I * RP, &m->M[n]));
     SACD_TRY(A.get_t((size_t)RP * RP, &m->H[n]));
     SACD_TRY(A.get_t((size_t)RP * RP, &m->G64[n]));
+    if (m->prec == SACD_PREC_MIXED_BF16) SACD_TRY(A.get_t((size_t)RP * RP, &m->G64o[n]));
+    else m->G64o[n] = m->G64[n];
     SACD_TRY(A.get_t(1, &m->hinfo[n]));
     SACD_TRY(A.get_t((size_t)RP, &m->colcnt[n]));
     SACD_TRY(A.get_t((size_t)I * RP, &m->selmask[n]));
@@ -764,6 +775,7 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   SACD_TRY(A.get_t(3, &m->st));
   SACD_TRY(A.get_t((size_t)maxslots * RP, &m->part));
   SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart));
+  if (m->prec == SACD_PREC_MIXED_BF16) SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart_obj));
   // one importance partial per importance block (blocks of its own size)
   SACD_TRY(A.get_t((size_t)std::max(maxparts, importance_blocks(RP, (int)maxI)), &m->ti_part));
   SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
@@ -925,7 +937,7 @@ sacd_status sacd_pd(const sacd_model *m, int32_t mode, double *pd) {
   SACD_TRY(enter(m->t->dev));
   const int RP = m->RP, R = m->R;
   std::vector<double> G((size_t)RP * RP);
-  HIP_TRY(hipMemcpyAsync(G.data(), m->G64[mode], sizeof(double) * RP * RP, hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipMemcpyAsync(G.data(), m->G64o[mode], sizeof(double) * RP * RP, hipMemcpyDeviceToHost, m->s));
   HIP_TRY(hipStreamSynchronize(m->s));
   // cosine of columns i < r from the Gram matrix of the factor
   double sum = 0.0;
@@ -1185,7 +1197,7 @@ int pad_rank(int R) { return R <= 16 ? 16 : (R <= 32 ? 32 : (R <= 64 ? 64 : 128)
 
 // Upper bounds of the device bytes of a job: resident (tensor + model) and
 // the transient ingest buffers.
-void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int64_t *transient) {
+void job_bytes(const int64_t dims[3], int64_t nnz, int R, bool mixed, int64_t *resident, int64_t *transient) {
   const int RP = pad_rank(R);
   const int64_t slack = 64 * 1024;
   int64_t maxI = 0, maxunits = 0, ten = 0, mod = 0;
@@ -1203,6 +1215,7 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, int64_t *resident, int
   mod += al256(3 * sizeof(ModeState)) + al256(4 * maxunits * RP) + al256(4 * parts * RP * RP) +
          al256(8 * iparts) + al256(8 * parts) + al256(4 * parts * RP) + al256(8 * gram_model_parts(RP)) + al256(8 * 1024) +
          6 * 256;
+  if (mixed) mod += al256(4 * parts * RP * RP) + 3 * al256(8 * RP * RP);  // the objective's Gram partials and Grams
   int64_t tb = (int64_t)radix_sort_temp_bytes(nnz);
   tb = std::max(tb, (int64_t)dedup_temp_bytes(nnz));
   for (int n = 0; n < 3; ++n) tb = std::max(tb, (int64_t)build_ptr_temp_bytes(nnz, (int)dims[n]));
@@ -1624,11 +1637,13 @@ sacd_status retire(sacd_server *S, ServerJob &j, int state) {
 
 extern "C" {
 
-sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, int64_t *resident,
+sacd_status sacd_job_bytes(const int64_t dims[3], int64_t nnz, int32_t R, sacd_precision prec, int64_t *resident,
                            int64_t *transient) {
   if (!dims || nnz < 0 || R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  if (prec != SACD_PREC_FP32 && prec != SACD_PREC_MIXED_BF16)
+    return fail(SACD_ERR_INVALID_ARG, "unknown precision %d", (int)prec);
   int64_t a = 0, b = 0;
-  job_bytes(dims, nnz, R, &a, &b);
+  job_bytes(dims, nnz, R, prec == SACD_PREC_MIXED_BF16, &a, &b);
   if (resident) *resident = a;
   if (transient) *transient = b;
   return SACD_OK;
@@ -1692,7 +1707,7 @@ sacd_status sacd_server_submit(sacd_server *S, const int64_t dims[3], int64_t nn
   q.nnz = nnz;
   q.R = R;
   q.seed = seed;
-  job_bytes(dims, nnz, R, &q.est_resident, &q.est_transient);
+  job_bytes(dims, nnz, R, S->cfg.precision == SACD_PREC_MIXED_BF16, &q.est_resident, &q.est_transient);
   if (q.est_resident + q.est_transient > S->cfg.budget_bytes)
     return fail(SACD_ERR_NO_MEMORY, "job needs up to %lld bytes, more than the whole budget",
                 (long long)(q.est_resident + q.est_transient));

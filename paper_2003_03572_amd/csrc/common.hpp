@@ -178,6 +178,7 @@ struct UpdArgs {
   const HInfo *hi;
   const ModeState *st;
   float *gpart;
+  float *gpart_obj;  // mixed form: FP32 Gram partials for the objective (else nullptr)
   double *inner_part;
   int *cnt_part;
   uint8_t *selmask;
@@ -191,6 +192,12 @@ struct GramArgs {
   const double *inner_part;
   const int *cnt_part;
   long long *colcnt;
+  // mixed form: the objective's Grams, reduced from FP32 partials (gpart_obj)
+  // into Gn_obj; the other modes' objective Grams Ga_obj, Gb_obj.  nullptr in
+  // the FP32 form, where Gn, Ga, Gb serve both.
+  const float *gpart_obj;
+  double *Gn_obj;
+  const double *Ga_obj, *Gb_obj;
   double normX2;
   int with_f;
   unsigned *counter;    // arrival counter (zero between launches)
@@ -211,7 +218,10 @@ hipError_t launch_importance_b(int RP, bool bf, bool big, const ImpArgs *jobs, c
 hipError_t launch_select_update(int RP, int update, bool diag, bool bf, const UpdArgs &a, hipStream_t s);
 hipError_t launch_select_update_b(int RP, bool bf, bool big, const UpdArgs *jobs, const int4 *bmap, int nblocks,
                                   hipStream_t s);
-hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s);
+// bf: BF16 operands into gpart, and FP32 ones into gpart_obj when it is not
+// nullptr (mixed form); otherwise FP32 into gpart.
+hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, float *gpart_obj,
+                               hipStream_t s);
 hipError_t launch_gram_final(int RP, const GramArgs &a, hipStream_t s);
 hipError_t launch_gram_final_b(int RP, const GramArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 hipError_t launch_inner_full(const unsigned long long *keys0, const float *vals0, long long nnz,

@@ -580,6 +580,14 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
   // partial Gram matrix of the block's new rows (upper triangle of 16x16 tiles)
   // (sG is free again: it serves as the tiles' LDS scratch)
   gram_tiles<RP, Cf::RB, BF, Cf::W>(sA, gpart + (long long)blk * RP * RP, sG, wv, lane);
+  if constexpr (BF) {
+    // the objective's Gram from FP32 operands (eq. 6 in FP64 of the factors
+    // as they are, not of their BF16 roundings)
+    if (args.gpart_obj) {
+      __syncthreads();  // the scratch of the first pass is read until here
+      gram_tiles<RP, Cf::RB, false, Cf::W>(sA, args.gpart_obj + (long long)blk * RP * RP, sG, wv, lane);
+    }
+  }
   } while (0);
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
@@ -589,7 +597,8 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
 // Gram partials of an arbitrary factor (initialisation, set_factor).
 template <int RP, bool BF>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *__restrict__ A,
-                                                           float *__restrict__ gpart) {
+                                                           float *__restrict__ gpart,
+                                                           float *__restrict__ gpart_obj) {
   using Cf = UCfg<RP, upd_rows<RP>()>;
   constexpr int NUT = (RP / 16) * (RP / 16 + 1) / 2, P = Cf::RB / 64;
   __shared__ float sA[Cf::RB * Cf::STR];
@@ -598,6 +607,12 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(int I, const float *_
   load_rows<RP, Cf::RB>(sA, A, blockIdx.x * Cf::RB, I);
   __syncthreads();
   gram_tiles<RP, Cf::RB, BF>(sA, gpart + (long long)blockIdx.x * RP * RP, scratch, wv, lane);
+  if constexpr (BF) {
+    if (gpart_obj) {
+      __syncthreads();
+      gram_tiles<RP, Cf::RB, false>(sA, gpart_obj + (long long)blockIdx.x * RP * RP, scratch, wv, lane);
+    }
+  }
 }
 
 // Threads per block of the Gram reduction: 16 entries x kGramStripes.  One
@@ -688,6 +703,10 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
   double *Gn = args.Gn;
   const double *__restrict__ Ga = args.Ga;
   const double *__restrict__ Gb = args.Gb;
+  const float *__restrict__ gpart_obj = args.gpart_obj;
+  double *Gn_obj = args.Gn_obj;
+  const double *__restrict__ Ga_obj = args.Ga_obj;
+  const double *__restrict__ Gb_obj = args.Gb_obj;
   const double *__restrict__ inner_part = args.inner_part;
   const int *__restrict__ cnt_part = args.cnt_part;
   long long *__restrict__ colcnt = args.colcnt;
@@ -711,14 +730,22 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
     const int j = tj * 16 + e;
     const int x = i * RP + j;
     double wab = 0.0;
-    if (with_f && s == 0) wab = (ti == tj ? 1.0 : 2.0) * Ga[x] * Gb[x];  // issued early
+    if (with_f && s == 0)  // issued early
+      wab = (ti == tj ? 1.0 : 2.0) * (gpart_obj ? Ga_obj[x] * Gb_obj[x] : Ga[x] * Gb[x]);
     const double tot = stripe_tree(stripe_sum<double>(gpart + x, RR, s, nparts), red);
     if (s == 0) {
-      const double v = tot;
-      Gn[x] = v;
-      Gn[j * RP + i] = v;
-      if (with_f) red[tid] = v * wab;
+      Gn[x] = tot;
+      Gn[j * RP + i] = tot;
     }
+    double vobj = tot;
+    if (gpart_obj) {  // mixed form: the objective's Gram from the FP32 partials
+      vobj = stripe_tree(stripe_sum<double>(gpart_obj + x, RR, s, nparts), red);
+      if (s == 0) {
+        Gn_obj[x] = vobj;
+        Gn_obj[j * RP + i] = vobj;
+      }
+    }
+    if (with_f && s == 0) red[tid] = vobj * wab;
     if (with_f) {
       __syncthreads();
       if (tid == 0) {
@@ -1056,11 +1083,11 @@ struct UpdBL {
 
 template <int RP>
 struct GpL {
-  static hipError_t run(bool bf, int I, const float *A, float *gpart, hipStream_t s) {
+  static hipError_t run(bool bf, int I, const float *A, float *gpart, float *gpart_obj, hipStream_t s) {
     const int nb = update_blocks(RP, I);
     if (nb == 0) return hipSuccess;
-    if (bf) hipLaunchKernelGGL((k_gram_partial<RP, true>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
-    else hipLaunchKernelGGL((k_gram_partial<RP, false>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart);
+    if (bf) hipLaunchKernelGGL((k_gram_partial<RP, true>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart, gpart_obj);
+    else hipLaunchKernelGGL((k_gram_partial<RP, false>), dim3(nb), dim3(kThreads), 0, s, I, A, gpart, nullptr);
     return hipGetLastError();
   }
 };
@@ -1100,8 +1127,9 @@ hipError_t launch_select_update_b(int RP, bool bf, bool big, const UpdArgs *jobs
                                   hipStream_t s) {
   return rp_dispatch<UpdBL>(RP, bf, big, jobs, bmap, nblocks, s);
 }
-hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, hipStream_t s) {
-  return rp_dispatch<GpL>(RP, bf, I, A, gpart, s);
+hipError_t launch_gram_partial(int RP, bool bf, int I, const float *A, float *gpart, float *gpart_obj,
+                               hipStream_t s) {
+  return rp_dispatch<GpL>(RP, bf, I, A, gpart, gpart_obj, s);
 }
 hipError_t launch_gram_final(int RP, const GramArgs &a, hipStream_t s) { return rp_dispatch<GfL>(RP, a, s); }
 hipError_t launch_gram_final_b(int RP, const GramArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {

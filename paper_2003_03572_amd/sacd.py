@@ -98,7 +98,7 @@ def lib():
             "sacd_iterate_timed": [p, i32, p],
             "sacd_kernel_bytes": [p, i32, i32, p],
             "sacd_model_bytes": [p, p],
-            "sacd_job_bytes": [p, i64, i32, p, p],
+            "sacd_job_bytes": [p, i64, i32, C.c_int, p, p],
             "sacd_rmse": [p, i64, p, p, p],
             "sacd_pd": [p, i32, p],
             "sacd_server_create": [p, p, p, C.POINTER(p)],
@@ -375,11 +375,12 @@ class Model:
         self.t.stream.synchronize()
 
 
-def job_bytes(dims: Sequence[int], nnz: int, rank: int) -> Tuple[int, int]:
+def job_bytes(dims: Sequence[int], nnz: int, rank: int, precision: int = PREC_FP32) -> Tuple[int, int]:
     """Upper bounds (resident, transient) of the device bytes of a job."""
     d = (C.c_int64 * 3)(*[int(x) for x in dims])
     a, b = C.c_int64(), C.c_int64()
-    _check(lib().sacd_job_bytes(d, int(nnz), int(rank), C.byref(a), C.byref(b)), "sacd_job_bytes")
+    _check(lib().sacd_job_bytes(d, int(nnz), int(rank), int(precision), C.byref(a), C.byref(b)),
+           "sacd_job_bytes")
     return a.value, b.value
 
 

@@ -8,6 +8,7 @@ the MTTKRP stays at FP32 parity, factors stay finite and nonnegative, and
 the errors stay within the size BF16 rounding (2^-9 relative per operand)
 can explain."""
 import json
+import math
 
 import numpy as np
 import pytest
@@ -38,24 +39,34 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
-@pytest.mark.parametrize("case", ["small_r8", "uniform_r64"])
-def test_mixed_one_sweep_vs_oracle(sacd, oracle_mod, case):
-    """From the same state, one sweep of every mode on both sides."""
-    O = oracle_mod
-    if case == "small_r8":
-        w, scale, R = gen.SMALL_UNIFORM, 1.0, 8
-    else:
-        w, scale, R = gen.UNIFORM_20M_R64, 0.002, 64
-    dims, idx, vals = gen.make(w, scale)
+def _balanced(F):
+    """Factors with the scale of every rank-one component spread evenly over
+    the modes (CP factors are defined up to the column scales of each
+    component), so that factor errors compare the components themselves."""
+    norms = [np.linalg.norm(A, axis=0) for A in F]
+    lam = norms[0] * norms[1] * norms[2]
+    out = []
+    for A, nr in zip(F, norms):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sc = np.where(nr > 0, np.cbrt(lam) / nr, 0.0)
+        out.append(A * sc[None, :])
+    return out
+
+
+def mixed_sweep_report(sacd, O, dims, idx, vals, R, seed, warm_iters=1, case=""):
+    """From the same state (the oracle after warm_iters iterations, rounded to
+    FP32), one sweep of every mode on both sides; each result of the mixed
+    form against the FP64 oracle."""
     T_g = gpu_tensor(sacd, dims, idx, vals)
     T_o = O.Tensor(dims, idx, vals)
-    om = O.Model(T_o, R, seed=w.init_seed)
-    for n in range(3):  # move away from the initial point (k >= 2 state)
-        om.sweep(n)
-    gm = sacd.Model(T_g, R, seed=w.init_seed, precision=BF16)
+    om = O.Model(T_o, R, seed=seed)
+    for _ in range(warm_iters):  # move away from the initial point (k >= 2 state)
+        for n in range(3):
+            om.sweep(n)
+    gm = sacd.Model(T_g, R, seed=seed, precision=BF16)
     gm.set_diagnostics(True)
     load_oracle_state_into_gpu(gm, om)
-    report = {"case": case, "dims": list(dims), "nnz": int(idx.shape[0]), "R": R, "modes": []}
+    report = {"case": case, "dims": list(dims), "nnz": int(T_o.nnz), "R": R, "modes": []}
     for n in range(3):
         om.sweep(n)
         gm.sweep(n)
@@ -66,14 +77,17 @@ def test_mixed_one_sweep_vs_oracle(sacd, oracle_mod, case):
         A_o = om.factor(n)
         A_g = to_np(gm.factor(n)).astype(np.float64)
         assert np.all(np.isfinite(A_g)) and A_g.min() >= 0.0
+        z_g = to_np(gm.state(n)[0]).astype(np.float64)
         G_o = A_o.T @ A_o
-        _, f_g = gm.fit()
+        st = gm.stats(n)
         rec = {"mode": n,
                "mttkrp_max_rel": float(m_err),
+               "importance_rel": _rel(z_g, info["z"]),
+               "ti_rel": abs(st["ti"] - info["ti"]) / max(abs(info["ti"]), 1e-300),
                "selection_jaccard": _jaccard(to_np(sel_g).astype(bool), info["sel"]),
                "factor_rel": _rel(A_g, A_o),
                "gram_rel": _rel(G_g, G_o),
-               "f_rel": abs(f_g - info["f"]) / abs(info["f"])}
+               "f_rel": abs(st["f"] - info["f"]) / abs(info["f"])}
         report["modes"].append(rec)
         # MTTKRP is FP32 in both forms
         assert m_err <= RTOL_M, rec
@@ -81,10 +95,48 @@ def test_mixed_one_sweep_vs_oracle(sacd, oracle_mod, case):
         assert rec["gram_rel"] < 2e-2 and rec["f_rel"] < 5e-2, rec
         # resynchronise, so that every mode is measured from the oracle's state
         load_oracle_state_into_gpu(gm, om)
+    return report
+
+
+@pytest.mark.parametrize("case", ["small_r8", "uniform_r64", "uniform_r128"])
+def test_mixed_one_sweep_vs_oracle(sacd, oracle_mod, case):
+    """From the same state, one sweep of every mode on both sides."""
+    w, scale, R = {"small_r8": (gen.SMALL_UNIFORM, 1.0, 8),
+                   "uniform_r64": (gen.UNIFORM_20M_R64, 0.002, 64),
+                   "uniform_r128": (gen.UNIFORM_20M_R128, 0.002, 128)}[case]
+    dims, idx, vals = gen.make(w, scale)
+    report = mixed_sweep_report(sacd, oracle_mod, dims, idx, vals, R, w.init_seed, case=case)
     print("MIXED_VS_FP64", json.dumps(report))
 
 
-def test_mixed_trajectory_vs_oracle(sacd, oracle_mod):
+@pytest.mark.parametrize("case", ["small_r8", "zipf_r32", "uniform_r128"])
+def test_mixed_objective_is_that_of_its_factors(sacd, oracle_mod, case):
+    """The objective the mixed form reports (eq. 6, FP64 from Grams of FP32
+    operands) is the objective of the factors it holds: the FP64 oracle's
+    objective of those same factors agrees to 1e-5 relative, after every
+    iteration."""
+    w, scale, R = {"small_r8": (gen.SMALL_UNIFORM, 1.0, 8),
+                   "zipf_r32": (gen.ZIPF_UIT, 0.005, 32),
+                   "uniform_r128": (gen.UNIFORM_20M_R128, 0.002, 128)}[case]
+    dims, idx, vals = gen.make(w, scale)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    T_o = oracle_mod.Tensor(dims, idx, vals)
+    gm = sacd.Model(T_g, R, seed=w.init_seed, precision=BF16)
+    om = oracle_mod.Model(T_o, R, seed=w.init_seed)
+    worst = 0.0
+    for it in range(6):
+        gm.iterate(1)
+        fit_g, f_g = gm.fit()
+        for n in range(3):
+            om.set_factor(n, to_np(gm.factor(n)).astype(np.float64))
+        fit_o, f_o = om.fit()
+        rel = abs(f_g - f_o) / abs(f_o)
+        worst = max(worst, rel)
+        assert rel <= 1e-5, (case, it, f_g, f_o)
+    print(f"MIXED_OBJECTIVE {case}: worst f rel {worst:.2e} over 6 iterations")
+
+
+def test_mixed_trajectory_vs_oracle(sacd, oracle_mod):  # noqa: D103
     """Independent 20-iteration runs on the small uniform tensor: objective
     per iteration and final fit against the FP64 oracle, beside the FP32
     GPU path."""
@@ -115,6 +167,58 @@ def test_mixed_trajectory_vs_oracle(sacd, oracle_mod):
               "fit_oracle": fit_o, "fit_fp32": fit32, "fit_mixed": fitbf,
               "fit_diff_mixed": fitbf - fit_o,
               "factor_rel_mixed": [_rel(to_np(gbf.factor(n)).astype(np.float64), om.factor(n))
-                                   for n in range(3)]}
+                                   for n in range(3)],
+              "factor_rel_mixed_balanced": [
+                  _rel(b, a) for b, a in zip(_balanced([to_np(gbf.factor(n)).astype(np.float64) for n in range(3)]),
+                                             _balanced([om.factor(n) for n in range(3)]))]}
     print("MIXED_TRAJECTORY", json.dumps(report))
     assert abs(fitbf - fit_o) < 2e-2, report
+
+
+def mixed_trajectory_report(sacd, O, dims, idx, vals, R, seed, iters, case=""):
+    """Independent runs from the same initial factors: f and fit of the mixed
+    form, the FP32 form and the FP64 oracle after every iteration, and the
+    final factors (raw and with balanced component scales)."""
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    T_o = O.Tensor(dims, idx, vals)
+    om = O.Model(T_o, R, seed=seed)
+    g32 = sacd.Model(T_g, R, seed=seed)
+    gbf = sacd.Model(T_g, R, seed=seed, precision=BF16)
+    nx = math.sqrt(T_o.norm2)
+    rows = []
+    for it in range(iters):
+        for n in range(3):
+            om.sweep(n)
+        g32.iterate(1)
+        gbf.iterate(1)
+        f_o = om.info(2)["f"]
+        fit_o = 1.0 - math.sqrt(max(f_o, 0.0)) / nx
+        (fit32, f32_), (fitbf, fbf) = g32.fit(), gbf.fit()
+        rows.append({"iter": it + 1, "f_oracle": f_o, "f_rel_fp32": abs(f32_ - f_o) / abs(f_o),
+                     "f_rel_mixed": abs(fbf - f_o) / abs(f_o), "fit_oracle": fit_o,
+                     "fit_diff_fp32": fit32 - fit_o, "fit_diff_mixed": fitbf - fit_o})
+    Fo = [om.factor(n) for n in range(3)]
+    F32 = [to_np(g32.factor(n)).astype(np.float64) for n in range(3)]
+    Fbf = [to_np(gbf.factor(n)).astype(np.float64) for n in range(3)]
+    return {"case": case, "dims": list(dims), "nnz": int(T_o.nnz), "R": R, "iterations": rows,
+            "factor_rel_fp32": [_rel(a, b) for a, b in zip(F32, Fo)],
+            "factor_rel_mixed": [_rel(a, b) for a, b in zip(Fbf, Fo)],
+            "factor_rel_fp32_balanced": [_rel(a, b) for a, b in zip(_balanced(F32), _balanced(Fo))],
+            "factor_rel_mixed_balanced": [_rel(a, b) for a, b in zip(_balanced(Fbf), _balanced(Fo))],
+            "component_scale_ratio_mixed_mode0": float(np.max(np.linalg.norm(Fbf[0], axis=0) /
+                                                             np.maximum(np.linalg.norm(Fo[0], axis=0), 1e-300)))}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("case", ["zipf_r32", "uniform_r64", "uniform_r128"])
+def test_mixed_full_size_vs_fp64(sacd, oracle_mod, case):
+    """The bench tensors at full size: one sweep per mode from a shared state,
+    and a 10-iteration independent trajectory, of the mixed form against the
+    FP64 oracle (stated, with the FP32 path beside it)."""
+    w = {"zipf_r32": gen.ZIPF_UIT, "uniform_r64": gen.UNIFORM_20M_R64,
+         "uniform_r128": gen.UNIFORM_20M_R128}[case]
+    dims, idx, vals = gen.make(w)
+    rep = mixed_sweep_report(sacd, oracle_mod, dims, idx, vals, w.rank, w.init_seed, case=case)
+    print("MIXED_FULL_SWEEP", json.dumps(rep), flush=True)
+    tr = mixed_trajectory_report(sacd, oracle_mod, dims, idx, vals, w.rank, w.init_seed, 10, case=case)
+    print("MIXED_FULL_TRAJECTORY", json.dumps(tr), flush=True)

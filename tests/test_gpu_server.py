@@ -45,7 +45,7 @@ def _alone(sacd, dims, idx, vals, R, seed, precision):
 def _serve(sacd, jobs, budget, precision, max_slots=64):
     S = sacd.Server(budget, max_slots=max_slots, max_iter=MAX_ITER, tol=TOL, precision=precision)
     tickets = [S.submit(dims, idx, vals, R, seed) for (seed, dims, idx, vals, R) in jobs]
-    est = {t: sum(sacd.job_bytes(j[1], j[2].shape[0], j[4])) for t, j in zip(tickets, jobs)}
+    est = {t: sum(sacd.job_bytes(j[1], j[2].shape[0], j[4], precision)) for t, j in zip(tickets, jobs)}
     trace = []
     for _ in range(10_000):
         running, queued = S.step()
@@ -114,9 +114,10 @@ def test_oversized_job_is_refused(sacd):
     assert e.value.status == -3
 
 
-def test_actual_bytes_within_estimate(sacd):
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp32", "mixed_bf16"])
+def test_actual_bytes_within_estimate(sacd, prec):
     for (seed, dims, idx, vals, R) in _small_jobs(4, ranks=[8, 32, 64, 128]):
         T = sacd.Tensor.from_numpy(dims, idx, vals)
-        m = sacd.Model(T, R, seed=seed)
-        resident, _ = sacd.job_bytes(dims, idx.shape[0], R)
+        m = sacd.Model(T, R, seed=seed, precision=prec)
+        resident, _ = sacd.job_bytes(dims, idx.shape[0], R, prec)
         assert T.info()["device_bytes"] + m.device_bytes() <= resident

@@ -177,6 +177,22 @@ sacd_status sacd_set_factor(sacd_model *m, int32_t mode, const float *src);
 sacd_status sacd_rmse(sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *rmse);
 sacd_status sacd_pd(const sacd_model *m, int32_t mode, double *pd);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sacd_rmse
+ * without any allocation and without synchronising.  The same kernel runs on
+ * the model's stream with its scratch (1024 per-block partial sums, their
+ * total, a counter and a flag: 8.4 KiB) in a static device array of the
+ * library, one copy per device, kept until the process ends.
+ *   idx, vals  device, as for sacd_rmse; n in [0, 2^31 - 1] (larger n:
+ *              INVALID_ARG, nothing launched).
+ *   out        device, 2 doubles written asynchronously: out[0] the RMSE
+ *              (0 for n = 0; NaN if a coordinate is outside dims), out[1] 1.0
+ *              if a coordinate was outside dims, else 0.0.
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one GPU (other streams, other threads, other models) race and must be
+ * ordered by the caller.  Errors: INVALID_ARG, DEVICE. */
+sacd_status sacd_rmse_static(const sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *out);
+
 /* Selection state of one mode, for checkpoint / resume: zprev device
  * I_n x R FP32 (importance of the last sweep, Z^{k-1} of Alg. 1), ti_prev
  * (host, eq. 26) and k (host, sweeps done; k = 0 means Z is empty).

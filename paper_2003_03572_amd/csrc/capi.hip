@@ -395,6 +395,45 @@ sacd_status objective_full(sacd_model *m, double *f) {
   return SACD_OK;
 }
 
+// ---------------------------------------------------------------- static scratch --
+// The allocation-free entry point (sacd_rmse_static) keeps its scratch -- the
+// per-block partial sums of the squared errors, their total, the arrival
+// counter and the out-of-range flag -- in the file-scope device array
+// `scratch` below, one copy per device, instead of the model's buffers.  Host
+// code never passes the array's name to a kernel or a copy (on the host it is
+// only a stand-in): the array's device address is looked up once per device
+// with hipGetSymbolAddress and kept in g_scratch_ptr.
+
+constexpr int kStaticParts = 1024;                       // partial sums: one per block, at most
+constexpr long long kStaticMaxEntries = 2147483647LL;    // entries per call, at most
+constexpr size_t kStaticScratchBytes = (size_t)kStaticParts * 8 + 256;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current.  Looked up
+// once per device (at model set-up, else at the entry point's first call).
+sacd_status static_scratch(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(SACD_ERR_DEVICE, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SACD_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SACD_OK;
+}
+
 sacd_status check_mode(const sacd_model *m, int32_t mode) {
   if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
   if (mode < 0 || mode > 2) return fail(SACD_ERR_INVALID_ARG, "mode %d not in {0, 1, 2}", mode);
@@ -819,6 +858,8 @@ sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_pre
   if (update != SACD_UPDATE_GS && update != SACD_UPDATE_JACOBI)
     return fail(SACD_ERR_INVALID_ARG, "unknown update rule %d", (int)update);
   SACD_TRY(enter(t->dev));
+  void *scratch_dev = nullptr;  // set-up of the allocation-free entry point on this device
+  SACD_TRY(static_scratch(t->dev, &scratch_dev));
   sacd_model *m = new (std::nothrow) sacd_model();
   if (!m) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
   m->t = t;
@@ -928,6 +969,27 @@ sacd_status sacd_rmse(sacd_model *m, int64_t n, const int32_t *idx, const float 
   std::memcpy(&bad, m->h_pinned + 1, sizeof(int));
   if (bad) return fail(SACD_ERR_OUT_OF_RANGE, "a coordinate is outside the tensor's dims");
   *rmse = std::sqrt(m->h_pinned[0] / (double)n);
+  return SACD_OK;
+}
+
+sacd_status sacd_rmse_static(const sacd_model *m, int64_t n, const int32_t *idx, const float *vals, double *out) {
+  if (!m || !out || n < 0 || (n > 0 && (!idx || !vals))) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  if (n > kStaticMaxEntries)
+    return fail(SACD_ERR_INVALID_ARG, "n = %lld entries is beyond the maximum %lld of sacd_rmse_static", (long long)n,
+                kStaticMaxEntries);
+  SACD_TRY(enter(m->t->dev));
+  void *base = nullptr;
+  SACD_TRY(static_scratch(m->t->dev, &base));
+  double *part = (double *)base;           // kStaticParts partial sums
+  double *sum = part + kStaticParts;       // their total
+  unsigned *counter = (unsigned *)(sum + 1);
+  int *bad = (int *)(counter + 1);
+  // the arrival counter and the flag start at zero (the array keeps the last
+  // call's contents); a fill kernel, not a memset
+  HIP_TRY(launch_zero_words(counter, 2, m->s));
+  HIP_TRY(launch_sq_error(idx, vals, n, m->t->dims, m->RP, m->A[0], m->A[1], m->A[2], part, kStaticParts, sum,
+                          counter, bad, m->s));
+  HIP_TRY(launch_rmse_finish(sum, bad, n, out, m->s));
   return SACD_OK;
 }
 

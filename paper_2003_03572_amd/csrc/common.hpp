@@ -234,6 +234,8 @@ hipError_t launch_sq_error(const int32_t *idx, const float *vals, long long n, c
                            const float *A0, const float *A1, const float *A2, double *partials, int nparts,
                            double *out, unsigned *counter, int *bad, hipStream_t s);
 hipError_t launch_gather_f(const ModeState *const *sts, int n, double *out, hipStream_t s);
+hipError_t launch_zero_words(unsigned *p, int n, hipStream_t s);
+hipError_t launch_rmse_finish(const double *sum, const int *bad, long long n, double *out, hipStream_t s);
 hipError_t launch_check_factor(const float *src, long long n, int *flag, hipStream_t s);
 
 }  // namespace sacd

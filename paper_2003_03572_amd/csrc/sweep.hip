@@ -930,6 +930,25 @@ __global__ __launch_bounds__(kThreads) void k_sq_error(const int32_t *__restrict
   }
 }
 
+// Zero n 32-bit words: a fill kernel, so that code a caller captures into a
+// graph records no memset node.
+__global__ __launch_bounds__(kThreads) void k_zero_words(unsigned *__restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// eq. 30 from the sum of squared errors of n entries: out[0] = sqrt(sum / n)
+// (0 for n = 0), or NaN when a coordinate was outside dims; out[1] = 1 in
+// that case, else 0.  Correctly rounded division and square root.
+__global__ void k_rmse_finish(const double *__restrict__ sum, const int *__restrict__ bad, long long n,
+                              double *__restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int b = *bad;
+  out[0] = b ? __longlong_as_double(0x7ff8000000000000ll)
+             : (n > 0 ? __dsqrt_rn(__ddiv_rn(*sum, (double)n)) : 0.0);
+  out[1] = b ? 1.0 : 0.0;
+}
+
 // Objective of the last sweep of each of n jobs, gathered into one array.
 __global__ __launch_bounds__(kThreads) void k_gather_f(const ModeState *const *__restrict__ sts, int n,
                                                        double *__restrict__ out) {
@@ -1160,6 +1179,17 @@ hipError_t launch_sq_error(const int32_t *idx, const float *vals, long long n, c
   if (g > nparts) g = nparts;
   hipLaunchKernelGGL(k_sq_error, dim3((int)g), dim3(kThreads), 0, s, idx, vals, n, (int)dims[0], (int)dims[1],
                      (int)dims[2], RP, A0, A1, A2, partials, out, counter, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_words(unsigned *p, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rmse_finish(const double *sum, const int *bad, long long n, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_rmse_finish, dim3(1), dim3(64), 0, s, sum, bad, n, out);
   return hipGetLastError();
 }
 

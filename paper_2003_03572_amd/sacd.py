@@ -100,6 +100,7 @@ def lib():
             "sacd_model_bytes": [p, p],
             "sacd_job_bytes": [p, i64, i32, C.c_int, p, p],
             "sacd_rmse": [p, i64, p, p, p],
+            "sacd_rmse_static": [p, i64, p, p, p],
             "sacd_pd": [p, i32, p],
             "sacd_server_create": [p, p, p, C.POINTER(p)],
             "sacd_server_submit": [p, p, i64, p, p, i32, C.c_uint64, p],
@@ -336,6 +337,24 @@ class Model:
         out = C.c_double()
         _check(lib().sacd_rmse(self._h, idx.shape[0], _dptr(idx), _dptr(vals), C.byref(out)), "sacd_rmse")
         return out.value
+
+    def rmse_static(self, idx: torch.Tensor, vals: torch.Tensor, out: torch.Tensor):
+        """sacd_rmse_static: eq. 30 into out (device, 2 float64: RMSE, out-of-range
+        flag) on the model's stream, with no allocation and no synchronisation.
+        idx (n, 3) int32 and vals (n,) float32 are device tensors."""
+        if idx.dtype != torch.int32 or vals.dtype != torch.float32 or out.dtype != torch.float64:
+            raise TypeError("idx int32, vals float32, out float64")
+        if not (idx.is_cuda and vals.is_cuda and out.is_cuda) or out.numel() < 2:
+            raise ValueError("device tensors; out holds 2 values")
+        if not (idx.is_contiguous() and vals.is_contiguous() and out.is_contiguous()):
+            raise ValueError("contiguous tensors")
+        n = vals.numel()
+        if idx.numel() != 3 * n:
+            raise ValueError("idx is not n x 3")
+        dev = self.t.device
+        self.t.stream.wait_stream(torch.cuda.current_stream(dev))  # inputs ready
+        _check(lib().sacd_rmse_static(self._h, n, _dptr(idx), _dptr(vals), _dptr(out)), "sacd_rmse_static")
+        torch.cuda.current_stream(dev).wait_stream(self.t.stream)  # out ready for later torch work
 
     def pd(self, mode: int = 2) -> float:
         """Pattern distinctiveness (eq. pd) of the columns of factor `mode`."""

@@ -237,12 +237,14 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
  * outer iterations -- the same kernels, on the same stream, advancing the
  * model exactly like sacd_iterate(m, n_iters), but enqueued launch by launch
  * instead of replayed from the graph, with an event recorded right before
- * and right after each MTTKRP launch -- waits for them, and writes the MTTKRP
- * kernel duration of iteration i, mode n (milliseconds) to mttkrp_ms[3 i + n]
- * (host array of 3 n_iters floats).  BAD_STATE if events for fewer than
- * n_iters iterations were prepared.  The events live as long as the model. */
+ * and right after each MTTKRP launch and after each sweep's last kernel --
+ * waits for them, and writes the MTTKRP kernel duration of iteration i, mode
+ * n (milliseconds) to mttkrp_ms[3 i + n] and, when sweep_ms is not NULL, the
+ * duration of that whole sweep to sweep_ms[3 i + n] (host arrays of 3 n_iters
+ * floats).  BAD_STATE if events for fewer than n_iters iterations were
+ * prepared.  The events live as long as the model. */
 sacd_status sacd_timing_prepare(sacd_model *m, int32_t n_iters);
-sacd_status sacd_iterate_timed(sacd_model *m, int32_t n_iters, float *mttkrp_ms);
+sacd_status sacd_iterate_timed(sacd_model *m, int32_t n_iters, float *mttkrp_ms, float *sweep_ms);
 
 /* Algorithmic HBM bytes of one launch of kernel `which` (as in
  * sacd_time_kernel) for mode `mode` at the model's shapes (host). */

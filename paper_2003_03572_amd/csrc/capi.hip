@@ -191,7 +191,8 @@ struct sacd_model {
   MttkrpPlan plan[3];
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  // measurement: events recorded around the MTTKRP launches (6 per iteration)
+  // measurement: events recorded around the MTTKRP launches and at the end of
+  // every sweep (9 per iteration)
   std::vector<hipEvent_t> tev;
   double *h_pinned = nullptr;
   bool counted = false;  // included in t->nmodels
@@ -312,8 +313,9 @@ GramArgs gram_args(const sacd_model *m, int n, bool with_f) {
 
 bool is_bf16(const sacd_model *m) { return m->prec == SACD_PREC_MIXED_BF16; }
 
-// Enqueues one sweep of mode n on the model's stream.  mark (optional): two
-// events recorded right before and right after the MTTKRP launch.
+// Enqueues one sweep of mode n on the model's stream.  mark (optional): three
+// events recorded right before and right after the MTTKRP launch and after the
+// sweep's last kernel.
 sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr) {
   hipStream_t s = m->s;
   const bool bf = is_bf16(m);
@@ -324,6 +326,7 @@ sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr
   HIP_TRY(launch_importance(m->RP, bf, imp_args(m, n), s));
   HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, bf, upd_args(m, n), s));
   HIP_TRY(launch_gram_final(m->RP, gram_args(m, n, true), s));
+  if (mark) HIP_TRY(hipEventRecord(mark[2], s));
   return SACD_OK;
 }
 
@@ -908,7 +911,7 @@ sacd_status sacd_timing_prepare(sacd_model *m, int32_t n_iters) {
   if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
   if (n_iters < 1 || n_iters > 100000) return fail(SACD_ERR_INVALID_ARG, "n_iters out of [1, 100000]");
   SACD_TRY(enter(m->t->dev));
-  while ((int)m->tev.size() < 6 * n_iters) {
+  while ((int)m->tev.size() < 9 * n_iters) {
     hipEvent_t e;
     HIP_TRY(hipEventCreate(&e));
     m->tev.push_back(e);
@@ -916,21 +919,25 @@ sacd_status sacd_timing_prepare(sacd_model *m, int32_t n_iters) {
   return SACD_OK;
 }
 
-sacd_status sacd_iterate_timed(sacd_model *m, int32_t n_iters, float *mttkrp_ms) {
+sacd_status sacd_iterate_timed(sacd_model *m, int32_t n_iters, float *mttkrp_ms, float *sweep_ms) {
   if (!m || !mttkrp_ms) return fail(SACD_ERR_INVALID_ARG, "model or output is NULL");
-  if (n_iters < 1 || 6 * n_iters > (int)m->tev.size())
+  if (n_iters < 1 || 9 * n_iters > (int)m->tev.size())
     return fail(SACD_ERR_BAD_STATE, "sacd_timing_prepare was not called for %d iterations", (int)n_iters);
   SACD_TRY(enter(m->t->dev));
   for (int i = 0; i < n_iters; ++i)
-    for (int n = 0; n < 3; ++n) SACD_TRY(enqueue_sweep(m, n, &m->tev[6 * i + 2 * n]));
+    for (int n = 0; n < 3; ++n) SACD_TRY(enqueue_sweep(m, n, &m->tev[9 * i + 3 * n]));
   m->last_mode = 2;
   m->dirty = false;
   HIP_TRY(hipStreamSynchronize(m->s));
   for (int i = 0; i < n_iters; ++i)
     for (int n = 0; n < 3; ++n) {
       float ms = 0.0f;
-      HIP_TRY(hipEventElapsedTime(&ms, m->tev[6 * i + 2 * n], m->tev[6 * i + 2 * n + 1]));
+      HIP_TRY(hipEventElapsedTime(&ms, m->tev[9 * i + 3 * n], m->tev[9 * i + 3 * n + 1]));
       mttkrp_ms[3 * i + n] = ms;
+      if (sweep_ms) {
+        HIP_TRY(hipEventElapsedTime(&ms, m->tev[9 * i + 3 * n], m->tev[9 * i + 3 * n + 2]));
+        sweep_ms[3 * i + n] = ms;
+      }
     }
   return SACD_OK;
 }

@@ -95,7 +95,7 @@ def lib():
             "sacd_set_diagnostics": [p, i32],
             "sacd_time_kernel": [p, i32, i32, i32, p],
             "sacd_timing_prepare": [p, i32],
-            "sacd_iterate_timed": [p, i32, p],
+            "sacd_iterate_timed": [p, i32, p, p],
             "sacd_kernel_bytes": [p, i32, i32, p],
             "sacd_model_bytes": [p, p],
             "sacd_job_bytes": [p, i64, i32, C.c_int, p, p],
@@ -371,14 +371,19 @@ class Model:
         """Create the HIP events for n_iters timed iterations (see iterate_timed)."""
         _check(lib().sacd_timing_prepare(self._h, n_iters), "sacd_timing_prepare")
 
-    def iterate_timed(self, n_iters: int):
+    def iterate_timed(self, n_iters: int, sweeps: bool = False):
         """n_iters outer iterations, the same work as iterate() but enqueued
-        launch by launch with HIP events around the MTTKRP launches.  Waits
-        for them; returns the MTTKRP kernel milliseconds as a list of n_iters
-        [mode 0, 1, 2]."""
+        launch by launch with HIP events around the MTTKRP launches and at the
+        end of every sweep.  Waits for them; returns the MTTKRP kernel
+        milliseconds as a list of n_iters [mode 0, 1, 2], and with sweeps=True
+        also the whole sweeps' milliseconds in the same form."""
         out = (C.c_float * (3 * n_iters))()
-        _check(lib().sacd_iterate_timed(self._h, n_iters, out), "sacd_iterate_timed")
-        return [[out[3 * i + n] for n in range(3)] for i in range(n_iters)]
+        sw = (C.c_float * (3 * n_iters))()
+        _check(lib().sacd_iterate_timed(self._h, n_iters, out, sw), "sacd_iterate_timed")
+        mt = [[out[3 * i + n] for n in range(3)] for i in range(n_iters)]
+        if not sweeps:
+            return mt
+        return mt, [[sw[3 * i + n] for n in range(3)] for i in range(n_iters)]
 
     def kernel_bytes(self, which: int, mode: int) -> float:
         b = C.c_double()

@@ -369,8 +369,9 @@ def test_timed_iterations_equal_iterate(sacd):
     with pytest.raises(sacd.SacdError):
         b.iterate_timed(4)
     a.iterate(3)
-    ms = b.iterate_timed(3)
+    ms, sw = b.iterate_timed(3, sweeps=True)
     assert len(ms) == 3 and all(len(r) == 3 and all(0.0 < v < 1e3 for v in r) for r in ms)
+    assert all(sw[i][n] >= ms[i][n] for i in range(3) for n in range(3))
     for n in range(3):
         np.testing.assert_array_equal(to_np(a.factor(n)).view(np.uint32),
                                       to_np(b.factor(n)).view(np.uint32))

@@ -189,6 +189,7 @@ struct sacd_model {
   int full_nparts = 0;
   int nparts[3] = {0, 0, 0};
   MttkrpPlan plan[3];
+  int lds_cols[3] = {0, 0, 0};  // MTTKRP form per mode: A_b staged in LDS slabs of this many columns (0: plain)
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   // measurement: events recorded around the MTTKRP launches and at the end of
@@ -313,6 +314,17 @@ GramArgs gram_args(const sacd_model *m, int n, bool with_f) {
 
 bool is_bf16(const sacd_model *m) { return m->prec == SACD_PREC_MIXED_BF16; }
 
+// The MTTKRP of mode n: the LDS-staged form when A_b has few enough rows,
+// else the plain one (both give the same M bit for bit).
+hipError_t launch_mode_mttkrp(const sacd_model *m, int n, hipStream_t s) {
+  if (m->lds_cols[n] > 0) {
+    int a, b;
+    other_modes(n, &a, &b);
+    return launch_mttkrp_lds(m->RP, m->lds_cols[n], mttkrp_args(m, n), (int)m->t->dims[b], s);
+  }
+  return launch_mttkrp(m->RP, mttkrp_args(m, n), s);
+}
+
 // Enqueues one sweep of mode n on the model's stream.  mark (optional): three
 // events recorded right before and right after the MTTKRP launch and after the
 // sweep's last kernel.
@@ -320,7 +332,7 @@ sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr
   hipStream_t s = m->s;
   const bool bf = is_bf16(m);
   if (mark) HIP_TRY(hipEventRecord(mark[0], s));
-  HIP_TRY(launch_mttkrp(m->RP, mttkrp_args(m, n), s));
+  HIP_TRY(launch_mode_mttkrp(m, n, s));
   if (mark) HIP_TRY(hipEventRecord(mark[1], s));
   HIP_TRY(launch_mttkrp_fix(m->RP, fix_args(m, n), s));
   HIP_TRY(launch_importance(m->RP, bf, imp_args(m, n), s));
@@ -800,6 +812,11 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
     const int I = (int)t->dims[n];
     if (I > maxI) maxI = I;
     SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n]));
+    {
+      int a, b;
+      other_modes(n, &a, &b);
+      m->lds_cols[n] = mttkrp_lds_cols(RP, t->dims[b]);
+    }
     if (m->plan[n].nslots > maxslots) maxslots = m->plan[n].nslots;
     m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
     SACD_TRY(A.get_t((size_t)I * RP, &m->A[n]));
@@ -1179,7 +1196,7 @@ sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t
   HIP_TRY(hipEventRecord(e0, m->s));
   for (int i = 0; i < reps; ++i) {
     if (which == 0)
-      HIP_TRY(launch_mttkrp(m->RP, mttkrp_args(m, mode), m->s));
+      HIP_TRY(launch_mode_mttkrp(m, mode, m->s));
     else if (which == 1)
       HIP_TRY(launch_select_update(m->RP, (int)m->upd, m->diag, is_bf16(m), upd_args(m, mode), m->s));
     else

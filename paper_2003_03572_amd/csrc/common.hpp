@@ -153,6 +153,10 @@ struct FixArgs {
   ModeState *st;
 };
 hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s);
+// LDS-staged form (same M, bit for bit): CS columns of A_b (Ib rows) per slab;
+// mttkrp_lds_cols gives CS for a table of Ib rows, or 0 when it does not apply.
+int mttkrp_lds_cols(int RP, long long Ib);
+hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, hipStream_t s);
 hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 hipError_t launch_mttkrp_fix(int RP, const FixArgs &a, hipStream_t s);
 hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);

@@ -19,24 +19,33 @@ namespace sacd {
 
 namespace {
 
-// Columns per lane (compile-time tuning knob) and entries decoded per step.
-#ifndef SACD_MT_W
-#define SACD_MT_W 4
-#endif
-#ifndef SACD_MT_U
-#define SACD_MT_U 8
-#endif
-
+// Four columns per lane (one float4 of a row), eight entries decoded per
+// step (measured: 8 columns per lane and 10 or 12 entries per step were
+// slower).
 template <int RP>
 struct MCfg {
-  static constexpr int W = SACD_MT_W < RP ? SACD_MT_W : RP;  // columns per lane
-  static constexpr int LPN = RP / W;                           // lanes per unit
-  static constexpr int NV = W / 4;                             // float4 per lane
-  static constexpr int U = SACD_MT_U;
+  static constexpr int W = 4;          // columns per lane
+  static constexpr int LPN = RP / W;   // lanes per unit
+  static constexpr int NV = W / 4;     // float4 per lane
+  static constexpr int U = 8;          // entries per step
 };
 
 __device__ __forceinline__ f32x4 ld4(const float *p) { return *(const f32x4 *)p; }
 __device__ __forceinline__ void st4(float *p, f32x4 v) { *(f32x4 *)p = v; }
+
+// One entry's contribution to four columns: acc + x (a .* b) -- the product
+// a b rounded, then a fused multiply-add.  The plain kernel writes it as an
+// expression, which the compiler contracts to exactly that (v_mul, v_fmac);
+// the LDS-staged kernel spells the same two roundings with intrinsics (the
+// expression there was scheduled into 25% slower code).  Both give the same
+// sums bit for bit.
+__device__ __forceinline__ f32x4 entry_fma(float x, f32x4 a, f32x4 b, f32x4 acc) { return x * (a * b) + acc; }
+__device__ __forceinline__ f32x4 entry_fma_rn(float x, f32x4 a, f32x4 b, f32x4 acc) {
+  f32x4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = __fmaf_rn(x, __fmul_rn(a[i], b[i]), acc[i]);
+  return r;
+}
 
 // MTTKRP of one sweep.  Solo form (BATCHED false): block b is work item b
 // of the job in `solo`.  Job-batched form: a persistent grid loops over the
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
         for (int j = 0; j < NV; ++j) arow[j] = av[u][j];
       }
 #pragma unroll
-      for (int j = 0; j < NV; ++j) acc[j] = xc[u] * (arow[j] * bv[u][j]) + acc[j];
+      for (int j = 0; j < NV; ++j) acc[j] = entry_fma(xc[u], arow[j], bv[u][j], acc[j]);
     }
     // batch k + 1 is shared after the products of batch k: sharing it
     // before them keeps its registers live across them and costs a wave
@@ -207,7 +216,7 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
       }
       if (e + u < len) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) acc[j] = xv[u] * (arow[j] * bv[u][j]) + acc[j];
+        for (int j = 0; j < NV; ++j) acc[j] = entry_fma(xv[u], arow[j], bv[u][j], acc[j]);
       }
     }
   }
@@ -242,6 +251,158 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
  }
+}
+
+// MTTKRP with the per-entry table A_b staged in LDS, CS of its columns at a
+// time (a column slab; S = RP / CS slabs), for modes whose A_b has few rows.
+// Each entry then gathers only its A_a row chunk through the vector memory
+// path; its A_b row chunk is read from LDS.  A block of kLdsThreads threads
+// runs one slab of one block of kLdsUnits(CS) consecutive units of the plan,
+// with CS / 4 lanes per unit: the lanes own the same four columns and add the
+// same products in the same order as in k_mttkrp (entry_fma), and the split
+// slices' runs -- which never span the plain kernel's blocks of units, and the
+// block here covers a whole number of those -- are summed in the same unit
+// order, so M is bit for bit that of k_mttkrp.  The S slab blocks of a unit
+// block are numbered so that they go to one XCD one after the other, and the
+// entry stream they all read is fetched from HBM about once.
+constexpr int kLdsThreads = 1024;
+constexpr int kLdsU = 6;  // entries per step: 1024 threads leave 128 VGPRs per lane (measured: 4, 6, 8 at 512 to 1024 threads)
+constexpr long long kLdsTableBytes = 128 * 1024;  // the A_b slab; the run sums add 16 KB
+
+template <int RP, int CS>
+__global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int Ib, int nub) {
+  constexpr int S = RP / CS, LPN = CS / 4, UPB = kLdsThreads / LPN, U = kLdsU;
+  extern __shared__ __align__(16) float smem[];  // A_b slab (Ib x CS), then UPB x CS run sums
+  __shared__ int s_slot[UPB];
+  // block -> (unit block, slab); blocks are dealt to the 8 XCDs round robin
+  const int bx = blockIdx.x & 7, bk = blockIdx.x >> 3;
+  const int ublk = 8 * (bk / S) + bx, slab = bk % S;
+  if (ublk >= nub) return;  // the whole block, before any barrier
+  const int c0 = slab * CS;
+  const unsigned long long *__restrict__ keys = args.keys;
+  const float *__restrict__ vals = args.vals;
+  const float *__restrict__ Aa = args.Aa;
+  const float *__restrict__ Ab = args.Ab;
+  float *__restrict__ M = args.M;
+  float *__restrict__ part = args.part;
+  float *sB = smem;
+  float *s_acc = smem + (size_t)Ib * CS;
+  for (int i = threadIdx.x; i < Ib * (CS / 4); i += kLdsThreads) {
+    const int r = i / (CS / 4), q = i % (CS / 4);
+    st4(sB + (size_t)r * CS + 4 * q, ld4(Ab + (long long)r * RP + c0 + 4 * q));
+  }
+  __syncthreads();
+  const int ub = threadIdx.x / LPN;
+  const int gid = ublk * UPB + ub;
+  const bool active = gid < args.nunits;
+  const int sub = threadIdx.x % LPN;
+  const int4 unit = active ? args.units[gid] : make_int4(0, 0, 0, -1);
+  const long long p0 = unit.y;
+  const int len = unit.z;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f}, arow = acc;
+  const KeyLayout lay = args.lay;
+  const unsigned mb = (unsigned)lay.mask_b, ma = (unsigned)lay.mask_a, sha = (unsigned)lay.sh_a;
+  const char *__restrict__ Aa_l = (const char *)(Aa + c0 + 4 * sub);
+  const float *sB_l = sB + 4 * sub;
+  constexpr int kRowShift = RP == 16 ? 6 : (RP == 32 ? 7 : (RP == 64 ? 8 : 9));
+  static_assert((1 << kRowShift) == 4 * RP, "row size");
+  unsigned fa = ~0u;
+  constexpr int KPL = (U + LPN - 1) / LPN;
+  static_assert(2 * U <= kKeySlack, "raw loads run up to 2U - 1 entries past the unit");
+  const int gb4 = (int)((threadIdx.x & 63u) & ~(unsigned)(LPN - 1)) * 4;
+  unsigned long long rk[KPL];
+  float rx[KPL];
+  unsigned ib[U], ia[U];
+  float xv[U];
+#define SACD_MT_LOAD_RAW(q)                                              \
+  _Pragma("unroll") for (int k = 0; k < KPL; ++k) {                      \
+    if (sub + LPN * k < U) {                                             \
+      rk[k] = keys[p0 + (q) + sub + LPN * k];                            \
+      rx[k] = vals[p0 + (q) + sub + LPN * k];                            \
+    }                                                                    \
+  }
+#define SACD_MT_SHARE_RAW()                                                              \
+  {                                                                                      \
+    unsigned dib[KPL], dia[KPL];                                                         \
+    _Pragma("unroll") for (int k = 0; k < KPL; ++k) {                                    \
+      const unsigned lo = (unsigned)rk[k], hi = (unsigned)(rk[k] >> 32);                 \
+      dib[k] = lo & mb;                                                                  \
+      dia[k] = __builtin_amdgcn_alignbit(hi, lo, sha) & ma;                              \
+    }                                                                                    \
+    _Pragma("unroll") for (int u = 0; u < U; ++u) {                                      \
+      const int src = gb4 + 4 * (u % LPN);                                               \
+      ib[u] = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)dib[u / LPN]);            \
+      ia[u] = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)dia[u / LPN]);            \
+      xv[u] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(rx[u / LPN]))); \
+    }                                                                                    \
+  }
+  SACD_MT_LOAD_RAW(0)
+  SACD_MT_SHARE_RAW()
+  SACD_MT_LOAD_RAW(U)
+  int e = 0;
+  for (; e + U <= len; e += U) {
+    bool nf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      nf[u] = ia[u] != fa;
+      fa = ia[u];
+    }
+    f32x4 bv[U], av[U];
+    float xc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (nf[u]) av[u] = ld4((const float *)(Aa_l + ((size_t)ia[u] << kRowShift)));
+      bv[u] = *(const f32x4 *)(sB_l + (size_t)ib[u] * CS);
+      xc[u] = xv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (nf[u]) arow = av[u];
+      acc = entry_fma_rn(xc[u], arow, bv[u], acc);
+    }
+    SACD_MT_SHARE_RAW()
+    SACD_MT_LOAD_RAW(e + 2 * U)
+  }
+#undef SACD_MT_LOAD_RAW
+#undef SACD_MT_SHARE_RAW
+  if (e < len) {
+    f32x4 bv[U], av[U];
+    bool nf[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = e + u < len;
+      nf[u] = ok && ia[u] != fa;
+      if (ok) fa = ia[u];
+      if (ok) bv[u] = *(const f32x4 *)(sB_l + (size_t)ib[u] * CS);
+      if (nf[u]) av[u] = ld4((const float *)(Aa_l + ((size_t)ia[u] << kRowShift)));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (nf[u]) arow = av[u];
+      if (e + u < len) acc = entry_fma_rn(xv[u], arow, bv[u], acc);
+    }
+  }
+  if (active && unit.w < 0) {
+    st4(M + (long long)unit.x * RP + c0 + 4 * sub, acc);
+  } else {
+    st4(&s_acc[ub * CS + 4 * sub], acc);
+  }
+  if (sub == 0) s_slot[ub] = active ? unit.w : -1;
+  __syncthreads();
+  for (int c = threadIdx.x; c < CS; c += kLdsThreads) {
+    int run = -1;
+    float sum = 0.0f;
+    for (int q = 0; q < UPB; ++q) {
+      const int w = s_slot[q];
+      if (w != run) {
+        if (run >= 0) part[(long long)run * RP + c0 + c] = sum;
+        run = w;
+        sum = 0.0f;
+      }
+      if (w >= 0) sum += s_acc[q * CS + c];
+    }
+    if (run >= 0) part[(long long)run * RP + c0 + c] = sum;
+  }
 }
 
 }  // namespace
@@ -402,6 +563,45 @@ struct FxBL {
 };
 
 }  // namespace
+
+// Columns per slab of the LDS-staged form for a per-entry table of Ib rows,
+// or 0 for the plain kernel.  The staged form pays where the row gathers
+// dominate: at RP >= 64, with slabs of 64 columns (one pass at RP = 64, two at
+// 128) whose Ib rows fit kLdsTableBytes.  At RP <= 32 every entry's key and
+// value handling, repeated per slab, outweighs the 128-byte gather it saves
+// (measured 1.7-1.9x slower on the 1e7-entry Zipf tensor at R = 32).
+int mttkrp_lds_cols(int RP, long long Ib) {
+  if (RP < 64) return 0;
+  return Ib * 64 * 4 <= kLdsTableBytes ? 64 : 0;
+}
+
+template <int RP, int CS>
+static hipError_t launch_lds(const MttkrpArgs &a, int Ib, hipStream_t s) {
+  constexpr int UPB = kLdsThreads / (CS / 4);
+  static_assert(UPB % (kThreads / MCfg<RP>::LPN) == 0, "a block covers whole blocks of the plain kernel");
+  const int nub = (a.nunits + UPB - 1) / UPB;
+  if (nub == 0) return hipSuccess;
+  const int S = RP / CS;
+  const int nb = 8 * S * ((nub + 7) / 8);
+  const size_t shm = ((size_t)Ib * CS + (size_t)UPB * CS) * sizeof(float);
+  if ((long long)Ib * CS * 4 > kLdsTableBytes) return hipErrorInvalidValue;
+  // more dynamic LDS than the default limit: allowed once per kernel
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void *>(&k_mttkrp_lds<RP, CS>), hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(kLdsTableBytes + (long long)UPB * CS * sizeof(float)));
+  if (attr != hipSuccess) return attr;
+  hipLaunchKernelGGL((k_mttkrp_lds<RP, CS>), dim3(nb), dim3(kLdsThreads), shm, s, a, Ib, nub);
+  return hipGetLastError();
+}
+
+hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, hipStream_t s) {
+  if (CS != 64) return hipErrorInvalidValue;
+  switch (RP) {
+    case 64: return launch_lds<64, 64>(a, Ib, s);
+    case 128: return launch_lds<128, 64>(a, Ib, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 int mttkrp_blocks(int RP, int nunits) {
   const int upb = mttkrp_units_per_block(RP);

@@ -166,9 +166,10 @@ def run_tensor(sacd, gen, w, prec, args, with_cpu: bool):
     nnz = T.nnz
     torch.cuda.synchronize()
     t_ingest = time.perf_counter() - t0
-    m = sacd.Model(T, w.rank, seed=w.init_seed, precision=prec)
+    m = sacd.Model(T, w.rank, seed=w.init_seed, precision=prec, columns=args.columns)
     m.synchronize()
-    log(f"[bench] GPU ingest {t_ingest:.3f} s (incl. host->device copy), model ready")
+    log(f"[bench] GPU ingest {t_ingest:.3f} s (incl. host->device copy), model ready "
+        f"({m.device_bytes() / 2**20:.1f} MiB of model state)")
 
     stream = T.stream
     m.iterate(args.warmup)
@@ -216,7 +217,7 @@ def run_tensor(sacd, gen, w, prec, args, with_cpu: bool):
 
     # other kernels, timed after the region (HIP events on the library stream)
     ktimes = {}
-    for which, name in [(2, "importance"), (1, "select_update")]:
+    for which, name in ([(2, "importance"), (1, "select_update")] if not args.columns else []):
         for n in range(3):
             ktimes[(name, n)] = m.time_kernel(which, n, args.kernel_reps)
     for n in range(3):
@@ -274,9 +275,13 @@ def run_tensor(sacd, gen, w, prec, args, with_cpu: bool):
                    "kernel_us": {f"{k[0]}_mode{k[1]}": round(1e3 * v, 2) for k, v in ktimes.items()},
                    # algorithmic bytes of each launch over its measured time
                    "kernel_gbps_algorithmic": kernel_gbps,
-                   "ingest_s_incl_upload": t_ingest},
+                   "ingest_s_incl_upload": t_ingest,
+                   "model_device_bytes": m.device_bytes()},
         "roofline": roof,
     }
+    if args.columns:
+        out["config"]["form"] = (f"column-at-a-time, {args.columns} columns per block: the MTTKRP interval covers "
+                                 f"both passes over the column blocks")
     if prec != sacd.PREC_FP32:
         out["config"]["precision"] = "mixed: Gram and A*H on BF16 MFMA, FP32 accumulation"
         out["config"]["vs_fp32_gpu"] = mixed_vs_fp32(sacd, T, w, m, args.warmup + 2 * args.steps)
@@ -506,6 +511,8 @@ def main():
     ap.add_argument("--rates", default="50,200,800", help="serving: arrival rates (1/s)")
     ap.add_argument("--budget-mb", type=float, default=0.0,
                     help="serving: HBM budget of the server (MB); 0 picks one that binds at the top rate")
+    ap.add_argument("--columns", type=int, default=0,
+                    help="tensor workloads: the column-at-a-time form with blocks of this many columns")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline: skip the Zipf and serving legs")
     ap.add_argument("--cpu-budget", type=float, default=10.0)

@@ -136,6 +136,24 @@ void sacd_destroy_tensor(sacd_tensor *t);
 sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
                               sacd_update update, sacd_model **out);
 
+/* A model in the column-at-a-time form (Sec. 4.4, Alg. 2: the MTTKRP formed a
+ * column block at a time, as the paper's "sparse tensor times vector" column
+ * form does one column at a time): every sweep forms M in blocks of
+ * column_block columns -- once for the importances of all elements (whose
+ * total ti, eq. 25, is needed before any update), and once more per block,
+ * in ascending column order, right before the Gauss-Seidel steps of that
+ * block's selected elements -- so the model holds an I_n x column_block block
+ * of M instead of three I_n x R buffers (and no per-element selection record
+ * unless diagnostics are on).  The sweeps compute what sacd_init_factors'
+ * models compute (same selection rule and steps; sums in another order), at
+ * the cost of two passes over the entries per column block.  FP32,
+ * Gauss-Seidel; other arguments as sacd_init_factors.  column_block in
+ * {1, 2, 4, 8, 16}, else INVALID_ARG.  Kernel timing (sacd_time_kernel) is
+ * not available for such a model (BAD_STATE); sacd_iterate_timed's MTTKRP
+ * interval covers both passes. */
+sacd_status sacd_init_factors_columns(sacd_tensor *t, int32_t R, uint64_t seed, int32_t column_block,
+                                      sacd_model **out);
+
 /* Enqueue one SaCD sweep of mode `mode` in {0, 1, 2} (Alg. 1 body for one
  * factor matrix: MTTKRP, H and L, gradient and importance eq. 14 / eq. 20,
  * total importance eq. 25, selection eq. 24 / eq. 27, update eq. 11-13,

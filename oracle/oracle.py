@@ -77,6 +77,8 @@ def lib():
         L.ora_sweep_info.argtypes = [p, i32, p, p, p, p, p, p]
         L.ora_sweep_band.argtypes = [p, i32, p, p, p]
         L.ora_sweep_undo.argtypes = [p, i32]
+        L.ora_sttvp.argtypes = [p, i32, i32, i32, p, p, p, p]
+        L.ora_model_set_columns.argtypes = [p, i32]
         L.ora_set_threads.argtypes = [i32]
         L.ora_set_threads.restype = i32
         L.ora_row_outcome.argtypes = [p, i32, i64, p, p]
@@ -144,6 +146,15 @@ class Tensor:
         _check(lib().ora_tensor_mode_coo(self._h, mode, _ptr(coords), _ptr(vals), _ptr(ptr)),
                "ora_tensor_mode_coo")
         return coords, vals, ptr
+
+    def sttvp(self, mode: int, r: int, factors) -> np.ndarray:
+        """Column r of the MTTKRP of `mode` (Sec. 4.4 column form)."""
+        R = factors[0].shape[1]
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+        m = np.empty(self.dims[mode], np.float64)
+        _check(lib().ora_sttvp(self._h, mode, R, r, _ptr(fs[0]), _ptr(fs[1]), _ptr(fs[2]), _ptr(m)),
+               "ora_sttvp")
+        return m
 
     def mttkrp(self, mode: int, factors) -> np.ndarray:
         R = factors[0].shape[1]
@@ -221,6 +232,10 @@ class Model:
         assert zp.shape == (self.t.dims[mode], self.R)
         _check(lib().ora_model_set_state(self._h, mode, _ptr(zp), float(ti_prev), int(k)),
                "set_state")
+
+    def set_columns(self, cb: int):
+        """Column-at-a-time form with blocks of cb columns (0: row form)."""
+        _check(lib().ora_model_set_columns(self._h, int(cb)), "set_columns")
 
     def force_flip(self, v: int):
         lib().ora_model_force_flip(self._h, int(v))

@@ -197,6 +197,28 @@ int ora_mttkrp(const ora_tensor *t, int mode, int R, const double *A0,
   return ORA_OK;
 }
 
+/* Column r of the MTTKRP (Sec. 4.4): one pass over the slices with column r
+ * of the two other factors only. */
+int ora_sttvp(const ora_tensor *t, int mode, int R, int r, const double *A0, const double *A1,
+              const double *A2, double *m) {
+  if (!t || mode < 0 || mode > 2 || R < 1 || r < 0 || r >= R || !m) return ORA_EINVAL;
+  const double *F[3] = {A0, A1, A2};
+  int a, b;
+  other_modes(mode, &a, &b);
+  if (!F[a] || !F[b]) return ORA_EINVAL;
+  const int32_t *c = t->coords[mode];
+  const float *v = t->vals[mode];
+  const int64_t *ptr = t->ptr[mode];
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < t->dims[mode]; ++i) {
+    double s = 0.0;
+    for (int64_t p = ptr[i]; p < ptr[i + 1]; ++p)
+      s += (double)v[p] * F[a][(int64_t)c[3 * p + 1] * R + r] * F[b][(int64_t)c[3 * p + 2] * R + r];
+    m[i] = s;
+  }
+  return ORA_OK;
+}
+
 /* Gram matrix A^T A (R x R). */
 static void gram(const double *A, int64_t I, int R, double *G) {
 #pragma omp parallel for schedule(dynamic, 1)
@@ -268,6 +290,7 @@ struct ora_model {
   const ora_tensor *t;
   int R;
   int update_rule;
+  int cb; /* column-at-a-time form: columns per block (0: row form) */
   int force_flip;
   double tau;
   /* state of Alg. 1 */
@@ -386,6 +409,12 @@ int ora_model_set_state(ora_model *m, int mode, const double *zprev,
   m->ti_prev[mode] = ti_prev;
   m->k[mode] = k;
   m->undo_ok[mode] = 0;
+  return ORA_OK;
+}
+
+int ora_model_set_columns(ora_model *m, int cb) {
+  if (!m || cb < 0 || (cb > 0 && m->update_rule != ORA_UPDATE_GS)) return ORA_EINVAL;
+  m->cb = cb;
   return ORA_OK;
 }
 
@@ -550,8 +579,18 @@ int ora_sweep(ora_model *m, int mode) {
   }
   const double L = sqrt(L2);
 
-  /* 3 */
-  ora_mttkrp(t, mode, R, m->A[0], m->A[1], m->A[2], M);
+  /* 3 (in the column form, the MTTKRP column by column: Sec. 4.4) */
+  double *col = NULL;
+  if (m->cb > 0) {
+    col = (double *)malloc((size_t)(I > 0 ? I : 1) * sizeof(double));
+    if (!col) { free(delta); return ORA_ENOMEM; }
+    for (int r = 0; r < R; ++r) {
+      ora_sttvp(t, mode, R, r, m->A[0], m->A[1], m->A[2], col);
+      for (int64_t q = 0; q < I; ++q) M[q * R + r] = col[q];
+    }
+  } else {
+    ora_mttkrp(t, mode, R, m->A[0], m->A[1], m->A[2], M);
+  }
 
   /* 4, 5 */
 #pragma omp parallel for schedule(static)
@@ -589,9 +628,37 @@ int ora_sweep(ora_model *m, int mode) {
   m->ti_prev[mode] = ti;
 
   /* 9 */
+  if (m->cb > 0) {
+    /* column form: block by block in ascending column order, the block's
+     * columns of M computed again (M is not kept between the two passes),
+     * then each selected element of the block updated with the gradient of
+     * the row's current values -- the same element steps, in the same order
+     * per row, as update_row */
+    for (int c0 = 0; c0 < R; c0 += m->cb) {
+      const int c1 = c0 + m->cb < R ? c0 + m->cb : R;
+      for (int r = c0; r < c1; ++r) {
+        ora_sttvp(t, mode, R, r, m->A[0], m->A[1], m->A[2], col);
+        for (int64_t q = 0; q < I; ++q) M[q * R + r] = col[q];
+      }
 #pragma omp parallel for schedule(static)
-  for (int64_t q = 0; q < I; ++q)
-    update_row(A + q * R, sel + q * R, M + q * R, delta + q * R, H, R, m->update_rule);
+      for (int64_t q = 0; q < I; ++q) {
+        double *a = A + q * R;
+        for (int r = c0; r < c1; ++r) {
+          const double h = H[r * R + r];
+          if (!sel[q * R + r] || !(h > 0.0)) continue;
+          double g = -M[q * R + r];
+          for (int s2 = 0; s2 < R; ++s2) g += a[s2] * H[s2 * R + r];
+          const double u = a[r] - g / h;
+          a[r] = u > 0.0 ? u : 0.0;
+        }
+      }
+    }
+    free(col);
+  } else {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < I; ++q)
+      update_row(A + q * R, sel + q * R, M + q * R, delta + q * R, H, R, m->update_rule);
+  }
   free(delta);
 
   /* 10 */

@@ -46,6 +46,12 @@ int ora_tensor_mode_coo(const ora_tensor *t, int mode, int32_t *coords,
 int ora_mttkrp(const ora_tensor *t, int mode, int R, const double *A0,
                const double *A1, const double *A2, double *M);
 
+/* Column r of the MTTKRP of `mode` alone (Sec. 4.4, the column form of FSaCD:
+ * m_r[i_n] = sum over the slice Omega^n_{i_n} of x * A_a[i_a, r] * A_b[i_b, r],
+ * a sparse tensor times vector product per column): m has dims[mode] entries. */
+int ora_sttvp(const ora_tensor *t, int mode, int R, int r, const double *A0, const double *A1,
+              const double *A2, double *m);
+
 /* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): writes the first `count`
  * outputs of the generator seeded with `seed`. */
 void ora_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
@@ -74,6 +80,15 @@ int ora_model_set_state(ora_model *m, int mode, const double *zprev,
 /* force_flip: -1 = decide from ti (normal), 0 / 1 = force the eq. 27 branch
  * off / on (used to enumerate both outcomes at a total-importance tie). */
 void ora_model_force_flip(ora_model *m, int force_flip);
+/* Column-at-a-time form (Sec. 4.4, Alg. 2): cb >= 1 makes every later sweep
+ * compute the MTTKRP cb columns at a time by ora_sttvp, once for the
+ * importances and again, block by block in ascending column order, right
+ * before the update of those columns, so that M is never needed whole; cb = 0
+ * (default) is the row form.  Gauss-Seidel only (the update of a column uses
+ * the current values of the earlier columns, as in the row form, so both forms
+ * give the same sweep).  INVALID_ARG for cb < 0 or the Jacobi rule. */
+int ora_model_set_columns(ora_model *m, int cb);
+
 /* Relative width tau of the tie band (default 1e-6), see ora_sweep_band. */
 void ora_model_set_tie_tol(ora_model *m, double tau);
 

@@ -190,6 +190,11 @@ struct sacd_model {
   int nparts[3] = {0, 0, 0};
   MttkrpPlan plan[3];
   int lds_cols[3] = {0, 0, 0};  // MTTKRP form per mode: A_b staged in LDS slabs of this many columns (0: plain)
+  // column-at-a-time form: cb columns of M at a time (0: the row form, M held whole)
+  int cb = 0;
+  float *Mb = nullptr, *upart = nullptr;
+  unsigned *bits = nullptr;
+  double *colpart = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   // measurement: events recorded around the MTTKRP launches and at the end of
@@ -325,10 +330,75 @@ hipError_t launch_mode_mttkrp(const sacd_model *m, int n, hipStream_t s) {
   return launch_mttkrp(m->RP, mttkrp_args(m, n), s);
 }
 
+// One sweep of mode n in the column-at-a-time form (Sec. 4.4): H and L; pass A
+// over the column blocks (M_b, importances, both decisions, Z); ti and the
+// eq. 27 branch; pass B (M_b again, Gauss-Seidel steps of the selected
+// elements, <M, A_n>); counts; Gram and objective.  mark (optional): events
+// before pass A, after pass B and at the end.
+sacd_status enqueue_sweep_columns(sacd_model *m, int n, const hipEvent_t *mark) {
+  hipStream_t s = m->s;
+  const int I = (int)m->t->dims[n], RP = m->RP, CB = m->cb;
+  const int Rc = (m->R + CB - 1) / CB * CB;  // columns swept; the others are zero padding
+  const int ncb = Rc / CB, nrb = col_row_blocks(I);
+  FixArgs fx = fix_args(m, n);
+  fx.nlong = 0;  // H, L and the diagonal only: no split slices of a whole M to add
+  HIP_TRY(launch_mttkrp_fix(RP, fx, s));
+  if (mark) HIP_TRY(hipEventRecord(mark[0], s));
+  HIP_TRY(launch_zero_words(m->bits, (int)(((long long)I * RP + 15) / 16), s));
+  MttkrpArgs ma = mttkrp_args(m, n);
+  ma.M = nullptr;
+  ma.part = m->upart;
+  const MttkrpPlan &pl = m->plan[n];
+  ColArgs ca;
+  ca.I = I;
+  ca.RP = RP;
+  ca.CB = CB;
+  ca.A = m->A[n];
+  ca.Mb = m->Mb;
+  ca.H = m->H[n];
+  ca.hi = m->hinfo[n];
+  ca.st = m->st + n;
+  ca.Z = m->Z[n];
+  ca.bits = m->bits;
+  ca.part = m->colpart;
+  ca.cnt_part = m->cnt_part;
+  ca.selmask = m->diag ? m->selmask[n] : nullptr;
+  ca.Mdiag = m->diag ? m->M[n] : nullptr;
+  // M_b is shared by the modes and the column blocks, and the rows of empty
+  // slices are never written by the MTTKRP: it is cleared before each block
+  const int mb_words = I * CB;
+  for (int b = 0; b < ncb; ++b) {
+    HIP_TRY(launch_zero_words((unsigned *)m->Mb, mb_words, s));
+    HIP_TRY(launch_sttvp(CB, ma, RP, b * CB, pl.uslot, pl.ulongs, pl.nulong, m->Mb, s));
+    ca.c0 = b * CB;
+    ca.part_off = b * nrb;
+    HIP_TRY(launch_col_importance(CB, ca, s));
+  }
+  HIP_TRY(launch_col_decide(m->colpart, ncb * nrb, m->st + n, s));
+  for (int b = 0; b < ncb; ++b) {
+    HIP_TRY(launch_zero_words((unsigned *)m->Mb, mb_words, s));
+    HIP_TRY(launch_sttvp(CB, ma, RP, b * CB, pl.uslot, pl.ulongs, pl.nulong, m->Mb, s));
+    ca.c0 = b * CB;
+    ca.part_off = b * nrb;
+    HIP_TRY(launch_col_update(CB, ca, s));
+  }
+  if (mark) HIP_TRY(hipEventRecord(mark[1], s));
+  HIP_TRY(launch_col_finish(m->colpart, ncb * nrb, m->cnt_part, nrb, RP, Rc, m->colcnt[n], m->st + n, s));
+  HIP_TRY(launch_gram_partial(RP, false, I, m->A[n], m->gpart, nullptr, s));
+  GramArgs g = gram_args(m, n, true);
+  g.inner_part = nullptr;  // <M, A_n>, the counts and |E| come from k_col_finish
+  g.cnt_part = nullptr;
+  g.colcnt = nullptr;
+  HIP_TRY(launch_gram_final(RP, g, s));
+  if (mark) HIP_TRY(hipEventRecord(mark[2], s));
+  return SACD_OK;
+}
+
 // Enqueues one sweep of mode n on the model's stream.  mark (optional): three
 // events recorded right before and right after the MTTKRP launch and after the
 // sweep's last kernel.
 sacd_status enqueue_sweep(sacd_model *m, int n, const hipEvent_t *mark = nullptr) {
+  if (m->cb > 0) return enqueue_sweep_columns(m, n, mark);
   hipStream_t s = m->s;
   const bool bf = is_bf16(m);
   if (mark) HIP_TRY(hipEventRecord(mark[0], s));
@@ -579,21 +649,49 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
   }
   for (size_t u = 0; u < units.size(); ++u)
     if (units[u].w == -2) units[u].w = slot_of[run_of[u]];
+  // one slot per unit of a split slice, numbered slice by slice in entry order
+  std::vector<int> uslot(units.size(), -1);
+  std::vector<int4> ulongs;
+  {
+    std::vector<int> su;
+    for (size_t u = 0; u < units.size(); ++u)
+      if (units[u].w >= 0) su.push_back((int)u);
+    std::stable_sort(su.begin(), su.end(), [&](int x, int y) {
+      if (units[x].x != units[y].x) return units[x].x < units[y].x;
+      return units[x].y < units[y].y;
+    });
+    for (size_t k = 0; k < su.size(); ++k) {
+      uslot[su[k]] = (int)k;
+      if (ulongs.empty() || ulongs.back().x != units[su[k]].x) ulongs.push_back(make_int4(units[su[k]].x, (int)k, 0, 0));
+      ulongs.back().z += 1;
+    }
+  }
   MttkrpPlan p;
   p.nnz = t->nnz;
   p.nunits = (int)units.size();
   p.nlong = (int)longs.size();
   p.nslots = (int)run_slice.size();
-  int4 *du = nullptr, *dl = nullptr;
+  int4 *du = nullptr, *dl = nullptr, *dul = nullptr;
+  int *dus = nullptr;
   SACD_TRY(mem.get_t(units.size() + 1, &du));
   SACD_TRY(mem.get_t(longs.size() + 1, &dl));
-  if (!units.empty())
+  SACD_TRY(mem.get_t(units.size() + 1, &dus));
+  SACD_TRY(mem.get_t(ulongs.size() + 1, &dul));
+  if (!units.empty()) {
     HIP_TRY(hipMemcpyAsync(du, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipMemcpyAsync(dus, uslot.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, t->stream));
+  }
   if (!longs.empty())
     HIP_TRY(hipMemcpyAsync(dl, longs.data(), sizeof(int4) * longs.size(), hipMemcpyHostToDevice, t->stream));
+  if (!ulongs.empty())
+    HIP_TRY(hipMemcpyAsync(dul, ulongs.data(), sizeof(int4) * ulongs.size(), hipMemcpyHostToDevice, t->stream));
   HIP_TRY(hipStreamSynchronize(t->stream));
   p.units = du;
   p.longs = dl;
+  p.uslot = dus;
+  p.ulongs = dul;
+  p.nuslots = (int)std::count_if(uslot.begin(), uslot.end(), [](int v) { return v >= 0; });
+  p.nulong = (int)ulongs.size();
   *out = p;
   return SACD_OK;
 }
@@ -821,14 +919,14 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
     m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
     SACD_TRY(A.get_t((size_t)I * RP, &m->A[n]));
     SACD_TRY(A.get_t((size_t)I * RP, &m->Z[n]));
-    SACD_TRY(A.get_t((size_t)I * RP, &m->M[n]));
+    if (m->cb == 0) SACD_TRY(A.get_t((size_t)I * RP, &m->M[n]));  // the column form holds I x cb only
     SACD_TRY(A.get_t((size_t)RP * RP, &m->H[n]));
     SACD_TRY(A.get_t((size_t)RP * RP, &m->G64[n]));
     if (m->prec == SACD_PREC_MIXED_BF16) SACD_TRY(A.get_t((size_t)RP * RP, &m->G64o[n]));
     else m->G64o[n] = m->G64[n];
     SACD_TRY(A.get_t(1, &m->hinfo[n]));
     SACD_TRY(A.get_t((size_t)RP, &m->colcnt[n]));
-    SACD_TRY(A.get_t((size_t)I * RP, &m->selmask[n]));
+    if (m->cb == 0) SACD_TRY(A.get_t((size_t)I * RP, &m->selmask[n]));  // column form: with the diagnostics
   }
   const int maxparts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
   SACD_TRY(A.get_t(3, &m->st));
@@ -840,6 +938,18 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
   SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
   SACD_TRY(A.get_t((size_t)gram_model_parts(RP), &m->mpart));
+  if (m->cb > 0) {
+    int maxus = 1, maxcp = 1;
+    for (int n = 0; n < 3; ++n) {
+      maxus = std::max(maxus, m->plan[n].nuslots);
+      const int Rc = (m->R + m->cb - 1) / m->cb * m->cb;
+      maxcp = std::max(maxcp, (Rc / m->cb) * col_row_blocks((int)t->dims[n]));
+    }
+    SACD_TRY(A.get_t((size_t)maxI * m->cb, &m->Mb));
+    SACD_TRY(A.get_t((size_t)maxus * m->cb, &m->upart));
+    SACD_TRY(A.get_t(((size_t)maxI * RP + 15) / 16, &m->bits));
+    SACD_TRY(A.get_t((size_t)maxcp, &m->colpart));
+  }
   SACD_TRY(A.get_t(1, &m->gcounter));
   SACD_TRY(A.get_t(4, &m->flag));
   m->full_nparts = 1024;
@@ -858,8 +968,8 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
     off += (unsigned long long)I * m->R;
     HIP_TRY(hipMemsetAsync(m->Z[n], 0, sizeof(float) * I * RP, s));
     // empty slices are never written by the MTTKRP: their rows stay zero
-    HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * I * RP, s));
-    HIP_TRY(hipMemsetAsync(m->selmask[n], 0, (size_t)I * RP, s));
+    if (m->M[n]) HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * I * RP, s));
+    if (m->selmask[n]) HIP_TRY(hipMemsetAsync(m->selmask[n], 0, (size_t)I * RP, s));
     HIP_TRY(hipMemsetAsync(m->colcnt[n], 0, sizeof(long long) * RP, s));
   }
   for (int n = 0; n < 3; ++n) SACD_TRY(recompute_gram(m, n));
@@ -867,8 +977,25 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   return SACD_OK;
 }
 
+static sacd_status init_factors_impl(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
+                                     sacd_update update, int32_t cb, sacd_model **out);
+
 sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
                               sacd_update update, sacd_model **out) {
+  return init_factors_impl(t, R, seed, prec, update, 0, out);
+}
+
+sacd_status sacd_init_factors_columns(sacd_tensor *t, int32_t R, uint64_t seed, int32_t column_block,
+                                      sacd_model **out) {
+  if (column_block != 1 && column_block != 2 && column_block != 4 && column_block != 8 && column_block != 16) {
+    if (out) *out = nullptr;
+    return fail(SACD_ERR_INVALID_ARG, "column_block %d not in {1, 2, 4, 8, 16}", column_block);
+  }
+  return init_factors_impl(t, R, seed, SACD_PREC_FP32, SACD_UPDATE_GS, column_block, out);
+}
+
+static sacd_status init_factors_impl(sacd_tensor *t, int32_t R, uint64_t seed, sacd_precision prec,
+                                     sacd_update update, int32_t cb, sacd_model **out) {
   if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
@@ -890,6 +1017,7 @@ sacd_status sacd_init_factors(sacd_tensor *t, int32_t R, uint64_t seed, sacd_pre
   m->RP = R <= 16 ? 16 : R <= 32 ? 32 : R <= 64 ? 64 : 128;
   m->prec = prec;
   m->upd = update;
+  m->cb = cb;
   sacd_status st = init_model_impl(m, seed);
   if (st != SACD_OK) {
     sacd_destroy_model(m);
@@ -1155,6 +1283,8 @@ sacd_status sacd_get_diagnostics(const sacd_model *m, int32_t mode, float *mttkr
   SACD_TRY(enter(m->t->dev));
   const int I = (int)m->t->dims[mode];
   const int R = m->R, RP = m->RP;
+  if ((mttkrp || selection) && !m->M[mode])
+    return fail(SACD_ERR_BAD_STATE, "the column-at-a-time form records M and the selection only with diagnostics on");
   if (mttkrp) HIP_TRY(launch_copy_rows(m->M[mode], RP, mttkrp, R, I, R, R, m->s));
   if (selection) {
     HIP_TRY(hipMemcpy2DAsync(selection, (size_t)R, m->selmask[mode], (size_t)RP, (size_t)R, (size_t)I,
@@ -1178,6 +1308,17 @@ sacd_status sacd_set_diagnostics(sacd_model *m, int32_t enable) {
     SACD_TRY(enter(m->t->dev));
     HIP_TRY(hipStreamSynchronize(m->s));
     drop_graph(m);
+    if (d && m->cb > 0 && !m->M[0]) {
+      // the column form keeps no whole M: the diagnostics get their own
+      for (int n = 0; n < 3; ++n) {
+        const size_t IR = (size_t)m->t->dims[n] * m->RP;
+        SACD_TRY(m->mem.get_t(IR, &m->M[n]));
+        SACD_TRY(m->mem.get_t(IR, &m->selmask[n]));
+        HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * IR, m->s));
+        HIP_TRY(hipMemsetAsync(m->selmask[n], 0, IR, m->s));
+      }
+      HIP_TRY(hipStreamSynchronize(m->s));
+    }
     m->diag = d;
   }
   return SACD_OK;
@@ -1186,6 +1327,7 @@ sacd_status sacd_set_diagnostics(sacd_model *m, int32_t enable) {
 sacd_status sacd_time_kernel(sacd_model *m, int32_t which, int32_t mode, int32_t reps, float *avg_ms) {
   SACD_TRY(check_mode(m, mode));
   if (which < 0 || which > 2 || reps < 1 || !avg_ms) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  if (m->cb > 0) return fail(SACD_ERR_BAD_STATE, "kernel timing applies to the row form only");
   SACD_TRY(enter(m->t->dev));
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1292,7 +1434,8 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, bool mixed, int64_t *r
     maxI = std::max(maxI, I);
     const int64_t units = nnz / kSegment + I + 2;
     maxunits = std::max(maxunits, units);
-    ten += al256(8 * (nnz + kKeySlack)) + al256(4 * (nnz + kKeySlack)) + al256(4 * (I + 1)) + al256(16 * units) + al256(16 * (I + 2));
+    ten += al256(8 * (nnz + kKeySlack)) + al256(4 * (nnz + kKeySlack)) + al256(4 * (I + 1)) + al256(16 * units) +
+           al256(16 * (I + 2)) + al256(4 * (units + 1)) + al256(16 * (I + 2));
     mod += 3 * al256(4 * I * RP) + al256(I * RP) + 2 * al256(4 * RP * RP) + al256(8 * RP * RP) +
            al256(sizeof(HInfo)) + al256(8 * RP);
   }

@@ -129,6 +129,11 @@ struct MttkrpPlan {
   int nlong;          // slices split over several units
   const int4 *longs;  // device: (slice, first partial slot, slots, 0)
   int nslots;         // partial slots
+  // one partial slot per unit of a split slice (the column-at-a-time form):
+  const int *uslot;   // device, per unit: its slot, or -1 for a whole slice
+  int nuslots;
+  int nulong;
+  const int4 *ulongs; // device: (slice, first unit slot, unit slots, 0), slots in entry order
 };
 int mttkrp_units_per_block(int RP);
 int mttkrp_blocks(int RP, int nunits);
@@ -160,6 +165,33 @@ hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, hipStr
 hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 hipError_t launch_mttkrp_fix(int RP, const FixArgs &a, hipStream_t s);
 hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
+
+// lowmem.hip: the column-at-a-time form (the MTTKRP a block of CB columns at
+// a time, Sec. 4.4; no I_n x R buffer for M).  Mb: I_n x CB block of M.
+struct ColArgs {
+  int I, RP, c0, CB;
+  const float *A;       // I x RP, the factor being swept
+  const float *Mb;      // I x CB
+  const float *H;       // RP x RP
+  const HInfo *hi;
+  ModeState *st;
+  float *Z;             // I x RP
+  unsigned *bits;       // 2 bits per element of I x RP: eq. 24 (k = 1: z > 0) and eq. 27 outcomes
+  double *part;         // per (column block, row block) partial sums (ti, then <M, A_n>)
+  int part_off;         // first partial of this column block
+  int *cnt_part;        // per row block x RP selected counts
+  uint8_t *selmask;     // diagnostics (or nullptr)
+  float *Mdiag;         // diagnostics: the whole M (or nullptr)
+};
+constexpr int kColThreads = 256;  // rows per block of the column-form element kernels
+int col_row_blocks(int I);
+hipError_t launch_sttvp(int CB, const MttkrpArgs &a, int RP, int c0, const int *uslot, const int4 *ulongs, int nulong,
+                        float *Mb, hipStream_t s);
+hipError_t launch_col_importance(int CB, const ColArgs &a, hipStream_t s);
+hipError_t launch_col_decide(const double *part, int n, ModeState *st, hipStream_t s);
+hipError_t launch_col_update(int CB, const ColArgs &a, hipStream_t s);
+hipError_t launch_col_finish(const double *part, int n, const int *cnt_part, int nrb, int RP, int ncols,
+                             long long *colcnt, ModeState *st, hipStream_t s);
 
 // sweep.hip
 // Arguments of one job's element kernels.  The solo launchers pass them by

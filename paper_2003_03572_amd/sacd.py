@@ -81,6 +81,7 @@ def lib():
             "sacd_tensor_info": [p, p, p, p, p],
             "sacd_tensor_mode_coo": [p, i32, p, p, p],
             "sacd_init_factors": [p, i32, C.c_uint64, C.c_int, C.c_int, C.POINTER(p)],
+            "sacd_init_factors_columns": [p, i32, C.c_uint64, i32, C.POINTER(p)],
             "sacd_sweep": [p, i32],
             "sacd_iterate": [p, i32],
             "sacd_fit": [p, p, p],
@@ -237,12 +238,20 @@ class Model:
     """SaCD model of rank R over a Tensor (sacd_init_factors)."""
 
     def __init__(self, tensor: Tensor, rank: int, seed: int, precision: int = PREC_FP32,
-                 update: int = UPDATE_GS):
+                 update: int = UPDATE_GS, columns: int = 0):
+        """columns > 0: the column-at-a-time form with blocks of that many
+        columns (FP32, Gauss-Seidel; sacd_init_factors_columns)."""
         self.t = tensor
         self.R = int(rank)
         h = C.c_void_p()
-        _check(lib().sacd_init_factors(tensor._h, self.R, C.c_uint64(seed), precision, update,
-                                       C.byref(h)), "sacd_init_factors")
+        if columns:
+            if precision != PREC_FP32 or update != UPDATE_GS:
+                raise ValueError("the column-at-a-time form is FP32 Gauss-Seidel")
+            _check(lib().sacd_init_factors_columns(tensor._h, self.R, C.c_uint64(seed), int(columns),
+                                                   C.byref(h)), "sacd_init_factors_columns")
+        else:
+            _check(lib().sacd_init_factors(tensor._h, self.R, C.c_uint64(seed), precision, update,
+                                           C.byref(h)), "sacd_init_factors")
         self._h = h
         self.dims = tensor.dims
 

@@ -579,3 +579,62 @@ def test_gauss_seidel_monotone_jacobi_not_on_the_small_workload(oracle_mod):
                     f_prev = f
     assert rises[oracle_mod.UPDATE_GS] == 0
     assert rises[oracle_mod.UPDATE_JACOBI] >= 1
+
+
+# ------------------------------------------- column-at-a-time form (Sec. 4.4) --
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_sttvp_is_a_column_of_unfolding_times_khatri_rao(oracle_mod, seed):
+    """The column form of the MTTKRP (Sec. 4.4): column r alone equals column
+    r of the dense unfolding times the explicit Khatri-Rao product."""
+    dims, idx, vals = _tiny(seed, dims=(4, 3, 5), nnz=30)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    rng = np.random.default_rng(200 + seed)
+    R = 3
+    A = [rng.random((d, R)) for d in dims]
+    X = _dense(dims, idx, vals)
+    krp = {0: _khatri_rao(A[2], A[1]), 1: _khatri_rao(A[2], A[0]), 2: _khatri_rao(A[1], A[0])}
+    for n in range(3):
+        want = _unfold(X, n) @ krp[n]
+        for r in range(R):
+            np.testing.assert_allclose(T.sttvp(n, r, A), want[:, r], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("cb", [1, 2])
+def test_three_sweeps_in_the_column_form(oracle_mod, cb):
+    """The hand-worked three sweeps hold in the column-at-a-time form too."""
+    g, T, m = _three_sweep_setup(oracle_mod)
+    m.set_columns(cb)
+    for sw in g["sweeps"]:
+        m.set_factor(2, np.array(sw["W"]))
+        m.sweep(0)
+        info = m.info(0)
+        np.testing.assert_array_equal(info["z"], sw["z"])
+        assert info["ti"] == sw["ti"] and info["flip"] == sw["flip"]
+        np.testing.assert_array_equal(info["sel"].astype(int), sw["sel"])
+        np.testing.assert_array_equal(m.factor(0), sw["U"])
+        assert info["f"] == sw["f"]
+
+
+@pytest.mark.parametrize("cb", [1, 3, 8])
+def test_column_form_equals_row_form(oracle_mod, cb):
+    """Column by column (M recomputed per block before its update) the sweep
+    is the row form's: the same importances, selections and factors, and the
+    objective to rounding."""
+    dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
+    T = oracle_mod.Tensor(dims, idx, vals)
+    a = oracle_mod.Model(T, 8, seed=42)
+    b = oracle_mod.Model(T, 8, seed=42)
+    b.set_columns(cb)
+    for it in range(4):
+        for n in range(3):
+            a.sweep(n)
+            b.sweep(n)
+            ia, ib = a.info(n), b.info(n)
+            np.testing.assert_array_equal(ia["z"], ib["z"])
+            np.testing.assert_array_equal(ia["sel"], ib["sel"])
+            np.testing.assert_array_equal(a.factor(n), b.factor(n))
+            assert ia["ti"] == ib["ti"] and ia["flip"] == ib["flip"]
+            assert math.isclose(ia["f"], ib["f"], rel_tol=1e-12)
+    with pytest.raises(oracle_mod.OracleError):
+        oracle_mod.Model(T, 8, seed=1, update=oracle_mod.UPDATE_JACOBI).set_columns(2)

@@ -23,13 +23,16 @@ UPDATE_GS = 0
 UPDATE_JACOBI = 1
 
 
+SRC_N_PATH = os.path.join(_HERE, "sacd_oracle_n.c")
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math; OpenMP for the
     loops whose iterations are independent)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-                               "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm"])
+                               "-Wall", "-Wextra", "-o", tmp, SRC_PATH, SRC_N_PATH, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -78,6 +81,26 @@ def lib():
         L.ora_sweep_band.argtypes = [p, i32, p, p, p]
         L.ora_sweep_undo.argtypes = [p, i32]
         L.ora_sttvp.argtypes = [p, i32, i32, i32, p, p, p, p]
+        L.oran_tensor_create.argtypes = [i32, p, i64, p, p, C.POINTER(p)]
+        L.oran_tensor_destroy.argtypes = [p]
+        L.oran_tensor_destroy.restype = None
+        L.oran_tensor_nnz.argtypes = [p]
+        L.oran_tensor_nnz.restype = i64
+        L.oran_tensor_norm2.argtypes = [p]
+        L.oran_tensor_norm2.restype = dbl
+        L.oran_tensor_mode_coo.argtypes = [p, i32, p, p, p]
+        L.oran_mttkrp.argtypes = [p, i32, i32, p, p]
+        L.oran_model_create.argtypes = [p, i32, C.c_uint64, C.POINTER(p)]
+        L.oran_model_destroy.argtypes = [p]
+        L.oran_model_destroy.restype = None
+        L.oran_model_get_factor.argtypes = [p, i32, p]
+        L.oran_model_set_factor.argtypes = [p, i32, p]
+        L.oran_model_get_state.argtypes = [p, i32, p, p, p]
+        L.oran_model_set_state.argtypes = [p, i32, p, dbl, i64]
+        L.oran_sweep.argtypes = [p, i32]
+        L.oran_sweep_info.argtypes = [p, i32, p, p, p, p, p]
+        L.oran_objective.argtypes = [p]
+        L.oran_objective.restype = dbl
         L.ora_model_set_columns.argtypes = [p, i32]
         L.ora_set_threads.argtypes = [i32]
         L.ora_set_threads.restype = i32
@@ -312,3 +335,108 @@ class Model:
         _check(lib().ora_run_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit),
                                    _ptr(trace)), "ora_run_until")
         return it.value, fit.value, trace[: it.value]
+
+
+class NTensor:
+    """Sparse N-way tensor (Sec. 3, N modes)."""
+
+    def __init__(self, dims, idx: np.ndarray, vals: np.ndarray):
+        self.dims = tuple(int(d) for d in dims)
+        self.N = len(self.dims)
+        idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, self.N)
+        vals = np.ascontiguousarray(vals, dtype=np.float32).reshape(-1)
+        d = np.array(self.dims, dtype=np.int64)
+        h = C.c_void_p()
+        _check(lib().oran_tensor_create(self.N, _ptr(d), idx.shape[0], _ptr(idx), _ptr(vals), C.byref(h)),
+               "oran_tensor_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.oran_tensor_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def nnz(self) -> int:
+        return int(lib().oran_tensor_nnz(self._h))
+
+    @property
+    def norm2(self) -> float:
+        return float(lib().oran_tensor_norm2(self._h))
+
+    def mode_coo(self, mode: int):
+        nnz = self.nnz
+        coords = np.empty((nnz, self.N), np.int32)
+        vals = np.empty(nnz, np.float32)
+        ptr = np.empty(self.dims[mode] + 1, np.int64)
+        _check(lib().oran_tensor_mode_coo(self._h, mode, _ptr(coords), _ptr(vals), _ptr(ptr)), "mode_coo")
+        return coords, vals, ptr
+
+    def mttkrp(self, mode: int, factors) -> np.ndarray:
+        R = factors[0].shape[1]
+        fs = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+        arr = (C.c_void_p * self.N)(*[f.ctypes.data for f in fs])
+        M = np.empty((self.dims[mode], R), np.float64)
+        _check(lib().oran_mttkrp(self._h, mode, R, arr, _ptr(M)), "oran_mttkrp")
+        return M
+
+
+class NModel:
+    """SaCD state of an N-way tensor: factors, Grams, Z^{k-1}, ti^{k-1}, k."""
+
+    def __init__(self, tensor: NTensor, R: int, seed: int):
+        self.t = tensor
+        self.R = int(R)
+        h = C.c_void_p()
+        _check(lib().oran_model_create(tensor._h, self.R, C.c_uint64(seed), C.byref(h)), "oran_model_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            try:
+                _lib.oran_model_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def factor(self, mode: int) -> np.ndarray:
+        out = np.empty((self.t.dims[mode], self.R), np.float64)
+        _check(lib().oran_model_get_factor(self._h, mode, _ptr(out)), "get_factor")
+        return out
+
+    def set_factor(self, mode: int, A: np.ndarray):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        assert A.shape == (self.t.dims[mode], self.R)
+        _check(lib().oran_model_set_factor(self._h, mode, _ptr(A)), "set_factor")
+
+    def state(self, mode: int):
+        zp = np.empty((self.t.dims[mode], self.R), np.float64)
+        ti, k = C.c_double(), C.c_int64()
+        _check(lib().oran_model_get_state(self._h, mode, _ptr(zp), C.byref(ti), C.byref(k)), "get_state")
+        return zp, ti.value, k.value
+
+    def set_state(self, mode: int, zprev: np.ndarray, ti_prev: float, k: int):
+        zp = np.ascontiguousarray(zprev, dtype=np.float64)
+        _check(lib().oran_model_set_state(self._h, mode, _ptr(zp), float(ti_prev), int(k)), "set_state")
+
+    def sweep(self, mode: int):
+        _check(lib().oran_sweep(self._h, mode), "oran_sweep")
+
+    def info(self, mode: int) -> dict:
+        I, R = self.t.dims[mode], self.R
+        M = np.empty((I, R), np.float64)
+        z = np.empty((I, R), np.float64)
+        sel = np.empty((I, R), np.uint8)
+        H = np.empty((R, R), np.float64)
+        sc = np.empty(6, np.float64)
+        _check(lib().oran_sweep_info(self._h, mode, _ptr(M), _ptr(z), _ptr(sel), _ptr(H), _ptr(sc)), "info")
+        return dict(M=M, z=z, sel=sel.astype(bool), H=H, L=sc[0], ti=sc[1], flip=bool(sc[2]), ti_prev=sc[3],
+                    f=sc[4], nsel=int(sc[5]))
+
+    def objective(self) -> float:
+        return float(lib().oran_objective(self._h))

@@ -344,6 +344,86 @@ sacd_status sacd_server_stats(const sacd_server *s, sacd_server_stats_t *out);
 void sacd_server_destroy(sacd_server *s);
 
 /* ------------------------------------------------------------------------ */
+/* N-way tensors                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Sec. 3 defines nonnegative CP factorization for a tensor of any number of
+ * modes N; the paper derives the sweep for three.  For N modes each sweep of
+ * mode n is the same Alg. 1 body with the Khatri-Rao product of the N - 1
+ * other factors in the MTTKRP (eq. 9: M[i_n, r] = sum over the entries of the
+ * slice of x times the product of the other factors' rows at column r) and H
+ * the Hadamard product of the N - 1 other Gram matrices (eq. 10); the
+ * objective (eq. 6) is ||X||^2 - 2 <X, Xhat> + the sum over the Hadamard
+ * product of all N Grams.  FP32 arithmetic, Gauss-Seidel updates (as
+ * SACD_UPDATE_GS), objective in FP64; every convention of the three-way calls
+ * holds unless stated.  An outer iteration is one sweep of each mode
+ * 0, ..., N - 1. */
+typedef struct sacd_ntensor sacd_ntensor; /* opaque, library-owned */
+typedef struct sacd_nmodel sacd_nmodel;   /* opaque, library-owned */
+
+/* Ingest an N-way sparse tensor.
+ *   N     number of modes, in [2, 8].
+ *   dims  host, N mode lengths, each in [1, 2^31 - 1]; the bit widths of
+ *         (I_n - 1) must sum to at most 64.
+ *   nnz   in [0, 2^31 - 1]; idx device nnz x N int32 (row-major, 0-based);
+ *         vals device nnz float32.
+ *   alloc, stream, out: as sacd_create_tensor.
+ * Duplicates merged by FP32 addition in input order.  For each mode n the
+ * entries are sorted by (i_n, then the other indices in increasing mode
+ * order) and slice pointers built.  Errors: INVALID_ARG, OUT_OF_RANGE,
+ * NUMERIC (NaN/Inf value), NO_MEMORY, DEVICE. */
+sacd_status sacd_create_ntensor(int32_t N, const int64_t *dims, int64_t nnz, const int32_t *idx,
+                                const float *vals, const sacd_allocator *alloc, void *stream,
+                                sacd_ntensor **out);
+/* N, dims (host, N), nnz after merging, ||X||^2, device bytes; any output
+ * may be NULL. */
+sacd_status sacd_ntensor_info(const sacd_ntensor *t, int32_t *N, int64_t *dims, int64_t *nnz,
+                              double *norm2, int64_t *device_bytes);
+/* Mode `mode`'s sorted entries: coords device nnz x N int32 (i_n, then the
+ * other indices in increasing mode order), vals device nnz float32, ptr
+ * device (dims[mode] + 1) int64.  Any pointer may be NULL.  Synchronises. */
+sacd_status sacd_ntensor_mode_coo(const sacd_ntensor *t, int32_t mode, int32_t *coords, float *vals,
+                                  int64_t *ptr);
+/* Deferred while models built on the tensor are alive. */
+void sacd_destroy_ntensor(sacd_ntensor *t);
+
+/* Model of rank R in [1, 128]; factors A_0, ..., A_{N-1} filled in that order
+ * from consecutive SplitMix64 outputs as sacd_init_factors does.  Errors:
+ * INVALID_ARG, NO_MEMORY, DEVICE. */
+sacd_status sacd_init_nfactors(sacd_ntensor *t, int32_t R, uint64_t seed, sacd_nmodel **out);
+/* One sweep of mode `mode` in [0, N) (asynchronous). */
+sacd_status sacd_nsweep(sacd_nmodel *m, int32_t mode);
+/* n_iters outer iterations replayed from one captured HIP graph (asynchronous). */
+sacd_status sacd_niterate(sacd_nmodel *m, int32_t n_iters);
+/* n_iters outer iterations enqueued launch by launch with events around
+ * each MTTKRP launch and at each sweep's end; waits, then writes the MTTKRP
+ * milliseconds of iteration i, mode n to mttkrp_ms[N i + n] and (if sweep_ms
+ * is not NULL) the sweep's to sweep_ms[N i + n] (host, N n_iters floats).
+ * n_iters in [1, 100000]. */
+sacd_status sacd_niterate_timed(sacd_nmodel *m, int32_t n_iters, float *mttkrp_ms, float *sweep_ms);
+/* As sacd_fit / sacd_run_until (the objective is read after mode N - 1). */
+sacd_status sacd_nfit(sacd_nmodel *m, double *fit, double *objective);
+sacd_status sacd_nrun_until(sacd_nmodel *m, double tol, int32_t max_iter, int32_t *iters_done,
+                            double *final_fit);
+/* As sacd_get_factor / sacd_set_factor / sacd_get_state / sacd_set_state /
+ * sacd_get_stats / sacd_get_column_counts / sacd_get_diagnostics /
+ * sacd_set_diagnostics, for mode in [0, N). */
+sacd_status sacd_get_nfactor(const sacd_nmodel *m, int32_t mode, float *dst);
+sacd_status sacd_set_nfactor(sacd_nmodel *m, int32_t mode, const float *src);
+sacd_status sacd_get_nstate(const sacd_nmodel *m, int32_t mode, float *zprev, double *ti_prev,
+                            int64_t *k);
+sacd_status sacd_set_nstate(sacd_nmodel *m, int32_t mode, const float *zprev, double ti_prev,
+                            int64_t k);
+sacd_status sacd_get_nstats(const sacd_nmodel *m, int32_t mode, sacd_sweep_stats *out);
+sacd_status sacd_get_ncolumn_counts(const sacd_nmodel *m, int32_t mode, int64_t *counts);
+sacd_status sacd_get_ndiagnostics(const sacd_nmodel *m, int32_t mode, float *mttkrp,
+                                  uint8_t *selection, double *gram);
+sacd_status sacd_set_ndiagnostics(sacd_nmodel *m, int32_t enable);
+/* Device bytes held by the model. */
+sacd_status sacd_nmodel_bytes(const sacd_nmodel *m, int64_t *bytes);
+void sacd_destroy_nmodel(sacd_nmodel *m);
+
+/* ------------------------------------------------------------------------ */
 /* Misc                                                                      */
 /* ------------------------------------------------------------------------ */
 const char *sacd_status_string(sacd_status s);

@@ -99,6 +99,8 @@ def lib():
         L.oran_model_set_state.argtypes = [p, i32, p, dbl, i64]
         L.oran_sweep.argtypes = [p, i32]
         L.oran_sweep_info.argtypes = [p, i32, p, p, p, p, p]
+        L.oran_sweep_band.argtypes = [p, i32, p, p, p]
+        L.oran_row_outcome.argtypes = [p, i32, i64, p, p]
         L.oran_objective.argtypes = [p]
         L.oran_objective.restype = dbl
         L.ora_model_set_columns.argtypes = [p, i32]
@@ -428,15 +430,31 @@ class NModel:
         _check(lib().oran_sweep(self._h, mode), "oran_sweep")
 
     def info(self, mode: int) -> dict:
+        """Record of the last sweep of `mode` with its tie band (keys as the
+        three-way Model.info, without G0)."""
         I, R = self.t.dims[mode], self.R
         M = np.empty((I, R), np.float64)
         z = np.empty((I, R), np.float64)
         sel = np.empty((I, R), np.uint8)
         H = np.empty((R, R), np.float64)
-        sc = np.empty(6, np.float64)
+        sc = np.empty(8, np.float64)
         _check(lib().oran_sweep_info(self._h, mode, _ptr(M), _ptr(z), _ptr(sel), _ptr(H), _ptr(sc)), "info")
+        band = np.empty((I, R), np.float64)
+        kind = np.empty((I, R), np.uint8)
+        bs = np.empty(5, np.float64)
+        _check(lib().oran_sweep_band(self._h, mode, _ptr(band), _ptr(kind), _ptr(bs)), "sweep_band")
         return dict(M=M, z=z, sel=sel.astype(bool), H=H, L=sc[0], ti=sc[1], flip=bool(sc[2]), ti_prev=sc[3],
-                    f=sc[4], nsel=int(sc[5]))
+                    f=sc[4], nsel=int(sc[5]), inner=sc[6], model=sc[7],
+                    band=band, kind=kind, tie=kind >= 2, band_ti=bs[0], tie_global=bool(bs[1]),
+                    n_exact_zero=int(bs[2]), n_zero_grad=int(bs[3]), n_margin=int(bs[4]))
+
+    def row_outcome(self, mode: int, q: int, sel: np.ndarray) -> np.ndarray:
+        """Row q of the last sweep of `mode` updated under decisions `sel`."""
+        sel = np.ascontiguousarray(sel, np.uint8).reshape(-1)
+        assert sel.shape[0] == self.R
+        out = np.empty(self.R, np.float64)
+        _check(lib().oran_row_outcome(self._h, mode, int(q), _ptr(sel), _ptr(out)), "row_outcome")
+        return out
 
     def objective(self) -> float:
         return float(lib().oran_objective(self._h))

@@ -172,7 +172,14 @@ struct oran_model {
   int64_t k[NMAX];
   double *M[NMAX], *z[NMAX], *H[NMAX];
   uint8_t *sel[NMAX];
-  double info[NMAX][6];
+  double info[NMAX][8];
+  /* diagnostics of the tests (no step of the method reads them): the factor
+   * and Z^{k-1} the last sweep started from, its gradient G0, and the tie
+   * band of its importances (as in the three-way oracle) */
+  double *A_prev[NMAX], *G0[NMAX], *zprev_used[NMAX], *band[NMAX], *band_used[NMAX];
+  uint8_t *kind[NMAX];
+  double band_info[NMAX][5];
+  double tau;
 };
 
 void oran_model_destroy(oran_model *m) {
@@ -180,6 +187,8 @@ void oran_model_destroy(oran_model *m) {
   for (int n = 0; n < m->t->N; ++n) {
     free(m->A[n]); free(m->G[n]); free(m->zprev[n]); free(m->M[n]);
     free(m->z[n]); free(m->H[n]); free(m->sel[n]);
+    free(m->A_prev[n]); free(m->G0[n]); free(m->zprev_used[n]); free(m->band[n]);
+    free(m->band_used[n]); free(m->kind[n]);
   }
   free(m);
 }
@@ -190,6 +199,7 @@ int oran_model_create(const oran_tensor *t, int R, uint64_t seed, oran_model **o
   if (!m) return ORA_ENOMEM;
   m->t = t;
   m->R = R;
+  m->tau = 1e-6;
   uint64_t state = seed; /* SplitMix64 (Steele, Lea, Flood 2014), outputs in factor order */
   for (int n = 0; n < t->N; ++n) {
     const size_t IR = (size_t)t->dims[n] * R;
@@ -200,7 +210,14 @@ int oran_model_create(const oran_tensor *t, int R, uint64_t seed, oran_model **o
     m->z[n] = (double *)calloc(IR, sizeof(double));
     m->H[n] = (double *)calloc((size_t)R * R, sizeof(double));
     m->sel[n] = (uint8_t *)calloc(IR, 1);
-    if (!m->A[n] || !m->G[n] || !m->zprev[n] || !m->M[n] || !m->z[n] || !m->H[n] || !m->sel[n]) {
+    m->A_prev[n] = (double *)calloc(IR > 0 ? IR : 1, sizeof(double));
+    m->G0[n] = (double *)calloc(IR > 0 ? IR : 1, sizeof(double));
+    m->zprev_used[n] = (double *)calloc(IR > 0 ? IR : 1, sizeof(double));
+    m->band[n] = (double *)calloc(IR > 0 ? IR : 1, sizeof(double));
+    m->band_used[n] = (double *)calloc(IR > 0 ? IR : 1, sizeof(double));
+    m->kind[n] = (uint8_t *)calloc(IR > 0 ? IR : 1, 1);
+    if (!m->A[n] || !m->G[n] || !m->zprev[n] || !m->M[n] || !m->z[n] || !m->H[n] || !m->sel[n] ||
+        !m->A_prev[n] || !m->G0[n] || !m->zprev_used[n] || !m->band[n] || !m->band_used[n] || !m->kind[n]) {
       oran_model_destroy(m);
       return ORA_ENOMEM;
     }
@@ -241,7 +258,9 @@ int oran_model_get_state(const oran_model *m, int mode, double *zprev, double *t
 
 int oran_model_set_state(oran_model *m, int mode, const double *zprev, double ti_prev, int64_t k) {
   if (!m || mode < 0 || mode >= m->t->N || k < 0) return ORA_EINVAL;
-  if (zprev) memcpy(m->zprev[mode], zprev, (size_t)m->t->dims[mode] * m->R * sizeof(double));
+  const size_t IR = (size_t)m->t->dims[mode] * m->R;
+  if (zprev) memcpy(m->zprev[mode], zprev, IR * sizeof(double));
+  memset(m->band[mode], 0, IR * sizeof(double)); /* a Z^{k-1} from outside carries no band */
   m->ti_prev[mode] = ti_prev;
   m->k[mode] = k;
   return ORA_OK;
@@ -271,6 +290,99 @@ double oran_objective(const oran_model *m) {
   return t->norm2 - 2.0 * inner + model;
 }
 
+static double cd_step(double a, double g, double h) {
+  /* eq. 11-12: Newton step of one variable, clipped at zero; 0 where h = 0 */
+  if (!(h > 0.0)) return 0.0;
+  const double u = a - g / h;
+  return (u > 0.0 ? u : 0.0) - a;
+}
+
+/* Tie band of the last sweep of `mode`, as the three-way oracle records it
+ * (a diagnostic of the tests): the change of z (eq. 20) that a relative
+ * error tau in the terms of its gradient causes, to first order (|dz/dg| T)
+ * plus, for an interior or zero-gradient element, the second-order term
+ * (tau T / h)^2 (h + L/2); the element's kind from the margin of its
+ * selection (z, or z - Z^{k-1}) against that band plus the band of Z^{k-1}. */
+static void record_tie_band(oran_model *m, int mode) {
+  const int R = m->R;
+  const int64_t I = m->t->dims[mode];
+  const size_t IR = (size_t)I * R;
+  const double tau = m->tau, L = m->info[mode][0];
+  const int64_t k = m->k[mode];
+  const double *A = m->A_prev[mode], *H = m->H[mode], *M = m->M[mode], *G0 = m->G0[mode];
+  const double *z = m->z[mode], *zp = m->zprev_used[mode];
+  double *band = m->band[mode], *band_used = m->band_used[mode];
+  uint8_t *kind = m->kind[mode];
+  memcpy(band_used, band, IR * sizeof(double));
+  double sum_band = 0.0, sum_used = 0.0;
+  int64_t n_zero = 0, n_grad = 0, n_margin = 0;
+  for (int64_t q = 0; q < I; ++q)
+    for (int r = 0; r < R; ++r) {
+      const int64_t e = q * R + r;
+      const double h = H[r * R + r];
+      double T = fabs(M[e]);
+      for (int s = 0; s < R; ++s) T += fabs(A[q * R + s] * H[s * R + r]);
+      const double d = cd_step(A[e], G0[e], h);
+      const int interior = h > 0.0 && A[e] - G0[e] / h > 0.0;
+      const double dzdg = fabs(d) + (interior ? (fabs(G0[e]) + L * fabs(d)) / h : 0.0);
+      double bz = tau * (dzdg * T + 0.5 * L * d * d);
+      const int zero_grad = A[e] == 0.0 && h > 0.0 && T > 0.0 && fabs(G0[e]) <= tau * T;
+      if (interior || zero_grad) {
+        const double dd = tau * T / h;
+        bz += dd * dd * (h + 0.5 * L);
+      }
+      band[e] = bz;
+      const double margin = (k <= 1) ? z[e] : z[e] - zp[e];
+      const double width = (k <= 1) ? bz : bz + band_used[e];
+      if (zero_grad) {
+        kind[e] = 2;
+        ++n_grad;
+      } else if (width > 0.0 && fabs(margin) <= width) {
+        kind[e] = 3;
+        ++n_margin;
+      } else if (margin == 0.0) {
+        kind[e] = 1;
+        ++n_zero;
+      } else {
+        kind[e] = 0;
+      }
+      sum_band += bz;
+      sum_used += band_used[e];
+    }
+  const double band_ti = sum_band + sum_used;
+  m->band_info[mode][0] = band_ti;
+  m->band_info[mode][1] = (k >= 2 && fabs(m->info[mode][1] - m->info[mode][3]) <= band_ti) ? 1.0 : 0.0;
+  m->band_info[mode][2] = (double)n_zero;
+  m->band_info[mode][3] = (double)n_grad;
+  m->band_info[mode][4] = (double)n_margin;
+}
+
+int oran_sweep_band(const oran_model *m, int mode, double *band, uint8_t *kind, double *scalars) {
+  if (!m || mode < 0 || mode >= m->t->N) return ORA_EINVAL;
+  const size_t IR = (size_t)m->t->dims[mode] * m->R;
+  if (band) memcpy(band, m->band[mode], IR * sizeof(double));
+  if (kind) memcpy(kind, m->kind[mode], IR);
+  if (scalars) memcpy(scalars, m->band_info[mode], sizeof(m->band_info[mode]));
+  return ORA_OK;
+}
+
+int oran_row_outcome(const oran_model *m, int mode, int64_t q, const uint8_t *sel, double *out) {
+  if (!m || mode < 0 || mode >= m->t->N || !sel || !out) return ORA_EINVAL;
+  const int R = m->R;
+  if (q < 0 || q >= m->t->dims[mode]) return ORA_ERANGE;
+  const double *H = m->H[mode], *Mq = m->M[mode] + q * R;
+  memcpy(out, m->A_prev[mode] + q * R, (size_t)R * sizeof(double));
+  for (int r = 0; r < R; ++r) {
+    const double h = H[r * R + r];
+    if (!sel[r] || !(h > 0.0)) continue;
+    double g = -Mq[r];
+    for (int s = 0; s < R; ++s) g += out[s] * H[s * R + r];
+    const double u = out[r] - g / h;
+    out[r] = u > 0.0 ? u : 0.0;
+  }
+  return ORA_OK;
+}
+
 /* The steps of ora_sweep (sacd_oracle.c) with N - 1 other factors. */
 int oran_sweep(oran_model *m, int mode) {
   if (!m || mode < 0 || mode >= m->t->N) return ORA_EINVAL;
@@ -280,6 +392,8 @@ int oran_sweep(oran_model *m, int mode) {
   const size_t IR = (size_t)I * R;
   double *A = m->A[mode], *H = m->H[mode], *M = m->M[mode], *z = m->z[mode], *zprev = m->zprev[mode];
   uint8_t *sel = m->sel[mode];
+  memcpy(m->A_prev[mode], A, IR * sizeof(double));
+  memcpy(m->zprev_used[mode], zprev, IR * sizeof(double));
   /* 1 */
   m->k[mode] += 1;
   const int64_t k = m->k[mode];
@@ -296,8 +410,7 @@ int oran_sweep(oran_model *m, int mode) {
   /* 3 */
   oran_mttkrp(t, mode, R, (const double *const *)m->A, M);
   /* 4, 5: G0 = -M + A H, step, importance */
-  double *G0 = (double *)malloc((IR > 0 ? IR : 1) * sizeof(double));
-  if (!G0) return ORA_ENOMEM;
+  double *G0 = m->G0[mode];
   for (int64_t q = 0; q < I; ++q)
     for (int r = 0; r < R; ++r) {
       double ah = 0.0;
@@ -339,7 +452,6 @@ int oran_sweep(oran_model *m, int mode) {
       a[r] = u > 0.0 ? u : 0.0;
     }
   }
-  free(G0);
   /* 10, 11 */
   gram(A, I, R, m->G[mode]);
   double inner = 0.0;
@@ -356,6 +468,9 @@ int oran_sweep(oran_model *m, int mode) {
   m->info[mode][3] = ti_used;
   m->info[mode][4] = t->norm2 - 2.0 * inner + model;
   m->info[mode][5] = (double)nsel;
+  m->info[mode][6] = inner;
+  m->info[mode][7] = model;
+  record_tie_band(m, mode);
   return ORA_OK;
 }
 

@@ -47,9 +47,19 @@ int oran_model_set_state(oran_model *m, int mode, const double *zprev, double ti
 /* One sweep of mode n (Alg. 1 body; Gauss-Seidel reading as the 3-way oracle). */
 int oran_sweep(oran_model *m, int mode);
 /* Record of the last sweep of `mode` (any pointer may be NULL): M, z (I_n x R),
- * sel (uint8), H (R x R), scalars [L, ti, flip, ti_prev, f, nsel]. */
+ * sel (uint8), H (R x R), scalars [L, ti, flip, ti_prev, f, nsel, <M, A_n>,
+ * sum of the Hadamard product of all Grams]. */
 int oran_sweep_info(const oran_model *m, int mode, double *M, double *z, uint8_t *sel, double *H,
                     double *scalars);
+/* Tie band of the last sweep of `mode` (a diagnostic of the tests, as
+ * ora_sweep_band): band (I_n x R), kind (0 decided, 1 exact zero, 2
+ * zero-gradient tie, 3 margin tie), scalars [band of ti, global tie,
+ * exact zeros, zero-gradient ties, margin ties].  set_state clears the band
+ * of the Z^{k-1} it sets. */
+int oran_sweep_band(const oran_model *m, int mode, double *band, uint8_t *kind, double *scalars);
+/* Row q of the last sweep of `mode` updated (step 9) under the decisions
+ * sel (R bytes) instead of the oracle's own: out (R doubles). */
+int oran_row_outcome(const oran_model *m, int mode, int64_t q, const uint8_t *sel, double *out);
 /* eq. 6 for the current factors: ||X||^2 - 2 <X, Xhat> + sum_rs (prod_m Gram_m)_rs. */
 double oran_objective(const oran_model *m);
 

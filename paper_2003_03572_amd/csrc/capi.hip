@@ -2105,3 +2105,811 @@ void sacd_server_destroy(sacd_server *S) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ N-way --
+//
+// Tensors of N modes (Sec. 3 defines the factorization for any number of
+// modes; the three-way sweep carries over with the Khatri-Rao product of the
+// N - 1 other factors in the MTTKRP and the Hadamard product of their Gram
+// matrices as H).  Keys pack mode n's index in the high field and the other
+// indices below it in increasing mode order.  The sweep runs the N-way MTTKRP
+// (nway.hip), then the three-way element kernels with H formed from P, the
+// product of the other Grams, and a matrix of ones.
+
+struct sacd_ntensor {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  DevAlloc mem;
+  int N = 0;
+  int64_t dims[kMaxModes] = {};
+  long long nnz = 0;
+  NLayout lay[kMaxModes] = {};
+  unsigned long long *keys[kMaxModes] = {};
+  float *vals[kMaxModes] = {};
+  int *ptr[kMaxModes] = {};
+  std::vector<int> hptr[kMaxModes];
+  double norm2 = 0.0;
+  int nmodels = 0;
+  bool destroy_pending = false;
+};
+
+struct sacd_nmodel {
+  sacd_ntensor *t = nullptr;
+  hipStream_t s = nullptr;
+  DevAlloc mem;
+  int N = 0, R = 0, RP = 0;
+  bool diag = false;
+  float *A[kMaxModes] = {}, *Z[kMaxModes] = {}, *M[kMaxModes] = {}, *H[kMaxModes] = {};
+  double *G64[kMaxModes] = {};
+  HInfo *hinfo[kMaxModes] = {};
+  long long *colcnt[kMaxModes] = {};
+  uint8_t *selmask[kMaxModes] = {};
+  ModeState *st = nullptr;  // N entries
+  double *P = nullptr, *ones = nullptr;
+  float *part = nullptr, *gpart = nullptr;
+  double *mpart = nullptr;
+  unsigned *gcounter = nullptr;
+  double *ti_part = nullptr, *inner_part = nullptr;
+  int *cnt_part = nullptr, *flag = nullptr;
+  double *full_part = nullptr, *full_out = nullptr;
+  unsigned *full_cnt = nullptr;
+  int full_nparts = 0;
+  int nparts[kMaxModes] = {};
+  MttkrpPlan plan[kMaxModes];
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<hipEvent_t> tev;  // 3 per sweep: before and after the MTTKRP, end of the sweep
+  double *h_pinned = nullptr;
+  bool counted = false;
+  int last_mode = -1;
+  bool dirty = true;
+};
+
+namespace {
+
+// Field layout of mode n: n first (highest bits), then the other modes in
+// increasing order; field f sits above the fields after it.
+NLayout nlayout(int N, const int64_t *dims, int n) {
+  NLayout l{};
+  l.nf = N;
+  int order[kMaxModes];
+  order[0] = n;
+  for (int m = 0, f = 1; m < N; ++m)
+    if (m != n) order[f++] = m;
+  int sh = 0;
+  for (int f = N - 1; f >= 0; --f) {
+    const int b = bits_for(dims[order[f]]);
+    l.sh[f] = sh;
+    l.mask[f] = b == 0 ? 0ull : (b == 64 ? ~0ull : ((1ull << b) - 1ull));
+    sh += b;
+  }
+  for (int f = 0; f < N; ++f) l.dims[f] = dims[order[f]];
+  return l;
+}
+
+// Work plan of mode n of an N-way tensor: slices cut into segments of at most
+// kSegment entries, longest first (stable); one partial slot per unit of a
+// split slice, numbered slice by slice in entry order.
+sacd_status build_nplan(const sacd_ntensor *t, int n, DevAlloc &mem, MttkrpPlan *out) {
+  const std::vector<int> &ptr = t->hptr[n];
+  const int I = (int)t->dims[n];
+  std::vector<int4> units;
+  for (int r = 0; r < I; ++r) {
+    const int len = ptr[r + 1] - ptr[r];
+    if (len == 0) continue;
+    if (len <= kSegment) {
+      units.push_back(make_int4(r, ptr[r], len, -1));
+      continue;
+    }
+    for (int b = ptr[r]; b < ptr[r + 1]; b += kSegment)
+      units.push_back(make_int4(r, b, std::min(kSegment, ptr[r + 1] - b), -2));
+  }
+  std::stable_sort(units.begin(), units.end(), [](const int4 &x, const int4 &y) { return x.z > y.z; });
+  std::vector<int> su;
+  for (size_t u = 0; u < units.size(); ++u)
+    if (units[u].w == -2) su.push_back((int)u);
+  std::stable_sort(su.begin(), su.end(), [&](int x, int y) {
+    if (units[x].x != units[y].x) return units[x].x < units[y].x;
+    return units[x].y < units[y].y;
+  });
+  std::vector<int> uslot(units.size(), -1);
+  std::vector<int4> ulongs;
+  for (size_t k = 0; k < su.size(); ++k) {
+    uslot[su[k]] = (int)k;
+    if (ulongs.empty() || ulongs.back().x != units[su[k]].x) ulongs.push_back(make_int4(units[su[k]].x, (int)k, 0, 0));
+    ulongs.back().z += 1;
+  }
+  MttkrpPlan p{};
+  p.nnz = t->nnz;
+  p.nunits = (int)units.size();
+  int4 *du = nullptr, *dul = nullptr;
+  int *dus = nullptr;
+  SACD_TRY(mem.get_t(units.size() + 1, &du));
+  SACD_TRY(mem.get_t(units.size() + 1, &dus));
+  SACD_TRY(mem.get_t(ulongs.size() + 1, &dul));
+  if (!units.empty()) {
+    HIP_TRY(hipMemcpyAsync(du, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, t->stream));
+    HIP_TRY(hipMemcpyAsync(dus, uslot.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, t->stream));
+  }
+  if (!ulongs.empty())
+    HIP_TRY(hipMemcpyAsync(dul, ulongs.data(), sizeof(int4) * ulongs.size(), hipMemcpyHostToDevice, t->stream));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  p.units = du;
+  p.uslot = dus;
+  p.nuslots = (int)su.size();
+  p.ulongs = dul;
+  p.nulong = (int)ulongs.size();
+  *out = p;
+  return SACD_OK;
+}
+
+sacd_status create_ntensor_impl(sacd_ntensor *t, const int32_t *idx, const float *vals, long long n) {
+  const hipStream_t s = t->stream;
+  const int N = t->N;
+  for (int m = 0; m < N; ++m) t->lay[m] = nlayout(N, t->dims, m);
+  int total_bits = 0;
+  for (int m = 0; m < N; ++m) total_bits += bits_for(t->dims[m]);
+  DevAlloc tmp;
+  tmp.alloc = t->mem.alloc;
+  tmp.custom = t->mem.custom;
+  unsigned long long *k0 = nullptr, *k1 = nullptr;
+  float *v0 = nullptr, *v1 = nullptr;
+  int *err = nullptr, *cnt = nullptr;
+  void *temp = nullptr;
+  size_t tb = std::max(radix_sort_temp_bytes(n), dedup_temp_bytes(n));
+  for (int m = 0; m < N; ++m) tb = std::max(tb, build_ptr_temp_bytes(n, (int)t->dims[m]));
+  tb = std::max(tb, (size_t)8192);
+  sacd_status rs = SACD_OK;
+#define NT_TRY(expr)           \
+  do {                         \
+    rs = (expr);               \
+    if (rs != SACD_OK) {       \
+      tmp.release_all();       \
+      return rs;               \
+    }                          \
+  } while (0)
+#define NT_HIP(expr)                                                                \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      tmp.release_all();                                                            \
+      return fail(SACD_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));  \
+    }                                                                               \
+  } while (0)
+  NT_TRY(tmp.get_t(n > 0 ? n : 1, &k0));
+  NT_TRY(tmp.get_t(n > 0 ? n : 1, &k1));
+  NT_TRY(tmp.get_t(n > 0 ? n : 1, &v0));
+  NT_TRY(tmp.get_t(n > 0 ? n : 1, &v1));
+  NT_TRY(tmp.get_t(4, &err));
+  NT_TRY(tmp.get_t(4, &cnt));
+  NT_TRY(tmp.get(tb, &temp));
+  NT_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
+  NT_HIP(launch_make_keys_n(idx, vals, n, t->lay[0], k0, v0, err, s));
+  int herr = 0;
+  NT_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  NT_HIP(hipStreamSynchronize(s));
+  if (herr & 1) {
+    tmp.release_all();
+    return fail(SACD_ERR_OUT_OF_RANGE, "a coordinate is outside dims");
+  }
+  if (herr & 2) {
+    tmp.release_all();
+    return fail(SACD_ERR_NUMERIC, "a value is NaN or Inf");
+  }
+  // mode 0: stable sort by the whole key, duplicates merged in input order
+  bool in_alt = false;
+  NT_HIP(radix_sort_pairs(k0, v0, k1, v1, n, 0, total_bits, temp, s, &in_alt));
+  unsigned long long *ks = in_alt ? k1 : k0, *kd = in_alt ? k0 : k1;
+  float *vs = in_alt ? v1 : v0, *vd = in_alt ? v0 : v1;
+  NT_HIP(dedup_sorted(ks, vs, n, kd, vd, cnt, temp, s));
+  int hcnt = 0;
+  NT_HIP(hipMemcpyAsync(&hcnt, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
+  NT_HIP(hipStreamSynchronize(s));
+  const long long u = hcnt;
+  t->nnz = u;
+  for (int m = 0; m < N; ++m) {
+    NT_TRY(t->mem.get_t((size_t)u + kKeySlack, &t->keys[m]));
+    NT_TRY(t->mem.get_t((size_t)u + kKeySlack, &t->vals[m]));
+    NT_TRY(t->mem.get_t((size_t)t->dims[m] + 1, &t->ptr[m]));
+    NT_HIP(hipMemsetAsync(t->keys[m] + u, 0, sizeof(unsigned long long) * kKeySlack, s));
+    NT_HIP(hipMemsetAsync(t->vals[m] + u, 0, sizeof(float) * kKeySlack, s));
+  }
+  if (u > 0) {
+    NT_HIP(hipMemcpyAsync(t->keys[0], kd, sizeof(unsigned long long) * u, hipMemcpyDeviceToDevice, s));
+    NT_HIP(hipMemcpyAsync(t->vals[0], vd, sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+  }
+  // mode m > 0: the mode-0 order, re-keyed and sorted stably by i_m alone, is
+  // (i_m, then the other indices in increasing mode order)
+  for (int m = 1; m < N; ++m) {
+    NShifts to{};
+    // mode q sits in field 1 + q - (q > m) of mode m's layout (field 0: mode m)
+    for (int q = 0; q < N; ++q) to.sh[q] = t->lay[m].sh[q == m ? 0 : (q < m ? q + 1 : q)];
+    NT_HIP(launch_rekey_n(t->keys[0], u, t->lay[0], to, k0, s));
+    if (u > 0) NT_HIP(hipMemcpyAsync(v0, t->vals[0], sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+    bool alt = false;
+    const int lo = t->lay[m].sh[0];
+    NT_HIP(radix_sort_pairs(k0, v0, k1, v1, u, lo, lo + bits_for(t->dims[m]), temp, s, &alt));
+    if (u > 0) {
+      NT_HIP(hipMemcpyAsync(t->keys[m], alt ? k1 : k0, sizeof(unsigned long long) * u, hipMemcpyDeviceToDevice, s));
+      NT_HIP(hipMemcpyAsync(t->vals[m], alt ? v1 : v0, sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+    }
+  }
+  for (int m = 0; m < N; ++m) {
+    NT_HIP(build_ptr(t->keys[m], u, t->lay[m].sh[0], (int)t->dims[m], t->ptr[m], temp, s));
+    t->hptr[m].resize((size_t)t->dims[m] + 1);
+    NT_HIP(hipMemcpyAsync(t->hptr[m].data(), t->ptr[m], sizeof(int) * ((size_t)t->dims[m] + 1),
+                          hipMemcpyDeviceToHost, s));
+  }
+  NT_HIP(hipStreamSynchronize(s));
+  {
+    double *part = (double *)temp;
+    NT_HIP(launch_norm2(t->vals[0], u, part, 512, part + 512, s));
+    NT_HIP(hipMemcpyAsync(&t->norm2, part + 512, sizeof(double), hipMemcpyDeviceToHost, s));
+    NT_HIP(hipStreamSynchronize(s));
+  }
+  tmp.release_all();
+  return SACD_OK;
+#undef NT_TRY
+#undef NT_HIP
+}
+
+void release_ntensor(sacd_ntensor *t) {
+  (void)hipSetDevice(t->dev);
+  if (t->stream) (void)hipStreamSynchronize(t->stream);
+  t->mem.release_all();
+  if (t->own_stream && t->stream) (void)hipStreamDestroy(t->stream);
+  delete t;
+}
+
+sacd_status check_nmode(const sacd_nmodel *m, int32_t mode) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (mode < 0 || mode >= m->N) return fail(SACD_ERR_INVALID_ARG, "mode %d not in [0, %d)", mode, m->N);
+  return SACD_OK;
+}
+
+sacd_status nrecompute_gram(sacd_nmodel *m, int n) {
+  HIP_TRY(launch_gram_partial(m->RP, false, (int)m->t->dims[n], m->A[n], m->gpart, nullptr, m->s));
+  GramArgs g{};
+  g.nparts = m->nparts[n];
+  g.gpart = m->gpart;
+  g.mpart = m->mpart;
+  g.Gn = m->G64[n];
+  g.with_f = 0;
+  g.counter = m->gcounter;
+  g.st = m->st + n;
+  HIP_TRY(launch_gram_final(m->RP, g, m->s));
+  return SACD_OK;
+}
+
+// One sweep of mode n: P = product of the other Grams; the N-way MTTKRP; H, L
+// and the split slices; importance and total; selection and Gauss-Seidel
+// update; Gram, counts and objective.  mark (optional): 3 events.
+sacd_status enqueue_nsweep(sacd_nmodel *m, int n, const hipEvent_t *mark = nullptr) {
+  const sacd_ntensor *t = m->t;
+  hipStream_t s = m->s;
+  const int RP = m->RP, N = m->N, I = (int)t->dims[n];
+  NGrams ng{};
+  ng.n = N;
+  for (int q = 0; q < N; ++q) ng.G[q] = m->G64[q];
+  HIP_TRY(launch_prod_grams(ng, n, RP, m->P, m->ones, s));
+  NMttkrpArgs a{};
+  a.keys = t->keys[n];
+  a.vals = t->vals[n];
+  a.units = m->plan[n].units;
+  a.uslot = m->plan[n].uslot;
+  a.nunits = m->plan[n].nunits;
+  a.nother = N - 1;
+  for (int q = 0, f = 0; q < N; ++q) {
+    if (q == n) continue;
+    a.A[f] = m->A[q];
+    a.sh[f] = t->lay[n].sh[f + 1];
+    a.mask[f] = t->lay[n].mask[f + 1];
+    ++f;
+  }
+  a.M = m->M[n];
+  a.part = m->part;
+  if (mark) HIP_TRY(hipEventRecord(mark[0], s));
+  HIP_TRY(launch_mttkrp_n(RP, a, s));
+  if (mark) HIP_TRY(hipEventRecord(mark[1], s));
+  FixArgs fx{};
+  fx.longs = m->plan[n].ulongs;
+  fx.nlong = m->plan[n].nulong;
+  fx.part = m->part;
+  fx.M = m->M[n];
+  fx.Ga = m->P;
+  fx.Gb = m->ones;
+  fx.H = m->H[n];
+  fx.hinfo = m->hinfo[n];
+  fx.st = m->st + n;
+  HIP_TRY(launch_mttkrp_fix(RP, fx, s));
+  ImpArgs ia{};
+  ia.I = I;
+  ia.A = m->A[n];
+  ia.M = m->M[n];
+  ia.H = m->H[n];
+  ia.hi = m->hinfo[n];
+  ia.ti_part = m->ti_part;
+  ia.st = m->st + n;
+  HIP_TRY(launch_importance(RP, false, ia, s));
+  UpdArgs ua{};
+  ua.I = I;
+  ua.A = m->A[n];
+  ua.M = m->M[n];
+  ua.Z = m->Z[n];
+  ua.H = m->H[n];
+  ua.hi = m->hinfo[n];
+  ua.st = m->st + n;
+  ua.gpart = m->gpart;
+  ua.gpart_obj = nullptr;
+  ua.inner_part = m->inner_part;
+  ua.cnt_part = m->cnt_part;
+  ua.selmask = m->selmask[n];
+  HIP_TRY(launch_select_update(RP, (int)SACD_UPDATE_GS, m->diag, false, ua, s));
+  GramArgs g{};
+  g.nparts = m->nparts[n];
+  g.gpart = m->gpart;
+  g.mpart = m->mpart;
+  g.Gn = m->G64[n];
+  g.Ga = m->P;  // sum over the Hadamard product of all Grams = sum(Gram_n * P * 1)
+  g.Gb = m->ones;
+  g.inner_part = m->inner_part;
+  g.cnt_part = m->cnt_part;
+  g.colcnt = m->colcnt[n];
+  g.normX2 = t->norm2;
+  g.with_f = 1;
+  g.counter = m->gcounter;
+  g.st = m->st + n;
+  HIP_TRY(launch_gram_final(RP, g, s));
+  if (mark) HIP_TRY(hipEventRecord(mark[2], s));
+  return SACD_OK;
+}
+
+void drop_ngraph(sacd_nmodel *m) {
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->gexec = nullptr;
+  m->graph = nullptr;
+}
+
+sacd_status ensure_ngraph(sacd_nmodel *m) {
+  if (m->gexec) return SACD_OK;
+  HIP_TRY(hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal));
+  sacd_status st = SACD_OK;
+  for (int n = 0; n < m->N && st == SACD_OK; ++n) st = enqueue_nsweep(m, n);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(m->s, &g);
+  if (st != SACD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SACD_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t ge = nullptr;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(SACD_ERR_DEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  m->graph = g;
+  m->gexec = ge;
+  return SACD_OK;
+}
+
+sacd_status read_nstate(const sacd_nmodel *m, int n, ModeState *out) {
+  HIP_TRY(hipMemcpyAsync(out, m->st + n, sizeof(ModeState), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+// Objective of the current factors from scratch: ||X||^2 - 2 <X, Xhat> + the
+// sum over the Hadamard product of all Grams (FP64).
+sacd_status nobjective_full(sacd_nmodel *m, double *f) {
+  const sacd_ntensor *t = m->t;
+  const int RP = m->RP, N = m->N;
+  NFactors F{};
+  for (int q = 0; q < N; ++q) F.A[q] = m->A[q];
+  HIP_TRY(launch_inner_full_n(t->keys[0], t->vals[0], t->nnz, t->lay[0], F, RP, m->full_part, m->full_nparts,
+                              m->full_out, m->full_cnt, m->s));
+  std::vector<double> G((size_t)N * RP * RP);
+  double inner = 0.0;
+  for (int q = 0; q < N; ++q)
+    HIP_TRY(hipMemcpyAsync(G.data() + (size_t)q * RP * RP, m->G64[q], sizeof(double) * RP * RP,
+                           hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipMemcpyAsync(&inner, m->full_out, sizeof(double), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  double model = 0.0;
+  for (int i = 0; i < RP * RP; ++i) {
+    double p = 1.0;
+    for (int q = 0; q < N; ++q) p *= G[(size_t)q * RP * RP + i];
+    model += p;
+  }
+  *f = t->norm2 - 2.0 * inner + model;
+  return SACD_OK;
+}
+
+sacd_status init_nmodel_impl(sacd_nmodel *m, uint64_t seed) {
+  const sacd_ntensor *t = m->t;
+  const int RP = m->RP, N = m->N;
+  DevAlloc &A = m->mem;
+  int maxI = 0, maxus = 1;
+  for (int n = 0; n < N; ++n) {
+    const int I = (int)t->dims[n];
+    maxI = std::max(maxI, I);
+    SACD_TRY(build_nplan(t, n, A, &m->plan[n]));
+    maxus = std::max(maxus, m->plan[n].nuslots);
+    m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
+    const size_t IR = (size_t)I * RP;
+    SACD_TRY(A.get_t(IR, &m->A[n]));
+    SACD_TRY(A.get_t(IR, &m->Z[n]));
+    SACD_TRY(A.get_t(IR, &m->M[n]));
+    SACD_TRY(A.get_t(IR, &m->selmask[n]));
+    SACD_TRY(A.get_t((size_t)RP * RP, &m->H[n]));
+    SACD_TRY(A.get_t((size_t)RP * RP, &m->G64[n]));
+    SACD_TRY(A.get_t(1, &m->hinfo[n]));
+    SACD_TRY(A.get_t((size_t)RP, &m->colcnt[n]));
+  }
+  const int maxparts = (maxI + rows_per_block(RP) - 1) / rows_per_block(RP);
+  SACD_TRY(A.get_t((size_t)N, &m->st));
+  SACD_TRY(A.get_t((size_t)RP * RP, &m->P));
+  SACD_TRY(A.get_t((size_t)RP * RP, &m->ones));
+  SACD_TRY(A.get_t((size_t)maxus * RP, &m->part));
+  SACD_TRY(A.get_t((size_t)maxparts * RP * RP, &m->gpart));
+  SACD_TRY(A.get_t((size_t)std::max(maxparts, importance_blocks(RP, maxI)), &m->ti_part));
+  SACD_TRY(A.get_t((size_t)maxparts, &m->inner_part));
+  SACD_TRY(A.get_t((size_t)maxparts * RP, &m->cnt_part));
+  SACD_TRY(A.get_t((size_t)gram_model_parts(RP), &m->mpart));
+  SACD_TRY(A.get_t(1, &m->gcounter));
+  SACD_TRY(A.get_t(4, &m->flag));
+  m->full_nparts = 1024;
+  SACD_TRY(A.get_t((size_t)m->full_nparts, &m->full_part));
+  SACD_TRY(A.get_t(1, &m->full_out));
+  SACD_TRY(A.get_t(4, &m->full_cnt));
+  SACD_TRY(pinned_get(&m->h_pinned));
+  hipStream_t s = m->s;
+  HIP_TRY(hipMemsetAsync(m->st, 0, (size_t)N * sizeof(ModeState), s));
+  HIP_TRY(hipMemsetAsync(m->full_cnt, 0, 16, s));
+  HIP_TRY(hipMemsetAsync(m->gcounter, 0, sizeof(unsigned), s));
+  unsigned long long off = 0;
+  for (int n = 0; n < N; ++n) {
+    const int I = (int)t->dims[n];
+    HIP_TRY(launch_init_factor(m->A[n], I, m->R, RP, seed, off, s));
+    off += (unsigned long long)I * m->R;
+    HIP_TRY(hipMemsetAsync(m->Z[n], 0, sizeof(float) * I * RP, s));
+    HIP_TRY(hipMemsetAsync(m->M[n], 0, sizeof(float) * I * RP, s));  // rows of empty slices stay zero
+    HIP_TRY(hipMemsetAsync(m->selmask[n], 0, (size_t)I * RP, s));
+    HIP_TRY(hipMemsetAsync(m->colcnt[n], 0, sizeof(long long) * RP, s));
+  }
+  for (int n = 0; n < N; ++n) SACD_TRY(nrecompute_gram(m, n));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SACD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sacd_status sacd_create_ntensor(int32_t N, const int64_t *dims, int64_t nnz, const int32_t *idx, const float *vals,
+                                const sacd_allocator *alloc, void *stream, sacd_ntensor **out) {
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (N < 2 || N > kMaxModes) return fail(SACD_ERR_INVALID_ARG, "N = %d not in [2, %d]", (int)N, kMaxModes);
+  if (!dims) return fail(SACD_ERR_INVALID_ARG, "dims is NULL");
+  (void)hipGetLastError();
+  int bits = 0;
+  for (int n = 0; n < N; ++n) {
+    if (dims[n] < 1 || dims[n] > 2147483647LL)
+      return fail(SACD_ERR_INVALID_ARG, "dims[%d] = %lld not in [1, 2^31 - 1]", n, (long long)dims[n]);
+    bits += bits_for(dims[n]);
+  }
+  if (bits > 64) return fail(SACD_ERR_INVALID_ARG, "mode lengths need %d > 64 key bits", bits);
+  if (nnz < 0 || nnz > 2147483647LL) return fail(SACD_ERR_INVALID_ARG, "nnz = %lld not in [0, 2^31 - 1]", (long long)nnz);
+  if (nnz > 0 && (!idx || !vals)) return fail(SACD_ERR_INVALID_ARG, "idx / vals is NULL");
+  if (alloc && (!alloc->alloc || !alloc->release)) return fail(SACD_ERR_INVALID_ARG, "allocator callbacks are NULL");
+  sacd_ntensor *t = new (std::nothrow) sacd_ntensor();
+  if (!t) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
+  if (hipGetDevice(&t->dev) != hipSuccess) {
+    delete t;
+    return fail(SACD_ERR_DEVICE, "no HIP device");
+  }
+  t->N = N;
+  for (int n = 0; n < N; ++n) t->dims[n] = dims[n];
+  if (alloc) {
+    t->mem.alloc = *alloc;
+    t->mem.custom = true;
+  }
+  sacd_status st = make_stream(stream, &t->stream, &t->own_stream);
+  if (st == SACD_OK) st = create_ntensor_impl(t, idx, vals, nnz);
+  if (st != SACD_OK) {
+    release_ntensor(t);
+    return st;
+  }
+  *out = t;
+  return SACD_OK;
+}
+
+sacd_status sacd_ntensor_info(const sacd_ntensor *t, int32_t *N, int64_t *dims, int64_t *nnz, double *norm2,
+                              int64_t *device_bytes) {
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (N) *N = t->N;
+  if (dims)
+    for (int n = 0; n < t->N; ++n) dims[n] = t->dims[n];
+  if (nnz) *nnz = t->nnz;
+  if (norm2) *norm2 = t->norm2;
+  if (device_bytes) *device_bytes = t->mem.bytes;
+  return SACD_OK;
+}
+
+sacd_status sacd_ntensor_mode_coo(const sacd_ntensor *t, int32_t mode, int32_t *coords, float *vals, int64_t *ptr) {
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (mode < 0 || mode >= t->N) return fail(SACD_ERR_INVALID_ARG, "mode %d not in [0, %d)", mode, t->N);
+  SACD_TRY(enter(t->dev));
+  HIP_TRY(launch_export_coo_n(t->keys[mode], t->vals[mode], t->nnz, t->lay[mode], coords, vals, t->ptr[mode],
+                              (int)t->dims[mode], ptr, t->stream));
+  HIP_TRY(hipStreamSynchronize(t->stream));
+  return SACD_OK;
+}
+
+void sacd_destroy_ntensor(sacd_ntensor *t) {
+  if (!t) return;
+  if (t->nmodels > 0) {
+    t->destroy_pending = true;
+    return;
+  }
+  release_ntensor(t);
+}
+
+sacd_status sacd_init_nfactors(sacd_ntensor *t, int32_t R, uint64_t seed, sacd_nmodel **out) {
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!t) return fail(SACD_ERR_INVALID_ARG, "tensor is NULL");
+  if (R < 1 || R > kMaxRP) return fail(SACD_ERR_INVALID_ARG, "rank %d not in [1, %d]", R, kMaxRP);
+  SACD_TRY(enter(t->dev));
+  sacd_nmodel *m = new (std::nothrow) sacd_nmodel();
+  if (!m) return fail(SACD_ERR_NO_MEMORY, "host allocation failed");
+  m->t = t;
+  m->s = t->stream;
+  m->mem.alloc = t->mem.alloc;
+  m->mem.custom = t->mem.custom;
+  m->N = t->N;
+  m->R = R;
+  m->RP = pad_rank(R);
+  sacd_status st = init_nmodel_impl(m, seed);
+  if (st != SACD_OK) {
+    sacd_destroy_nmodel(m);
+    return st;
+  }
+  t->nmodels++;
+  m->counted = true;
+  *out = m;
+  return SACD_OK;
+}
+
+sacd_status sacd_nsweep(sacd_nmodel *m, int32_t mode) {
+  SACD_TRY(check_nmode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(enqueue_nsweep(m, mode));
+  m->last_mode = mode;
+  m->dirty = false;
+  return SACD_OK;
+}
+
+sacd_status sacd_niterate(sacd_nmodel *m, int32_t n_iters) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (n_iters < 0) return fail(SACD_ERR_INVALID_ARG, "n_iters < 0");
+  if (n_iters == 0) return SACD_OK;
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(ensure_ngraph(m));
+  for (int i = 0; i < n_iters; ++i) HIP_TRY(hipGraphLaunch(m->gexec, m->s));
+  m->last_mode = m->N - 1;
+  m->dirty = false;
+  return SACD_OK;
+}
+
+sacd_status sacd_niterate_timed(sacd_nmodel *m, int32_t n_iters, float *mttkrp_ms, float *sweep_ms) {
+  if (!m || !mttkrp_ms) return fail(SACD_ERR_INVALID_ARG, "model or output is NULL");
+  if (n_iters < 1 || n_iters > 100000) return fail(SACD_ERR_INVALID_ARG, "n_iters out of [1, 100000]");
+  SACD_TRY(enter(m->t->dev));
+  const int N = m->N;
+  while ((int)m->tev.size() < 3 * N * n_iters) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    m->tev.push_back(e);
+  }
+  for (int i = 0; i < n_iters; ++i)
+    for (int n = 0; n < N; ++n) SACD_TRY(enqueue_nsweep(m, n, &m->tev[3 * (N * i + n)]));
+  m->last_mode = N - 1;
+  m->dirty = false;
+  HIP_TRY(hipStreamSynchronize(m->s));
+  for (int i = 0; i < n_iters; ++i)
+    for (int n = 0; n < N; ++n) {
+      const hipEvent_t *e = &m->tev[3 * (N * i + n)];
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, e[0], e[1]));
+      mttkrp_ms[N * i + n] = ms;
+      if (sweep_ms) {
+        HIP_TRY(hipEventElapsedTime(&ms, e[0], e[2]));
+        sweep_ms[N * i + n] = ms;
+      }
+    }
+  return SACD_OK;
+}
+
+sacd_status sacd_nfit(sacd_nmodel *m, double *fit, double *objective) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  SACD_TRY(enter(m->t->dev));
+  double f = 0.0;
+  if (m->last_mode < 0 || m->dirty) {
+    SACD_TRY(nobjective_full(m, &f));
+  } else {
+    ModeState s;
+    SACD_TRY(read_nstate(m, m->last_mode, &s));
+    f = s.f;
+  }
+  if (objective) *objective = f;
+  if (!(m->t->norm2 > 0.0)) return fail(SACD_ERR_NUMERIC, "||X|| = 0: the fit is undefined");
+  if (fit) *fit = 1.0 - std::sqrt(f > 0.0 ? f : 0.0) / std::sqrt(m->t->norm2);
+  return SACD_OK;
+}
+
+sacd_status sacd_nrun_until(sacd_nmodel *m, double tol, int32_t max_iter, int32_t *iters_done, double *final_fit) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  if (max_iter < 1 || !(tol >= 0.0)) return fail(SACD_ERR_INVALID_ARG, "max_iter < 1 or tol < 0");
+  if (!(m->t->norm2 > 0.0)) return fail(SACD_ERR_NUMERIC, "||X|| = 0: the fit is undefined");
+  SACD_TRY(enter(m->t->dev));
+  SACD_TRY(ensure_ngraph(m));
+  const double nx = std::sqrt(m->t->norm2);
+  double prev = 0.0, fit = 0.0;
+  int it;
+  for (it = 1; it <= max_iter; ++it) {
+    HIP_TRY(hipGraphLaunch(m->gexec, m->s));
+    HIP_TRY(hipMemcpyAsync(m->h_pinned, &m->st[m->N - 1].f, sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    m->last_mode = m->N - 1;
+    m->dirty = false;
+    const double f = m->h_pinned[0];
+    fit = 1.0 - std::sqrt(f > 0.0 ? f : 0.0) / nx;
+    if (it >= 2 && std::fabs(fit - prev) < tol * std::fabs(prev)) break;
+    prev = fit;
+  }
+  if (it > max_iter) it = max_iter;
+  if (iters_done) *iters_done = it;
+  if (final_fit) *final_fit = fit;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_nfactor(const sacd_nmodel *m, int32_t mode, float *dst) {
+  SACD_TRY(check_nmode(m, mode));
+  if (!dst) return fail(SACD_ERR_INVALID_ARG, "dst is NULL");
+  SACD_TRY(enter(m->t->dev));
+  HIP_TRY(launch_copy_rows(m->A[mode], m->RP, dst, m->R, (int)m->t->dims[mode], m->R, m->R, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_set_nfactor(sacd_nmodel *m, int32_t mode, const float *src) {
+  SACD_TRY(check_nmode(m, mode));
+  if (!src) return fail(SACD_ERR_INVALID_ARG, "src is NULL");
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  HIP_TRY(hipMemsetAsync(m->flag, 0, sizeof(int), m->s));
+  HIP_TRY(launch_check_factor(src, (long long)I * m->R, m->flag, m->s));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, m->flag, sizeof(int), hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  if (hflag) return fail(SACD_ERR_NUMERIC, "factor has negative or non-finite entries");
+  HIP_TRY(launch_copy_rows(src, m->R, m->A[mode], m->RP, I, m->R, m->RP, m->s));
+  SACD_TRY(nrecompute_gram(m, mode));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  m->dirty = true;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_nstate(const sacd_nmodel *m, int32_t mode, float *zprev, double *ti_prev, int64_t *k) {
+  SACD_TRY(check_nmode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  if (zprev) HIP_TRY(launch_copy_rows(m->Z[mode], m->RP, zprev, m->R, I, m->R, m->R, m->s));
+  ModeState s;
+  SACD_TRY(read_nstate(m, mode, &s));
+  if (ti_prev) *ti_prev = s.ti_prev;
+  if (k) *k = s.k;
+  return SACD_OK;
+}
+
+sacd_status sacd_set_nstate(sacd_nmodel *m, int32_t mode, const float *zprev, double ti_prev, int64_t k) {
+  SACD_TRY(check_nmode(m, mode));
+  if (k < 0) return fail(SACD_ERR_INVALID_ARG, "k < 0");
+  if (k > 0 && !zprev) return fail(SACD_ERR_INVALID_ARG, "zprev is NULL with k > 0");
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode];
+  if (zprev) HIP_TRY(launch_copy_rows(zprev, m->R, m->Z[mode], m->RP, I, m->R, m->RP, m->s));
+  ModeState s;
+  SACD_TRY(read_nstate(m, mode, &s));
+  s.k = k;
+  s.ti_prev = ti_prev;
+  HIP_TRY(hipMemcpyAsync(m->st + mode, &s, sizeof(ModeState), hipMemcpyHostToDevice, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_get_nstats(const sacd_nmodel *m, int32_t mode, sacd_sweep_stats *out) {
+  SACD_TRY(check_nmode(m, mode));
+  if (!out) return fail(SACD_ERR_INVALID_ARG, "out is NULL");
+  SACD_TRY(enter(m->t->dev));
+  ModeState s;
+  SACD_TRY(read_nstate(m, mode, &s));
+  out->k = s.k;
+  out->lipschitz = s.L;
+  out->ti = s.ti;
+  out->flip = s.flip;
+  out->n_selected = s.nsel;
+  out->objective = s.f;
+  return SACD_OK;
+}
+
+sacd_status sacd_get_ncolumn_counts(const sacd_nmodel *m, int32_t mode, int64_t *counts) {
+  SACD_TRY(check_nmode(m, mode));
+  if (!counts) return fail(SACD_ERR_INVALID_ARG, "counts is NULL");
+  SACD_TRY(enter(m->t->dev));
+  std::vector<long long> c((size_t)m->RP);
+  HIP_TRY(hipMemcpyAsync(c.data(), m->colcnt[mode], sizeof(long long) * m->RP, hipMemcpyDeviceToHost, m->s));
+  HIP_TRY(hipStreamSynchronize(m->s));
+  for (int r = 0; r < m->R; ++r) counts[r] = (int64_t)c[(size_t)r];
+  return SACD_OK;
+}
+
+sacd_status sacd_get_ndiagnostics(const sacd_nmodel *m, int32_t mode, float *mttkrp, uint8_t *selection,
+                                  double *gram) {
+  SACD_TRY(check_nmode(m, mode));
+  SACD_TRY(enter(m->t->dev));
+  const int I = (int)m->t->dims[mode], R = m->R, RP = m->RP;
+  if (mttkrp) HIP_TRY(launch_copy_rows(m->M[mode], RP, mttkrp, R, I, R, R, m->s));
+  if (selection)
+    HIP_TRY(hipMemcpy2DAsync(selection, (size_t)R, m->selmask[mode], (size_t)RP, (size_t)R, (size_t)I,
+                             hipMemcpyDeviceToDevice, m->s));
+  if (gram) {
+    std::vector<double> G((size_t)RP * RP);
+    HIP_TRY(hipMemcpyAsync(G.data(), m->G64[mode], sizeof(double) * RP * RP, hipMemcpyDeviceToHost, m->s));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    for (int i = 0; i < R; ++i)
+      for (int j = 0; j < R; ++j) gram[i * R + j] = G[(size_t)i * RP + j];
+  }
+  HIP_TRY(hipStreamSynchronize(m->s));
+  return SACD_OK;
+}
+
+sacd_status sacd_set_ndiagnostics(sacd_nmodel *m, int32_t enable) {
+  if (!m) return fail(SACD_ERR_INVALID_ARG, "model is NULL");
+  const bool d = enable != 0;
+  if (d != m->diag) {
+    SACD_TRY(enter(m->t->dev));
+    HIP_TRY(hipStreamSynchronize(m->s));
+    drop_ngraph(m);
+    m->diag = d;
+  }
+  return SACD_OK;
+}
+
+sacd_status sacd_nmodel_bytes(const sacd_nmodel *m, int64_t *bytes) {
+  if (!m || !bytes) return fail(SACD_ERR_INVALID_ARG, "bad arguments");
+  *bytes = m->mem.bytes;
+  return SACD_OK;
+}
+
+void sacd_destroy_nmodel(sacd_nmodel *m) {
+  if (!m) return;
+  sacd_ntensor *t = m->t;
+  (void)hipSetDevice(t->dev);
+  if (m->s) (void)hipStreamSynchronize(m->s);
+  drop_ngraph(m);
+  for (hipEvent_t e : m->tev) (void)hipEventDestroy(e);
+  m->tev.clear();
+  m->mem.release_all();
+  pinned_put(m->h_pinned);
+  const bool counted = m->counted;
+  delete m;
+  if (counted && t->nmodels > 0) t->nmodels--;
+  if (t->destroy_pending && t->nmodels == 0) release_ntensor(t);
+}
+
+}  // extern "C"

@@ -193,6 +193,51 @@ hipError_t launch_col_update(int CB, const ColArgs &a, hipStream_t s);
 hipError_t launch_col_finish(const double *part, int n, const int *cnt_part, int nrb, int RP, int ncols,
                              long long *colcnt, ModeState *st, hipStream_t s);
 
+// nway.hip: the N-way form (N in [2, kMaxModes]).
+constexpr int kMaxModes = 8;
+// Key layout of one mode of an N-way tensor: field f holds the index of the
+// f-th mode of the layout's order (mode n first, then the others in
+// increasing mode order), at shift sh[f] with mask[f].
+struct NLayout {
+  int nf;                        // number of fields (modes)
+  long long dims[kMaxModes];     // mode lengths, in field order of the mode-0 layout
+  int sh[kMaxModes];
+  unsigned long long mask[kMaxModes];
+};
+struct NShifts {
+  int sh[kMaxModes];
+};
+struct NMttkrpArgs {
+  const unsigned long long *keys;
+  const float *vals;
+  const int4 *units;
+  const int *uslot;
+  int nunits;
+  int nother;                          // N - 1
+  const float *A[kMaxModes - 1];       // the other modes' factors, in increasing mode order
+  int sh[kMaxModes - 1];               // their fields in mode n's layout
+  unsigned long long mask[kMaxModes - 1];
+  float *M, *part;
+};
+struct NGrams {
+  int n;
+  const double *G[kMaxModes];
+};
+struct NFactors {
+  const float *A[kMaxModes];
+};
+hipError_t launch_make_keys_n(const int32_t *idx, const float *vals, long long nnz, const NLayout &lay,
+                              unsigned long long *keys, float *vout, int *err, hipStream_t s);
+hipError_t launch_rekey_n(const unsigned long long *k0, long long nnz, const NLayout &l0, const NShifts &to_sh,
+                          unsigned long long *kn, hipStream_t s);
+hipError_t launch_export_coo_n(const unsigned long long *keys, const float *vals, long long nnz, const NLayout &lay,
+                               int32_t *coords, float *vout, const int *ptr, int I, int64_t *ptr64, hipStream_t s);
+hipError_t launch_mttkrp_n(int RP, const NMttkrpArgs &a, hipStream_t s);
+hipError_t launch_prod_grams(const NGrams &g, int n, int RP, double *P, double *ones, hipStream_t s);
+hipError_t launch_inner_full_n(const unsigned long long *keys0, const float *vals0, long long nnz,
+                               const NLayout &lay, const NFactors &F, int RP, double *part, int nparts, double *out,
+                               unsigned *counter, hipStream_t s);
+
 // sweep.hip
 // Arguments of one job's element kernels.  The solo launchers pass them by
 // value; the job-batched launchers take device arrays of them plus a block

@@ -28,8 +28,13 @@ def _rng(seed: int) -> np.random.Generator:
 
 
 def _linear(idx: np.ndarray, dims: Sequence[int]) -> np.ndarray:
+    """Row-major linear index of each coordinate (any number of modes; the
+    product of the mode lengths must fit in int64)."""
     i = idx.astype(np.int64)
-    return (i[:, 0] * dims[1] + i[:, 1]) * dims[2] + i[:, 2]
+    lin = i[:, 0].copy()
+    for k in range(1, len(dims)):
+        lin = lin * int(dims[k]) + i[:, k]
+    return lin
 
 
 def _dedup_keep_first(idx: np.ndarray, dims) -> np.ndarray:
@@ -84,7 +89,7 @@ def _draw_distinct(rng, dims, nnz, draw_coords, max_rounds: int = 64):
         seen = np.sort(np.concatenate([seen, k]))
         need -= batch.shape[0]
         rounds += 1
-    idx = np.concatenate(parts) if parts else np.empty((0, 3), np.int32)
+    idx = np.concatenate(parts) if parts else np.empty((0, len(dims)), np.int32)
     return idx, rounds
 
 
@@ -133,6 +138,26 @@ def zipf_coords(dims, nnz: int, alpha: float, seed: int, values: str = "int1to5"
     return dims, idx, _values(rng, idx.shape[0], values)
 
 
+def nway_coords(dims, nnz: int, seed: int, alphas=None, values: str = "int1to5",
+                max_rounds: int = 64):
+    """N-way tensor: mode k's index drawn Zipf(alphas[k]) when alphas[k] is a
+    number, uniform when it is None (alphas None: all uniform); deduplicated
+    with top-up rounds to ``nnz`` distinct cells (at most ``max_rounds``)."""
+    dims = tuple(int(d) for d in dims)
+    alphas = [None] * len(dims) if alphas is None else list(alphas)
+    if len(alphas) != len(dims):
+        raise ValueError("one alpha per mode")
+    rng = _rng(seed)
+
+    def draw(n):
+        cols = [rng.integers(0, d, size=n, dtype=np.int32) if a is None else zipf_indices(rng, n, d, a)
+                for d, a in zip(dims, alphas)]
+        return np.stack(cols, axis=1)
+
+    idx, _ = _draw_distinct(rng, dims, nnz, draw, max_rounds=max_rounds)
+    return dims, idx, _values(rng, idx.shape[0], values)
+
+
 # --------------------------------------------------------------------------
 # Named workloads
 # --------------------------------------------------------------------------
@@ -162,11 +187,17 @@ UNIFORM_20M_R128 = dataclasses.replace(UNIFORM_20M_R64, name="uniform-20000x2000
                                        rank=128)
 
 
+#: user x item x tag x day 100,000 x 50,000 x 2,000 x 365: the Zipf(1.2)
+#: user x item x tag tensor with a fourth, uniform time mode; 10M cells, R = 32.
+ZIPF_UITD = Workload("zipf1.2-uitd-100000x50000x2000x365-r32", (100_000, 50_000, 2_000, 365),
+                     10_000_000, 32, 10, 1004, 42, "Zipf(1.2) on the first three modes, uniform day, values 1-5")
+
+
 def make(w: Workload, scale: float = 1.0) -> TensorCOO:
     """Draw the tensor of workload ``w``.  ``scale`` < 1 shrinks nnz (and the
     mode lengths by scale^(1/3)) for quick tests while keeping the structure."""
     if scale != 1.0:
-        f = scale ** (1.0 / 3.0)
+        f = scale ** (1.0 / len(w.dims))
         dims = tuple(max(4, int(round(d * f))) for d in w.dims)
         nnz = max(1, int(round(w.nnz * scale)))
     else:
@@ -177,6 +208,8 @@ def make(w: Workload, scale: float = 1.0) -> TensorCOO:
         return zipf_coords(dims, nnz, 1.2, w.data_seed, "int1to5")
     if w.name.startswith("uniform-20000"):
         return uniform_coords(dims, nnz, w.data_seed, "exp1")
+    if w.name.startswith("zipf1.2-uitd"):
+        return nway_coords(dims, nnz, w.data_seed, (1.2, 1.2, 1.2, None), "int1to5")
     raise ValueError(f"no generator for {w.name}")
 
 

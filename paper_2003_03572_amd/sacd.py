@@ -111,6 +111,24 @@ def lib():
             "sacd_server_result": [p, i64, i32, p],
             "sacd_server_release": [p, i64],
             "sacd_server_stats": [p, p],
+            "sacd_create_ntensor": [i32, p, i64, p, p, p, p, C.POINTER(p)],
+            "sacd_ntensor_info": [p, p, p, p, p, p],
+            "sacd_ntensor_mode_coo": [p, i32, p, p, p],
+            "sacd_init_nfactors": [p, i32, C.c_uint64, C.POINTER(p)],
+            "sacd_nsweep": [p, i32],
+            "sacd_niterate": [p, i32],
+            "sacd_niterate_timed": [p, i32, p, p],
+            "sacd_nfit": [p, p, p],
+            "sacd_nrun_until": [p, dbl, i32, p, p],
+            "sacd_get_nfactor": [p, i32, p],
+            "sacd_set_nfactor": [p, i32, p],
+            "sacd_get_nstate": [p, i32, p, p, p],
+            "sacd_set_nstate": [p, i32, p, dbl, i64],
+            "sacd_get_nstats": [p, i32, p],
+            "sacd_get_ncolumn_counts": [p, i32, p],
+            "sacd_get_ndiagnostics": [p, i32, p, p, p],
+            "sacd_set_ndiagnostics": [p, i32],
+            "sacd_nmodel_bytes": [p, p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -122,6 +140,10 @@ def lib():
         L.sacd_destroy_model.restype = None
         L.sacd_server_destroy.argtypes = [p]
         L.sacd_server_destroy.restype = None
+        L.sacd_destroy_ntensor.argtypes = [p]
+        L.sacd_destroy_ntensor.restype = None
+        L.sacd_destroy_nmodel.argtypes = [p]
+        L.sacd_destroy_nmodel.restype = None
         L.sacd_last_error.restype = C.c_char_p
         L.sacd_status_string.restype = C.c_char_p
         L.sacd_version.restype = C.c_char_p
@@ -402,6 +424,187 @@ class Model:
     def device_bytes(self) -> int:
         b = C.c_int64()
         _check(lib().sacd_model_bytes(self._h, C.byref(b)), "sacd_model_bytes")
+        return b.value
+
+    def synchronize(self):
+        self.t.stream.synchronize()
+
+
+
+class NTensor:
+    """A sparse N-way tensor resident on the GPU (sacd_create_ntensor)."""
+
+    def __init__(self, dims: Sequence[int], idx: torch.Tensor, vals: torch.Tensor,
+                 stream: Optional[torch.cuda.Stream] = None, torch_allocator: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the SaCD library runs on the GPU only")
+        self.N = len(dims)
+        self.device = idx.device if idx.is_cuda else torch.device("cuda", torch.cuda.current_device())
+        idx = idx.to(self.device, torch.int32).contiguous().view(-1, self.N)
+        vals = vals.to(self.device, torch.float32).contiguous().view(-1)
+        if idx.shape[0] != vals.shape[0]:
+            raise ValueError("idx and vals disagree on nnz")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.alloc = TorchAllocator(self.device) if torch_allocator else None
+        d = (C.c_int64 * self.N)(*[int(x) for x in dims])
+        h = C.c_void_p()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        _check(lib().sacd_create_ntensor(self.N, d, idx.shape[0], _dptr(idx), _dptr(vals),
+                                         C.byref(self.alloc.struct) if self.alloc else None,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)),
+               "sacd_create_ntensor")
+        self._h = h
+
+    @classmethod
+    def from_numpy(cls, dims, idx: np.ndarray, vals: np.ndarray, **kw) -> "NTensor":
+        dev = torch.device("cuda", torch.cuda.current_device())
+        return cls(dims, torch.from_numpy(np.ascontiguousarray(idx, np.int32)).to(dev),
+                   torch.from_numpy(np.ascontiguousarray(vals, np.float32)).to(dev), **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sacd_destroy_ntensor(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n = C.c_int32()
+        d = (C.c_int64 * 8)()
+        nnz, n2, by = C.c_int64(), C.c_double(), C.c_int64()
+        _check(lib().sacd_ntensor_info(self._h, C.byref(n), d, C.byref(nnz), C.byref(n2), C.byref(by)),
+               "sacd_ntensor_info")
+        return dict(N=n.value, dims=tuple(d[:n.value]), nnz=nnz.value, norm2=n2.value, device_bytes=by.value)
+
+    @property
+    def dims(self) -> Tuple[int, ...]:
+        return self.info()["dims"]
+
+    @property
+    def nnz(self) -> int:
+        return self.info()["nnz"]
+
+    @property
+    def norm2(self) -> float:
+        return self.info()["norm2"]
+
+    def mode_coo(self, mode: int):
+        info = self.info()
+        nnz = info["nnz"]
+        coords = torch.empty((max(nnz, 1), self.N), dtype=torch.int32, device=self.device)
+        vals = torch.empty(max(nnz, 1), dtype=torch.float32, device=self.device)
+        ptr = torch.empty(info["dims"][mode] + 1, dtype=torch.int64, device=self.device)
+        _check(lib().sacd_ntensor_mode_coo(self._h, mode, _dptr(coords), _dptr(vals), _dptr(ptr)),
+               "sacd_ntensor_mode_coo")
+        return coords[:nnz], vals[:nnz], ptr
+
+
+class NModel:
+    """SaCD model of rank R over an NTensor (sacd_init_nfactors): FP32,
+    Gauss-Seidel; an iteration sweeps modes 0, ..., N - 1."""
+
+    def __init__(self, tensor: NTensor, rank: int, seed: int):
+        self.t = tensor
+        self.R = int(rank)
+        self.N = tensor.N
+        h = C.c_void_p()
+        _check(lib().sacd_init_nfactors(tensor._h, self.R, C.c_uint64(seed), C.byref(h)), "sacd_init_nfactors")
+        self._h = h
+        self.dims = tensor.dims
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().sacd_destroy_nmodel(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sweep(self, mode: int):
+        _check(lib().sacd_nsweep(self._h, mode), "sacd_nsweep")
+
+    def iterate(self, n: int = 1):
+        _check(lib().sacd_niterate(self._h, n), "sacd_niterate")
+
+    def iterate_timed(self, n_iters: int):
+        """(MTTKRP ms, sweep ms), each an (n_iters, N) array."""
+        mt = np.zeros(n_iters * self.N, np.float32)
+        sw = np.zeros(n_iters * self.N, np.float32)
+        _check(lib().sacd_niterate_timed(self._h, int(n_iters), mt.ctypes.data_as(C.c_void_p),
+                                         sw.ctypes.data_as(C.c_void_p)), "sacd_niterate_timed")
+        return mt.reshape(n_iters, self.N), sw.reshape(n_iters, self.N)
+
+    def fit(self) -> Tuple[float, float]:
+        fit, f = C.c_double(), C.c_double()
+        _check(lib().sacd_nfit(self._h, C.byref(fit), C.byref(f)), "sacd_nfit")
+        return fit.value, f.value
+
+    def run_until(self, tol: float, max_iter: int) -> Tuple[int, float]:
+        it, fit = C.c_int32(), C.c_double()
+        _check(lib().sacd_nrun_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit)),
+               "sacd_nrun_until")
+        return it.value, fit.value
+
+    def factor(self, mode: int) -> torch.Tensor:
+        out = torch.empty((self.dims[mode], self.R), dtype=torch.float32, device=self.t.device)
+        _check(lib().sacd_get_nfactor(self._h, mode, _dptr(out)), "sacd_get_nfactor")
+        return out
+
+    def set_factor(self, mode: int, A: torch.Tensor):
+        A = A.to(self.t.device, torch.float32).contiguous()
+        if tuple(A.shape) != (self.dims[mode], self.R):
+            raise ValueError("factor shape mismatch")
+        torch.cuda.current_stream(self.t.device).synchronize()
+        _check(lib().sacd_set_nfactor(self._h, mode, _dptr(A)), "sacd_set_nfactor")
+
+    def state(self, mode: int):
+        zp = torch.empty((self.dims[mode], self.R), dtype=torch.float32, device=self.t.device)
+        ti, k = C.c_double(), C.c_int64()
+        _check(lib().sacd_get_nstate(self._h, mode, _dptr(zp), C.byref(ti), C.byref(k)), "sacd_get_nstate")
+        return zp, ti.value, k.value
+
+    def set_state(self, mode: int, zprev: torch.Tensor, ti_prev: float, k: int):
+        zp = zprev.to(self.t.device, torch.float32).contiguous()
+        if tuple(zp.shape) != (self.dims[mode], self.R):
+            raise ValueError("zprev shape mismatch")
+        torch.cuda.current_stream(self.t.device).synchronize()
+        _check(lib().sacd_set_nstate(self._h, mode, _dptr(zp), float(ti_prev), int(k)), "sacd_set_nstate")
+
+    def stats(self, mode: int) -> dict:
+        s = _Stats()
+        _check(lib().sacd_get_nstats(self._h, mode, C.byref(s)), "sacd_get_nstats")
+        return dict(k=s.k, L=s.lipschitz, ti=s.ti, flip=bool(s.flip), nsel=s.n_selected, f=s.objective)
+
+    def column_counts(self, mode: int) -> np.ndarray:
+        out = np.zeros(self.R, np.int64)
+        _check(lib().sacd_get_ncolumn_counts(self._h, mode, out.ctypes.data_as(C.c_void_p)),
+               "sacd_get_ncolumn_counts")
+        return out
+
+    def set_diagnostics(self, on: bool):
+        _check(lib().sacd_set_ndiagnostics(self._h, int(bool(on))), "sacd_set_ndiagnostics")
+
+    def diagnostics(self, mode: int):
+        I = self.dims[mode]
+        M = torch.empty((I, self.R), dtype=torch.float32, device=self.t.device)
+        sel = torch.empty((I, self.R), dtype=torch.uint8, device=self.t.device)
+        G = np.empty((self.R, self.R), np.float64)
+        _check(lib().sacd_get_ndiagnostics(self._h, mode, _dptr(M), _dptr(sel), G.ctypes.data_as(C.c_void_p)),
+               "sacd_get_ndiagnostics")
+        return M, sel.bool(), G
+
+    def device_bytes(self) -> int:
+        b = C.c_int64()
+        _check(lib().sacd_nmodel_bytes(self._h, C.byref(b)), "sacd_nmodel_bytes")
         return b.value
 
     def synchronize(self):

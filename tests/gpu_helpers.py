@@ -42,10 +42,11 @@ def to_np(t: torch.Tensor) -> np.ndarray:
     return t.detach().cpu().numpy()
 
 
-def load_oracle_state_into_gpu(gm, om, modes=(0, 1, 2)):
+def load_oracle_state_into_gpu(gm, om, modes=None):
     """Round the oracle's factors and Z^{k-1} to FP32, use them on both
-    sides, and copy the oracle's ti^{k-1} and k to the GPU model."""
-    for n in modes:
+    sides, and copy the oracle's ti^{k-1} and k to the GPU model (modes:
+    default all)."""
+    for n in (range(len(om.t.dims)) if modes is None else modes):
         A32 = om.factor(n).astype(np.float32)
         om.set_factor(n, A32.astype(np.float64))
         gm.set_factor(n, torch.from_numpy(A32).cuda())
@@ -55,18 +56,18 @@ def load_oracle_state_into_gpu(gm, om, modes=(0, 1, 2)):
         gm.set_state(n, torch.from_numpy(zp32).cuda(), ti, k)
 
 
-def load_gpu_factors_into_oracle(gm, om, modes=(0, 1, 2)):
+def load_gpu_factors_into_oracle(gm, om, modes=None):
     """The GPU's factors into the oracle; the oracle keeps its own Z^{k-1},
-    ti^{k-1} and k."""
-    for n in modes:
+    ti^{k-1} and k (modes: default all)."""
+    for n in (range(len(om.t.dims)) if modes is None else modes):
         om.set_factor(n, to_np(gm.factor(n)).astype(np.float64))
 
 
-def load_gpu_state_into_oracle(gm, om, modes=(0, 1, 2), state_modes=(0, 1, 2)):
+def load_gpu_state_into_oracle(gm, om, modes=None, state_modes=None):
     """The GPU's factors (all `modes`) and selection state (`state_modes`)
-    into the oracle."""
+    into the oracle (default: every mode)."""
     load_gpu_factors_into_oracle(gm, om, modes)
-    for n in state_modes:
+    for n in (range(len(om.t.dims)) if state_modes is None else state_modes):
         zp, ti, k = gm.state(n)
         om.set_state(n, to_np(zp).astype(np.float64), ti, k)
 
@@ -117,7 +118,13 @@ def compare_sweep(gm, om, mode, before, where=""):
     if not info["tie_global"]:
         assert st["flip"] == info["flip"], f"{where} flip differs on mode {mode}"
     tie, sel_o, kind = info["tie"], info["sel"], info["kind"]
-    diff = (sel_g != sel_o) & ~tie
+    # at a global tie of ti both branches are valid: where the GPU took the
+    # other one, its decisions are checked against the rule under its branch
+    # (the oracle's own decisions still give the rows it updated)
+    sel_ref = sel_o
+    if info["tie_global"] and st["flip"] != info["flip"]:
+        sel_ref = _rule(st["k"], info["z"], zp_o, st["flip"])
+    diff = (sel_g != sel_ref) & ~tie
     assert not diff.any(), (f"{where} selection mode {mode}: {diff.sum()} elements differ "
                             f"outside the tie band (first at {np.argwhere(diff)[:3].tolist()})")
     # every GPU decision, ties included, is the rule on the GPU's own values
@@ -132,8 +139,8 @@ def compare_sweep(gm, om, mode, before, where=""):
     # the valid outcome that matches the GPU's decisions on tie elements
     A_o = om.factor(mode)
     A_valid = A_o.copy()
-    other = sel_g != sel_o
-    changed_rows = np.nonzero(other.any(axis=1))[0]
+    other = sel_g != sel_ref
+    changed_rows = np.nonzero((sel_g != sel_o).any(axis=1))[0]
     for q in changed_rows:
         A_valid[q] = om.row_outcome(mode, int(q), sel_g[q].astype(np.uint8))
 
@@ -192,8 +199,9 @@ def compare_sweep(gm, om, mode, before, where=""):
 def sweep_both(gm, om, mode):
     """One sweep of `mode` on both sides from their current states.  At a
     global tie of the total importance (both branches valid) the oracle's
-    sweep is undone and re-run with the branch the GPU took.  Returns what
-    compare_sweep needs from before the sweep."""
+    sweep is undone and re-run with the branch the GPU took, where the oracle
+    can (the three-way one; compare_sweep handles the other case).  Returns
+    what compare_sweep needs from before the sweep."""
     A_old = om.factor(mode)
     zp_o = om.state(mode)[0]
     zp_g = to_np(gm.state(mode)[0])
@@ -201,7 +209,7 @@ def sweep_both(gm, om, mode):
     gm.sweep(mode)
     info = om.info(mode)
     st = gm.stats(mode)
-    if info["tie_global"] and st["flip"] != info["flip"]:
+    if info["tie_global"] and st["flip"] != info["flip"] and hasattr(om, "undo_sweep"):
         om.undo_sweep(mode)
         om.force_flip(int(st["flip"]))
         om.sweep(mode)
@@ -237,3 +245,14 @@ MAX_OTHER_OF_TIES = 0.30        # elements decided the other way / tie elements 
 def assert_tie_bounds(rep, where=""):
     assert rep["ties"] <= MAX_TIE_FRACTION * rep["elements"], (where, rep)
     assert rep["elements_other_decision"] <= MAX_OTHER_OF_TIES * rep["ties"] + 2, (where, rep)
+
+
+def summarize(rep):
+    """Totals and extremes of the figures of several compared sweeps."""
+    keys = ("ties", "zero_grad", "margin", "exact_zero", "elements_other_decision", "tie_rows_other_outcome")
+    out = {k: sum(r[k] for r in rep) for k in keys}
+    out.update(sweeps=len(rep), global_ties=sum(r["tie_global"] for r in rep),
+               z_over_band_max=max(r["z_over_band_max"] for r in rep),
+               sq_over_colmax=max(r["sq_over_colmax"] for r in rep),
+               colmax_bound_ok=all(r["colmax_bound_ok"] for r in rep))
+    return out

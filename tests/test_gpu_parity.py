@@ -11,7 +11,7 @@ import os
 
 from tests.gpu_helpers import (assert_tie_bounds, compare_sweep, gpu_tensor, load_gpu_factors_into_oracle,
                                load_gpu_state_into_oracle, load_oracle_state_into_gpu, step_parity,
-                               sweep_both, to_np)
+                               summarize, sweep_both, to_np)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -116,31 +116,21 @@ def _step_parity_run(sacd, oracle_mod, w, R, n_iter, scale=1.0, seed=42):
     return report
 
 
-def _summary(rep):
-    keys = ("ties", "zero_grad", "margin", "exact_zero", "elements_other_decision", "tie_rows_other_outcome")
-    out = {k: sum(r[k] for r in rep) for k in keys}
-    out.update(sweeps=len(rep), global_ties=sum(r["tie_global"] for r in rep),
-               z_over_band_max=max(r["z_over_band_max"] for r in rep),
-               sq_over_colmax=max(r["sq_over_colmax"] for r in rep),
-               colmax_bound_ok=all(r["colmax_bound_ok"] for r in rep))
-    return out
-
-
 def test_step_parity_small_uniform_20_iterations(sacd, oracle_mod):
     rep = _step_parity_run(sacd, oracle_mod, gen.SMALL_UNIFORM, 8, 20)
-    print("STEP_PARITY small-uniform-r8", json.dumps(_summary(rep)))
+    print("STEP_PARITY small-uniform-r8", json.dumps(summarize(rep)))
 
 
 @pytest.mark.parametrize("R", [32, 20])
 def test_step_parity_zipf_scaled(sacd, oracle_mod, R):
     rep = _step_parity_run(sacd, oracle_mod, gen.ZIPF_UIT, R, 3, scale=0.01)
-    print(f"STEP_PARITY zipf-0.01-r{R}", json.dumps(_summary(rep)))
+    print(f"STEP_PARITY zipf-0.01-r{R}", json.dumps(summarize(rep)))
 
 
 @pytest.mark.parametrize("R", [64, 128, 100])
 def test_step_parity_uniform_scaled(sacd, oracle_mod, R):
     rep = _step_parity_run(sacd, oracle_mod, gen.UNIFORM_20M_R64, R, 2, scale=0.004)
-    print(f"STEP_PARITY uniform-0.004-r{R}", json.dumps(_summary(rep)))
+    print(f"STEP_PARITY uniform-0.004-r{R}", json.dumps(summarize(rep)))
 
 
 def test_jacobi_flag_step_parity(sacd, oracle_mod):
@@ -215,18 +205,18 @@ def _chained_run(sacd, oracle_mod, w, R, n_iter, scale=1.0, seed=42):
 
 def test_chained_gpu_state_small_uniform(sacd, oracle_mod):
     rep = _chained_run(sacd, oracle_mod, gen.SMALL_UNIFORM, 8, 12)
-    print("CHAINED small-uniform-r8", json.dumps(_summary(rep)))
+    print("CHAINED small-uniform-r8", json.dumps(summarize(rep)))
 
 
 @pytest.mark.parametrize("R", [32, 64])
 def test_chained_gpu_state_zipf_scaled(sacd, oracle_mod, R):
     rep = _chained_run(sacd, oracle_mod, gen.ZIPF_UIT, R, 4, scale=0.01)
-    print(f"CHAINED zipf-0.01-r{R}", json.dumps(_summary(rep)))
+    print(f"CHAINED zipf-0.01-r{R}", json.dumps(summarize(rep)))
 
 
 def test_chained_gpu_state_uniform_r128_scaled(sacd, oracle_mod):
     rep = _chained_run(sacd, oracle_mod, gen.UNIFORM_20M_R128, 128, 4, scale=0.002)
-    print("CHAINED uniform-0.002-r128", json.dumps(_summary(rep)))
+    print("CHAINED uniform-0.002-r128", json.dumps(summarize(rep)))
 
 
 # ------------------------------------------------------------ trajectory --

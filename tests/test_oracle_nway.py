@@ -88,7 +88,8 @@ def test_nway_objective_is_dense_and_gauss_seidel_is_monotone(oracle_mod):
 
 
 def test_three_way_case_equals_the_three_way_oracle(oracle_mod):
-    """N = 3: the same sweep as the three-way oracle, bit for bit."""
+    """N = 3: the same sweep as the three-way oracle, bit for bit, with the
+    same tie band and the same row outcomes under other decisions."""
     dims, idx, vals = gen.make(gen.SMALL_UNIFORM)
     a = oracle_mod.Model(oracle_mod.Tensor(dims, idx, vals), 8, seed=42)
     T = oracle_mod.NTensor(dims, idx, vals)
@@ -97,6 +98,7 @@ def test_three_way_case_equals_the_three_way_oracle(oracle_mod):
         np.testing.assert_array_equal(a.factor(n), b.factor(n))
     for it in range(3):
         for n in range(3):
+            A_before = b.factor(n)
             a.sweep(n)
             b.sweep(n)
             ia, ib = a.info(n), b.info(n)
@@ -105,6 +107,19 @@ def test_three_way_case_equals_the_three_way_oracle(oracle_mod):
             np.testing.assert_array_equal(ia["sel"], ib["sel"])
             np.testing.assert_array_equal(a.factor(n), b.factor(n))
             assert ia["f"] == ib["f"] and ia["ti"] == ib["ti"]
+            assert ia["inner"] == ib["inner"] and ia["model"] == ib["model"]
+            np.testing.assert_array_equal(ia["band"], ib["band"])
+            np.testing.assert_array_equal(ia["kind"], ib["kind"])
+            assert ia["tie_global"] == ib["tie_global"] and ia["band_ti"] == ib["band_ti"]
+            # row outcomes: the own decisions give the swept row, none the old
+            # row, and flipped decisions agree between the two oracles
+            rng = np.random.default_rng(100 * it + n)
+            for q in rng.choice(dims[n], 5, replace=False):
+                own = ib["sel"][q].astype(np.uint8)
+                np.testing.assert_array_equal(b.row_outcome(n, q, own), b.factor(n)[q])
+                np.testing.assert_array_equal(b.row_outcome(n, q, np.zeros(8, np.uint8)), A_before[q])
+                alt = (rng.random(8) < 0.5).astype(np.uint8)
+                np.testing.assert_array_equal(b.row_outcome(n, q, alt), a.row_outcome(n, q, alt))
 
 
 def test_hand_worked_sweeps_with_a_fourth_unit_mode(oracle_mod):

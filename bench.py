@@ -10,12 +10,14 @@ nnz * R / (seconds per step).
 The default run prints one JSON line whose headline is the largest
 single-GPU configuration, the 2e7-entry uniform tensor at R = 128 in FP32,
 with per-mode values; its `config` also carries the Zipf user x item x tag
-tensor (1e7 entries, R = 32) and the served-vs-serial latencies to tolerance
+tensor (1e7 entries, R = 32), its 4-way extension with a day mode, and the
+served-vs-serial latencies to tolerance
 (Poisson arrivals at 50, 200 and 800 requests/s, both paths run live).
 Progress goes to stderr.
 
     python bench.py [--steps K] [--warmup W]              # headline + extras
     python bench.py --workload zipf|small|uniform64|uniform128 [--precision fp32|mixed]
+    python bench.py --workload nway        # the 4-way Zipf tensor (1e7 entries, R = 32)
     python bench.py --workload batched     # 256 uneven jobs to tolerance, batched vs serial
     python bench.py --workload serving     # Poisson arrivals, served vs serial, p50/p99
 """
@@ -294,6 +296,52 @@ def run_tensor(sacd, gen, w, prec, args, with_cpu: bool):
     return out
 
 
+def run_nway(sacd, gen, w, args):
+    """An N-way tensor (Sec. 3 for N modes): K timed outer iterations (sweeps
+    of modes 0, ..., N - 1, launch by launch with HIP events around every
+    MTTKRP launch and at the end of every sweep) and the graph replay;
+    returns the record that goes into the headline's config."""
+    import torch
+    dims, idx, vals = load_workload(gen, w, args.data_cache)
+    N = len(dims)
+    T = sacd.NTensor.from_numpy(dims, idx, vals)
+    nnz = T.nnz
+    m = sacd.NModel(T, w.rank, seed=w.init_seed)
+    m.iterate(args.warmup)
+    m.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mt_ms, sw_ms = m.iterate_timed(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fit = m.fit()[0]
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(T.stream)
+    m.iterate(args.steps)
+    e1.record(T.stream)
+    m.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    R = w.rank
+    # MTTKRP of mode n: 12 B per entry (key, value), each row of the N - 1
+    # other factors read once and M written once (4 R B per row); N R flops
+    # per entry (N - 2 products of rows, one by x, one add)
+    mt_bytes = [12.0 * nnz + 4.0 * R * (sum(dims) - dims[n]) + 4.0 * R * dims[n] for n in range(N)]
+    mt_us = [1e3 * _median([float(r[n]) for r in mt_ms]) for n in range(N)]
+    mt_time = float(mt_ms.sum()) * 1e-3
+    gbs = args.steps * sum(mt_bytes) / mt_time / 1e9
+    log(f"[bench] {w.name}: {1e3 * wall / args.steps:.3f} ms per iteration (graph {graph_ms:.3f}), MTTKRP " +
+        ", ".join(f"{u:.1f} us" for u in mt_us) + f", {gbs:.0f} GB/s algorithmic, fit {fit:.6f}")
+    return {"workload": w.name, "dims": list(dims), "nnz": nnz, "rank": R, "modes": N,
+            "value": nnz * R / (wall / args.steps), "unit": "nnz*R/s", "ms_per_step": 1e3 * wall / args.steps,
+            "graph_replay_ms_per_step": graph_ms, "fit_after": fit,
+            "per_mode": {f"mode{n}": {"sweep_ms_median": _median([float(r[n]) for r in sw_ms]),
+                                      "mttkrp_us_median": mt_us[n]} for n in range(N)},
+            "mttkrp_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": gbs / HBM_PEAK_GBS, "kernel": "k_mttkrp_n (one launch per mode)",
+                                "algorithmic_bytes_per_launch": sum(mt_bytes) / N}}
+
+
 # ------------------------------------------------------------- many jobs ----
 
 def _gen_job(spec):
@@ -500,7 +548,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="headline",
-                    choices=["headline"] + sorted(WORKLOADS) + ["batched", "serving"],
+                    choices=["headline"] + sorted(WORKLOADS) + ["nway", "batched", "serving"],
                     help="headline (default): the uniform R = 128 FP32 line with the Zipf tensor and the "
                          "served-vs-serial latencies in its config")
     ap.add_argument("--precision", default=None, choices=["fp32", "mixed"],
@@ -555,6 +603,9 @@ def main():
         if args.requests is None:
             args.requests = 2000
         return run_many(args, pool)
+    if args.workload == "nway":
+        print(json.dumps(run_nway(sacd, gen, gen.ZIPF_UITD, args)), flush=True)
+        return
     prec = sacd.PREC_MIXED_BF16 if args.precision == "mixed" else sacd.PREC_FP32
     name = "uniform128" if args.workload == "headline" else args.workload
     w = getattr(gen, WORKLOADS[name])
@@ -565,6 +616,7 @@ def main():
             "workload": z["config"]["workload"], "value": z["value"], "unit": z["unit"],
             "ms_per_step": z["ms_per_step"], "roofline": z["roofline"], "per_mode": z["config"]["per_mode"],
             "kernel_us": z["config"]["kernel_us"], "graph_replay_ms_per_step": z["config"]["graph_replay_ms_per_step"]}
+        out["config"]["nway_4mode_r32"] = run_nway(sacd, gen, gen.ZIPF_UITD, args)
         _serial(sacd, pool[:2], sacd.PREC_MIXED_BF16, 1e-4, 5)  # first launches, code objects
         per_rate, budget = run_served(sacd, gen, pool, sacd.PREC_MIXED_BF16,
                                       [float(x) for x in args.rates.split(",")], args.requests or 500,

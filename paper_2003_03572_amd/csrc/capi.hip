@@ -548,6 +548,41 @@ const char *sacd_status_string(sacd_status s) {
 
 // ------------------------------------------------------------------ tensor --
 
+// Partial slots of the units of split slices (w == -2 on entry): consecutive
+// units of one split slice inside one block of upb units form a run, whose
+// sum the MTTKRP kernel writes to one slot; the runs are numbered slice by
+// slice, and *longs gets (slice, first slot, slots, 0) per split slice.
+// Sets each such unit's w to its run's slot; returns the number of slots.
+static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *longs) {
+  std::vector<int> run_of(units.size(), -1);
+  std::vector<int> run_slice;
+  for (size_t u = 0; u < units.size(); ++u) {
+    if (units[u].w != -2) continue;
+    const bool cont = u > 0 && units[u - 1].w == -2 && units[u - 1].x == units[u].x &&
+                      (u - 1) / upb == u / upb;
+    if (cont) {
+      run_of[u] = run_of[u - 1];
+    } else {
+      run_of[u] = (int)run_slice.size();
+      run_slice.push_back(units[u].x);
+    }
+  }
+  std::vector<int> order(run_slice.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return run_slice[a] < run_slice[b]; });
+  std::vector<int> slot_of(run_slice.size());
+  longs->clear();
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int r = run_slice[order[k]];
+    slot_of[order[k]] = (int)k;
+    if (longs->empty() || longs->back().x != r) longs->push_back(make_int4(r, (int)k, 0, 0));
+    longs->back().z += 1;
+  }
+  for (size_t u = 0; u < units.size(); ++u)
+    if (units[u].w == -2) units[u].w = slot_of[run_of[u]];
+  return (int)run_slice.size();
+}
+
 // Work plan of mode m for the MTTKRP kernels: each slice cut into segments
 // of at most kSegment entries, ordered by length (longest first, stable);
 // unit u runs in block u / upb.  Segments of a split slice that sit next to
@@ -621,34 +656,8 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
     for (const auto &f : full) units.push_back(f.second);
     for (const int4 &u : rest) units.push_back(u);
   }
-  // runs: consecutive units of one split slice inside one block
-  std::vector<int> run_of(units.size(), -1);
-  std::vector<int> run_slice;
-  for (size_t u = 0; u < units.size(); ++u) {
-    if (units[u].w != -2) continue;
-    const bool cont = u > 0 && units[u - 1].w == -2 && units[u - 1].x == units[u].x &&
-                      (u - 1) / upb == u / upb;
-    if (cont) {
-      run_of[u] = run_of[u - 1];
-    } else {
-      run_of[u] = (int)run_slice.size();
-      run_slice.push_back(units[u].x);
-    }
-  }
-  // number the runs slice by slice
-  std::vector<int> order(run_slice.size());
-  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return run_slice[a] < run_slice[b]; });
-  std::vector<int> slot_of(run_slice.size());
   std::vector<int4> longs;
-  for (size_t k = 0; k < order.size(); ++k) {
-    const int r = run_slice[order[k]];
-    slot_of[order[k]] = (int)k;
-    if (longs.empty() || longs.back().x != r) longs.push_back(make_int4(r, (int)k, 0, 0));
-    longs.back().z += 1;
-  }
-  for (size_t u = 0; u < units.size(); ++u)
-    if (units[u].w == -2) units[u].w = slot_of[run_of[u]];
+  const int nslots = number_runs(units, upb, &longs);
   // one slot per unit of a split slice, numbered slice by slice in entry order
   std::vector<int> uslot(units.size(), -1);
   std::vector<int4> ulongs;
@@ -670,7 +679,7 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
   p.nnz = t->nnz;
   p.nunits = (int)units.size();
   p.nlong = (int)longs.size();
-  p.nslots = (int)run_slice.size();
+  p.nslots = nslots;
   int4 *du = nullptr, *dl = nullptr, *dul = nullptr;
   int *dus = nullptr;
   SACD_TRY(mem.get_t(units.size() + 1, &du));
@@ -2189,9 +2198,10 @@ NLayout nlayout(int N, const int64_t *dims, int n) {
 }
 
 // Work plan of mode n of an N-way tensor: slices cut into segments of at most
-// kSegment entries, longest first (stable); one partial slot per unit of a
-// split slice, numbered slice by slice in entry order.
-sacd_status build_nplan(const sacd_ntensor *t, int n, DevAlloc &mem, MttkrpPlan *out) {
+// kSegment entries, longest first (stable, so the segments of a split slice
+// stay together); the segments of a split slice that share a block of upb
+// units form a run with one partial slot (number_runs).
+sacd_status build_nplan(const sacd_ntensor *t, int n, int upb, DevAlloc &mem, MttkrpPlan *out) {
   const std::vector<int> &ptr = t->hptr[n];
   const int I = (int)t->dims[n];
   std::vector<int4> units;
@@ -2206,40 +2216,23 @@ sacd_status build_nplan(const sacd_ntensor *t, int n, DevAlloc &mem, MttkrpPlan 
       units.push_back(make_int4(r, b, std::min(kSegment, ptr[r + 1] - b), -2));
   }
   std::stable_sort(units.begin(), units.end(), [](const int4 &x, const int4 &y) { return x.z > y.z; });
-  std::vector<int> su;
-  for (size_t u = 0; u < units.size(); ++u)
-    if (units[u].w == -2) su.push_back((int)u);
-  std::stable_sort(su.begin(), su.end(), [&](int x, int y) {
-    if (units[x].x != units[y].x) return units[x].x < units[y].x;
-    return units[x].y < units[y].y;
-  });
-  std::vector<int> uslot(units.size(), -1);
-  std::vector<int4> ulongs;
-  for (size_t k = 0; k < su.size(); ++k) {
-    uslot[su[k]] = (int)k;
-    if (ulongs.empty() || ulongs.back().x != units[su[k]].x) ulongs.push_back(make_int4(units[su[k]].x, (int)k, 0, 0));
-    ulongs.back().z += 1;
-  }
+  std::vector<int4> longs;
+  const int nslots = number_runs(units, upb, &longs);
   MttkrpPlan p{};
   p.nnz = t->nnz;
   p.nunits = (int)units.size();
-  int4 *du = nullptr, *dul = nullptr;
-  int *dus = nullptr;
+  p.nlong = (int)longs.size();
+  p.nslots = nslots;
+  int4 *du = nullptr, *dl = nullptr;
   SACD_TRY(mem.get_t(units.size() + 1, &du));
-  SACD_TRY(mem.get_t(units.size() + 1, &dus));
-  SACD_TRY(mem.get_t(ulongs.size() + 1, &dul));
-  if (!units.empty()) {
+  SACD_TRY(mem.get_t(longs.size() + 1, &dl));
+  if (!units.empty())
     HIP_TRY(hipMemcpyAsync(du, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, t->stream));
-    HIP_TRY(hipMemcpyAsync(dus, uslot.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, t->stream));
-  }
-  if (!ulongs.empty())
-    HIP_TRY(hipMemcpyAsync(dul, ulongs.data(), sizeof(int4) * ulongs.size(), hipMemcpyHostToDevice, t->stream));
+  if (!longs.empty())
+    HIP_TRY(hipMemcpyAsync(dl, longs.data(), sizeof(int4) * longs.size(), hipMemcpyHostToDevice, t->stream));
   HIP_TRY(hipStreamSynchronize(t->stream));
   p.units = du;
-  p.uslot = dus;
-  p.nuslots = (int)su.size();
-  p.ulongs = dul;
-  p.nulong = (int)ulongs.size();
+  p.longs = dl;
   *out = p;
   return SACD_OK;
 }
@@ -2397,7 +2390,6 @@ sacd_status enqueue_nsweep(sacd_nmodel *m, int n, const hipEvent_t *mark = nullp
   a.keys = t->keys[n];
   a.vals = t->vals[n];
   a.units = m->plan[n].units;
-  a.uslot = m->plan[n].uslot;
   a.nunits = m->plan[n].nunits;
   a.nother = N - 1;
   for (int q = 0, f = 0; q < N; ++q) {
@@ -2413,8 +2405,8 @@ sacd_status enqueue_nsweep(sacd_nmodel *m, int n, const hipEvent_t *mark = nullp
   HIP_TRY(launch_mttkrp_n(RP, a, s));
   if (mark) HIP_TRY(hipEventRecord(mark[1], s));
   FixArgs fx{};
-  fx.longs = m->plan[n].ulongs;
-  fx.nlong = m->plan[n].nulong;
+  fx.longs = m->plan[n].longs;
+  fx.nlong = m->plan[n].nlong;
   fx.part = m->part;
   fx.M = m->M[n];
   fx.Ga = m->P;
@@ -2535,8 +2527,8 @@ sacd_status init_nmodel_impl(sacd_nmodel *m, uint64_t seed) {
   for (int n = 0; n < N; ++n) {
     const int I = (int)t->dims[n];
     maxI = std::max(maxI, I);
-    SACD_TRY(build_nplan(t, n, A, &m->plan[n]));
-    maxus = std::max(maxus, m->plan[n].nuslots);
+    SACD_TRY(build_nplan(t, n, nway_units_per_block(RP), A, &m->plan[n]));
+    maxus = std::max(maxus, m->plan[n].nslots);
     m->nparts[n] = (I + rows_per_block(RP) - 1) / rows_per_block(RP);
     const size_t IR = (size_t)I * RP;
     SACD_TRY(A.get_t(IR, &m->A[n]));

@@ -210,8 +210,7 @@ struct NShifts {
 struct NMttkrpArgs {
   const unsigned long long *keys;
   const float *vals;
-  const int4 *units;
-  const int *uslot;
+  const int4 *units;  // (slice, first entry, entries, run slot or -1)
   int nunits;
   int nother;                          // N - 1
   const float *A[kMaxModes - 1];       // the other modes' factors, in increasing mode order
@@ -233,6 +232,7 @@ hipError_t launch_rekey_n(const unsigned long long *k0, long long nnz, const NLa
 hipError_t launch_export_coo_n(const unsigned long long *keys, const float *vals, long long nnz, const NLayout &lay,
                                int32_t *coords, float *vout, const int *ptr, int I, int64_t *ptr64, hipStream_t s);
 hipError_t launch_mttkrp_n(int RP, const NMttkrpArgs &a, hipStream_t s);
+int nway_units_per_block(int RP);
 hipError_t launch_prod_grams(const NGrams &g, int n, int RP, double *P, double *ones, hipStream_t s);
 hipError_t launch_inner_full_n(const unsigned long long *keys0, const float *vals0, long long nnz,
                                const NLayout &lay, const NFactors &F, int RP, double *part, int nparts, double *out,

@@ -75,36 +75,146 @@ __global__ __launch_bounds__(kThreads) void k_export_coo_n(const unsigned long l
 }
 
 // Columns of the N-way MTTKRP: one lane group of RP / 4 lanes (four columns
-// each) per work unit of the plan (a segment of one slice), entries in order,
-// x times the product of the N - 1 other rows added per column.  A whole
-// slice is written to M; a segment of a split slice to its own unit slot,
-// which k_mttkrp_fix adds in a fixed order.
-template <int RP>
+// each) per work unit of the plan (a segment of one slice), entries in
+// order, x times the product of the NO = N - 1 other rows added per column.
+// The entries of a slice are sorted by the other indices in increasing mode
+// order, so consecutive entries often share a prefix of them (a fibre and
+// deeper): the running products of the rows of fields 0..f are kept, and an
+// entry gathers and multiplies only the rows from its first field that
+// differs from the previous entry's (the products are formed left to right
+// either way, so the sums are the same).  Entries go in batches of U: each
+// entry's key and value are loaded by one lane of the group and handed to
+// the others through the LDS crossbar (ds_bpermute); the raw entries of
+// batch k + 1 are in flight while batch k's rows are gathered and
+// multiplied.  The gathers of a batch are all in flight together, so the
+// entries in flight per SIMD are U times the waves that fit, and the U x NO
+// rows held in registers set both (measured on a 4-way tensor at R = 32:
+// U = 4 at four waves per SIMD beats U = 8 at two by 13%; staging the last
+// field's small factor in LDS gained nothing).  The key and value arrays
+// carry kKeySlack zeroed entries past their end, so these loads (at most
+// 2U - 1 past a unit) need no bounds test.  A whole slice is written to M;
+// the segments of a split slice that share a block are summed in LDS into
+// one partial slot per run, which k_mttkrp_fix adds in a fixed order.
+constexpr int kNU = 4;  // entries per batch
+
+template <int RP, int NO>
 __global__ __launch_bounds__(kThreads) void k_mttkrp_n(NMttkrpArgs a) {
-  constexpr int LPN = RP / 4, UPB = kThreads / LPN;
+  constexpr int LPN = RP / 4, UPB = kThreads / LPN, U = kNU;
+  constexpr int KPL = (U + LPN - 1) / LPN;  // raw entries loaded per lane and batch
+  constexpr int kRowShift = RP == 16 ? 6 : (RP == 32 ? 7 : (RP == 64 ? 8 : 9));
+  static_assert((1 << kRowShift) == 4 * RP, "row size");
+  static_assert(2 * U <= kKeySlack, "raw loads run up to 2U - 1 entries past the unit");
   const int ub = threadIdx.x / LPN, sub = threadIdx.x % LPN;
-  const int u = blockIdx.x * UPB + ub;
-  if (u >= a.nunits) return;
-  const int4 unit = a.units[u];  // (slice, first entry, entries, -)
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int no = a.nother;
-  for (long long p = unit.y; p < (long long)unit.y + unit.z; ++p) {
-    const unsigned long long k = a.keys[p];
-    const float x = a.vals[p];
-    f32x4 prod;
-    {
-      const unsigned long long i = (k >> a.sh[0]) & a.mask[0];
-      prod = ld4n(a.A[0] + i * RP + 4 * sub);
-    }
-    for (int f = 1; f < no; ++f) {
-      const unsigned long long i = (k >> a.sh[f]) & a.mask[f];
-      prod = prod * ld4n(a.A[f] + i * RP + 4 * sub);
-    }
-    acc = x * prod + acc;
+  const unsigned long long *__restrict__ keys = a.keys;
+  const float *__restrict__ vals = a.vals;
+  const char *Al[NO];
+  int sh[NO];
+  unsigned long long mk[NO];
+#pragma unroll
+  for (int f = 0; f < NO; ++f) {
+    Al[f] = (const char *)(a.A[f] + 4 * sub);
+    sh[f] = a.sh[f];
+    mk[f] = a.mask[f];
   }
-  const int us = a.uslot[u];
-  float *dst = us < 0 ? a.M + (long long)unit.x * RP : a.part + (long long)us * RP;
-  *(f32x4 *)(dst + 4 * sub) = acc;
+  const int gb4 = (int)((threadIdx.x & 63u) & ~(unsigned)(LPN - 1)) * 4;  // group's first lane, bytes
+  const int gid = blockIdx.x * UPB + ub;
+  const bool active = gid < a.nunits;
+  const int4 unit = active ? a.units[gid] : make_int4(0, 0, 0, -1);  // (slice, first entry, entries, -)
+  const long long p0 = unit.y;
+  const int len = unit.z;
+  unsigned long long rk[KPL];
+  float rx[KPL];
+  unsigned long long kv[U];
+  float xv[U];
+#define SACD_MN_LOAD_RAW(q)                                \
+  _Pragma("unroll") for (int k = 0; k < KPL; ++k) {        \
+    if (sub + LPN * k < U) {                               \
+      rk[k] = keys[p0 + (q) + sub + LPN * k];              \
+      rx[k] = vals[p0 + (q) + sub + LPN * k];              \
+    }                                                      \
+  }
+#define SACD_MN_SHARE_RAW()                                                                              \
+  _Pragma("unroll") for (int u = 0; u < U; ++u) {                                                        \
+    const int src = gb4 + 4 * (u % LPN);                                                                 \
+    const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)(unsigned)rk[u / LPN]);         \
+    const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(src, (int)(unsigned)(rk[u / LPN] >> 32)); \
+    kv[u] = ((unsigned long long)hi << 32) | lo;                                                         \
+    xv[u] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(rx[u / LPN])));              \
+  }
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 pre[NO];  // pre[f]: product of the rows of fields 0..f of the previous entry
+#pragma unroll
+  for (int f = 0; f < NO; ++f) pre[f] = acc;
+  unsigned long long pk = 0;  // previous entry's key
+  bool have = false;          // pre holds a previous entry's products
+  SACD_MN_LOAD_RAW(0)
+  SACD_MN_SHARE_RAW()
+  SACD_MN_LOAD_RAW(U)
+  for (int e = 0; e < len; e += U) {
+    const bool full = e + U <= len;
+    int lv[U];  // first field whose row is read (NO: none)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int l = NO;
+#pragma unroll
+      for (int f = NO - 1; f >= 0; --f)
+        if (((kv[u] ^ pk) >> sh[f]) & mk[f]) l = f;
+      if (!have) l = 0;
+      const bool ok = full || e + u < len;
+      lv[u] = ok ? l : NO;
+      if (ok) {
+        pk = kv[u];
+        have = true;
+      }
+    }
+    f32x4 row[U][NO];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int f = 0; f < NO; ++f)
+        if (f >= lv[u]) {
+          const size_t off = (size_t)((kv[u] >> sh[f]) & mk[f]) << kRowShift;
+          row[u][f] = ld4n((const float *)(Al[f] + off));
+        }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int f = 0; f < NO; ++f)
+        if (f >= lv[u]) pre[f] = f == 0 ? row[u][0] : pre[f - 1] * row[u][f];
+      if (full || e + u < len) acc = xv[u] * pre[NO - 1] + acc;
+    }
+    SACD_MN_SHARE_RAW()
+    // batch k + 2's raw entries, if it has any: the loads then end at most
+    // U - 1 entries past the unit, inside the slack
+    if (e + 2 * U < len) {
+      SACD_MN_LOAD_RAW(e + 2 * U)
+    }
+  }
+#undef SACD_MN_LOAD_RAW
+#undef SACD_MN_SHARE_RAW
+  // A whole slice goes straight to M.  Segments of split slices are first
+  // added up inside the block: consecutive units with the same run slot are
+  // summed in unit order and the run's sum is written once.
+  __shared__ __align__(16) float s_acc[UPB * RP];
+  __shared__ int s_slot[UPB];
+  if (active && unit.w < 0) *(f32x4 *)(a.M + (long long)unit.x * RP + 4 * sub) = acc;
+  else *(f32x4 *)(s_acc + ub * RP + 4 * sub) = acc;
+  if (sub == 0) s_slot[ub] = active ? unit.w : -1;
+  __syncthreads();
+  for (int c = threadIdx.x; c < RP; c += kThreads) {
+    int run = -1;
+    float sum = 0.0f;
+    for (int q = 0; q < UPB; ++q) {
+      const int w = s_slot[q];
+      if (w != run) {
+        if (run >= 0) a.part[(long long)run * RP + c] = sum;
+        run = w;
+        sum = 0.0f;
+      }
+      if (w >= 0) sum += s_acc[q * RP + c];
+    }
+    if (run >= 0) a.part[(long long)run * RP + c] = sum;
+  }
 }
 
 // P = Hadamard product of the Gram matrices of every mode but n (FP64, modes
@@ -195,18 +305,38 @@ hipError_t launch_export_coo_n(const unsigned long long *keys, const float *vals
   return hipGetLastError();
 }
 
+namespace {
+
+template <int RP>
+hipError_t launch_mttkrp_n_rp(const NMttkrpArgs &a, dim3 g, hipStream_t s) {
+  switch (a.nother) {
+    case 1: hipLaunchKernelGGL((k_mttkrp_n<RP, 1>), g, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_mttkrp_n<RP, 2>), g, dim3(kThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_mttkrp_n<RP, 3>), g, dim3(kThreads), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_mttkrp_n<RP, 4>), g, dim3(kThreads), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_mttkrp_n<RP, 5>), g, dim3(kThreads), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_mttkrp_n<RP, 6>), g, dim3(kThreads), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_mttkrp_n<RP, 7>), g, dim3(kThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int nway_units_per_block(int RP) { return kThreads / (RP / 4); }
+
 hipError_t launch_mttkrp_n(int RP, const NMttkrpArgs &a, hipStream_t s) {
   if (a.nunits == 0) return hipSuccess;
   const int upb = kThreads / (RP / 4);
   const dim3 g((a.nunits + upb - 1) / upb);
   switch (RP) {
-    case 16: hipLaunchKernelGGL(k_mttkrp_n<16>, g, dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_mttkrp_n<32>, g, dim3(kThreads), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_mttkrp_n<64>, g, dim3(kThreads), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(k_mttkrp_n<128>, g, dim3(kThreads), 0, s, a); break;
+    case 16: return launch_mttkrp_n_rp<16>(a, g, s);
+    case 32: return launch_mttkrp_n_rp<32>(a, g, s);
+    case 64: return launch_mttkrp_n_rp<64>(a, g, s);
+    case 128: return launch_mttkrp_n_rp<128>(a, g, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_prod_grams(const NGrams &g, int n, int RP, double *P, double *ones, hipStream_t s) {

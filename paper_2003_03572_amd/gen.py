@@ -204,12 +204,12 @@ def make(w: Workload, scale: float = 1.0) -> TensorCOO:
         dims, nnz = w.dims, w.nnz
     if w is SMALL_UNIFORM or w.name.startswith("small-uniform"):
         return uniform_distinct_linear(dims, nnz, w.data_seed, "int1to5")
-    if w.name.startswith("zipf1.2"):
+    if w.name.startswith("zipf1.2-uitd"):
+        return nway_coords(dims, nnz, w.data_seed, (1.2, 1.2, 1.2, None), "int1to5")
+    if w.name.startswith("zipf1.2-uit-"):
         return zipf_coords(dims, nnz, 1.2, w.data_seed, "int1to5")
     if w.name.startswith("uniform-20000"):
         return uniform_coords(dims, nnz, w.data_seed, "exp1")
-    if w.name.startswith("zipf1.2-uitd"):
-        return nway_coords(dims, nnz, w.data_seed, (1.2, 1.2, 1.2, None), "int1to5")
     raise ValueError(f"no generator for {w.name}")
 
 

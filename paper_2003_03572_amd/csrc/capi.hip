@@ -190,6 +190,12 @@ struct sacd_model {
   int nparts[3] = {0, 0, 0};
   MttkrpPlan plan[3];
   int lds_cols[3] = {0, 0, 0};  // MTTKRP form per mode: A_b staged in LDS slabs of this many columns (0: plain)
+  // tiled MTTKRP form of a mode (see tiled_mode): the mode's entries in
+  // (i_n, i_b tile, i_a, i_b) order, and the block table of the LDS kernel
+  unsigned long long *tkeys[3] = {};
+  float *tvals[3] = {};
+  int4 *btab[3] = {};
+  int nbt[3] = {0, 0, 0};
   // column-at-a-time form: cb columns of M at a time (0: the row form, M held whole)
   int cb = 0;
   float *Mb = nullptr, *upart = nullptr;
@@ -234,8 +240,8 @@ MttkrpArgs mttkrp_args(const sacd_model *m, int n) {
   int a, b;
   other_modes(n, &a, &b);
   MttkrpArgs x;
-  x.keys = t->keys[n];
-  x.vals = t->vals[n];
+  x.keys = m->tkeys[n] ? m->tkeys[n] : t->keys[n];
+  x.vals = m->tvals[n] ? m->tvals[n] : t->vals[n];
   x.units = m->plan[n].units;
   x.nunits = m->plan[n].nunits;
   x.lay = t->lay[n];
@@ -319,14 +325,16 @@ GramArgs gram_args(const sacd_model *m, int n, bool with_f) {
 
 bool is_bf16(const sacd_model *m) { return m->prec == SACD_PREC_MIXED_BF16; }
 
-// The MTTKRP of mode n: the LDS-staged form when A_b has few enough rows,
-// else the plain one (both give the same M bit for bit).
+// The MTTKRP of mode n: the LDS-staged form when A_b has few enough rows
+// (the same M as the plain form, bit for bit), the tiled form when the mode
+// has a tiled copy, else the plain form.
 hipError_t launch_mode_mttkrp(const sacd_model *m, int n, hipStream_t s) {
-  if (m->lds_cols[n] > 0) {
-    int a, b;
-    other_modes(n, &a, &b);
-    return launch_mttkrp_lds(m->RP, m->lds_cols[n], mttkrp_args(m, n), (int)m->t->dims[b], s);
-  }
+  int a, b;
+  other_modes(n, &a, &b);
+  if (m->btab[n])
+    return launch_mttkrp_lds(m->RP, 64, mttkrp_args(m, n), (int)m->t->dims[b], m->btab[n], m->nbt[n], s);
+  if (m->lds_cols[n] > 0)
+    return launch_mttkrp_lds(m->RP, m->lds_cols[n], mttkrp_args(m, n), (int)m->t->dims[b], nullptr, 0, s);
   return launch_mttkrp(m->RP, mttkrp_args(m, n), s);
 }
 
@@ -549,17 +557,19 @@ const char *sacd_status_string(sacd_status s) {
 // ------------------------------------------------------------------ tensor --
 
 // Partial slots of the units of split slices (w == -2 on entry): consecutive
-// units of one split slice inside one block of upb units form a run, whose
+// units of one split slice inside one block (of upb units, or as block_of
+// gives) form a run, whose
 // sum the MTTKRP kernel writes to one slot; the runs are numbered slice by
 // slice, and *longs gets (slice, first slot, slots, 0) per split slice.
 // Sets each such unit's w to its run's slot; returns the number of slots.
-static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *longs) {
+static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *longs,
+                       const std::vector<int> *block_of = nullptr) {
   std::vector<int> run_of(units.size(), -1);
   std::vector<int> run_slice;
+  auto blk = [&](size_t u) { return block_of ? (size_t)(*block_of)[u] : u / (size_t)upb; };
   for (size_t u = 0; u < units.size(); ++u) {
     if (units[u].w != -2) continue;
-    const bool cont = u > 0 && units[u - 1].w == -2 && units[u - 1].x == units[u].x &&
-                      (u - 1) / upb == u / upb;
+    const bool cont = u > 0 && units[u - 1].w == -2 && units[u - 1].x == units[u].x && blk(u - 1) == blk(u);
     if (cont) {
       run_of[u] = run_of[u - 1];
     } else {
@@ -909,6 +919,138 @@ void sacd_destroy_tensor(sacd_tensor *t) {
 
 // ------------------------------------------------------------------- model --
 
+// The tiled MTTKRP form applies to mode n of a row-form model at RP >= 64
+// when A_b (the per-entry table) is too large for the LDS kernel's whole
+// table and the tensor has at least kTileMinEntries entries (smaller ones
+// keep the plain form: the copy and its sort would not pay).  The bits of
+// the tile field must fit the key.
+constexpr long long kTileMinEntries = 1ll << 20;
+
+static int tile_bits(long long Ib) { return bits_for((Ib + kTileRows - 1) / kTileRows); }
+
+static bool tiled_mode(const int64_t dims[3], long long nnz, int RP, int cb, int n) {
+  int a, b;
+  other_modes(n, &a, &b);
+  if (cb != 0 || RP < 64 || nnz < kTileMinEntries || mttkrp_lds_cols(RP, dims[b]) != 0) return false;
+  const int tb = tile_bits(dims[b]);
+  if (bits_for(dims[0]) + bits_for(dims[1]) + bits_for(dims[2]) + tb > 64) return false;
+  return ((long long)dims[n] << tb) < 2147483647LL;
+}
+
+// Tiled copy of mode n's entries and its plan: keys in (i_n, i_b tile, i_a,
+// i_b) order (a stable sort of the mode's order on (i_n, tile)); units are
+// segments of at most kSegment entries of one (slice, tile) run, grouped by
+// tile, tile by tile, slice by slice; a block of the LDS kernel takes up to
+// its units-per-block of one tile.  A slice with more than one unit is split
+// (its units' sums meet in the fix-up's slots).
+static sacd_status build_tiled(sacd_model *m, int n, MttkrpPlan *out) {
+  sacd_tensor *t = m->t;
+  const hipStream_t s = m->s;
+  const long long u = t->nnz;
+  int a, b;
+  other_modes(n, &a, &b);
+  const int I = (int)t->dims[n];
+  const long long Ib = t->dims[b];
+  const int ntiles = (int)((Ib + kTileRows - 1) / kTileRows);
+  const int tb = tile_bits(Ib);
+  const int tsh = bits_for(kTileRows);
+  const KeyLayout &lay = t->lay[n];
+  const int Isup = I << tb;  // (slice, tile) pairs
+  DevAlloc tmp;
+  tmp.alloc = m->mem.alloc;
+  tmp.custom = m->mem.custom;
+  sacd_status rs = SACD_OK;
+#define TL_TRY(expr)         \
+  do {                       \
+    rs = (expr);             \
+    if (rs != SACD_OK) {     \
+      tmp.release_all();     \
+      return rs;             \
+    }                        \
+  } while (0)
+#define TL_HIP(expr)                                                                \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess) {                                                         \
+      tmp.release_all();                                                            \
+      return fail(SACD_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e));  \
+    }                                                                               \
+  } while (0)
+  unsigned long long *k0 = nullptr, *k1 = nullptr;
+  float *v0 = nullptr, *v1 = nullptr;
+  int *ptr = nullptr;
+  void *temp = nullptr;
+  const size_t tbytes = std::max(radix_sort_temp_bytes(u), build_ptr_temp_bytes(u, Isup));
+  TL_TRY(tmp.get_t((size_t)u, &k0));
+  TL_TRY(tmp.get_t((size_t)u, &k1));
+  TL_TRY(tmp.get_t((size_t)u, &v0));
+  TL_TRY(tmp.get_t((size_t)u, &v1));
+  TL_TRY(tmp.get_t((size_t)Isup + 1, &ptr));
+  TL_TRY(tmp.get(tbytes, &temp));
+  TL_HIP(launch_tile_keys(t->keys[n], u, lay, tsh, tb, k0, s));
+  TL_HIP(hipMemcpyAsync(v0, t->vals[n], sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+  bool alt = false;
+  TL_HIP(radix_sort_pairs(k0, v0, k1, v1, u, lay.sh_n, lay.sh_n + tb + bits_for(I), temp, s, &alt));
+  TL_TRY(m->mem.get_t((size_t)u + kKeySlack, &m->tkeys[n]));
+  TL_TRY(m->mem.get_t((size_t)u + kKeySlack, &m->tvals[n]));
+  TL_HIP(hipMemcpyAsync(m->tkeys[n], alt ? k1 : k0, sizeof(unsigned long long) * u, hipMemcpyDeviceToDevice, s));
+  TL_HIP(hipMemcpyAsync(m->tvals[n], alt ? v1 : v0, sizeof(float) * u, hipMemcpyDeviceToDevice, s));
+  TL_HIP(hipMemsetAsync(m->tkeys[n] + u, 0, sizeof(unsigned long long) * kKeySlack, s));
+  TL_HIP(hipMemsetAsync(m->tvals[n] + u, 0, sizeof(float) * kKeySlack, s));
+  // (slice, tile) run offsets: the key >> sh_n is slice * 2^tb + tile
+  TL_HIP(build_ptr(m->tkeys[n], u, lay.sh_n, Isup, ptr, temp, s));
+  std::vector<int> hp((size_t)Isup + 1);
+  TL_HIP(hipMemcpyAsync(hp.data(), ptr, sizeof(int) * ((size_t)Isup + 1), hipMemcpyDeviceToHost, s));
+  TL_HIP(hipStreamSynchronize(s));
+  tmp.release_all();
+#undef TL_TRY
+#undef TL_HIP
+  const int upb = mttkrp_lds_units_per_block(64);
+  std::vector<int4> units, blocks;
+  std::vector<int> block_of, units_of_slice((size_t)I, 0);
+  for (int tl = 0; tl < ntiles; ++tl) {
+    const int first = (int)units.size();
+    for (int r = 0; r < I; ++r) {
+      const int beg = hp[((size_t)r << tb) + tl], end = hp[((size_t)r << tb) + tl + 1];
+      for (int q = beg; q < end; q += kSegment) {
+        units.push_back(make_int4(r, q, std::min(kSegment, end - q), 0));
+        units_of_slice[r] += 1;
+      }
+    }
+    const int b0 = tl * kTileRows, rows = (int)std::min<long long>(kTileRows, Ib - b0);
+    for (int u0 = first; u0 < (int)units.size(); u0 += upb) {
+      const int nu = std::min(upb, (int)units.size() - u0);
+      for (int k = 0; k < nu; ++k) block_of.push_back((int)blocks.size());
+      blocks.push_back(make_int4(u0, nu, b0, rows));
+    }
+  }
+  for (int4 &x : units) x.w = units_of_slice[x.x] > 1 ? -2 : -1;
+  std::vector<int4> longs;
+  const int nslots = number_runs(units, upb, &longs, &block_of);
+  MttkrpPlan p{};
+  p.nnz = u;
+  p.nunits = (int)units.size();
+  p.nlong = (int)longs.size();
+  p.nslots = nslots;
+  int4 *du = nullptr, *dl = nullptr, *db = nullptr;
+  SACD_TRY(m->mem.get_t(units.size() + 1, &du));
+  SACD_TRY(m->mem.get_t(longs.size() + 1, &dl));
+  SACD_TRY(m->mem.get_t(blocks.size() + 1, &db));
+  if (!units.empty())
+    HIP_TRY(hipMemcpyAsync(du, units.data(), sizeof(int4) * units.size(), hipMemcpyHostToDevice, s));
+  if (!longs.empty())
+    HIP_TRY(hipMemcpyAsync(dl, longs.data(), sizeof(int4) * longs.size(), hipMemcpyHostToDevice, s));
+  if (!blocks.empty())
+    HIP_TRY(hipMemcpyAsync(db, blocks.data(), sizeof(int4) * blocks.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  p.units = du;
+  p.longs = dl;
+  *out = p;
+  m->btab[n] = db;
+  m->nbt[n] = (int)blocks.size();
+  return SACD_OK;
+}
+
 static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   sacd_tensor *t = m->t;
   const int RP = m->RP;
@@ -918,8 +1060,10 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   for (int n = 0; n < 3; ++n) {
     const int I = (int)t->dims[n];
     if (I > maxI) maxI = I;
-    SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n]));
-    {
+    if (tiled_mode(t->dims, t->nnz, RP, m->cb, n)) {
+      SACD_TRY(build_tiled(m, n, &m->plan[n]));
+    } else {
+      SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n]));
       int a, b;
       other_modes(n, &a, &b);
       m->lds_cols[n] = mttkrp_lds_cols(RP, t->dims[b]);
@@ -1457,8 +1601,25 @@ void job_bytes(const int64_t dims[3], int64_t nnz, int R, bool mixed, int64_t *r
   int64_t tb = (int64_t)radix_sort_temp_bytes(nnz);
   tb = std::max(tb, (int64_t)dedup_temp_bytes(nnz));
   for (int n = 0; n < 3; ++n) tb = std::max(tb, (int64_t)build_ptr_temp_bytes(nnz, (int)dims[n]));
-  *resident = ten + mod + slack;
-  *transient = 2 * al256(8 * nnz) + 2 * al256(4 * nnz) + al256(tb) + al256(16 * maxunits) + slack;
+  // tiled MTTKRP copies (modes in the tiled form): keys, values, units, slots
+  // and block table resident; the sort buffers and (slice, tile) offsets
+  // transient, while the model is set up (after the ingest buffers are gone)
+  int64_t tiled_res = 0, tiled_tr = 0;
+  for (int n = 0; n < 3; ++n) {
+    if (!tiled_mode(dims, nnz, RP, 0, n)) continue;
+    int a, b;
+    other_modes(n, &a, &b);
+    const int tbits = tile_bits(dims[b]);
+    const int64_t runs = std::min<int64_t>(nnz, dims[n] << tbits);
+    const int64_t units = nnz / kSegment + runs + 2;
+    tiled_res += al256(8 * (nnz + kKeySlack)) + al256(4 * (nnz + kKeySlack)) + al256(16 * (units + 1)) +
+                 al256(16 * (dims[n] + 2)) + al256(16 * (units + 1)) + al256(4 * units * RP);
+    tiled_tr = std::max(tiled_tr, 2 * al256(8 * nnz) + 2 * al256(4 * nnz) + al256(4 * ((dims[n] << tbits) + 1)) +
+                                      al256((int64_t)std::max(radix_sort_temp_bytes(nnz),
+                                                              build_ptr_temp_bytes(nnz, (int)(dims[n] << tbits)))));
+  }
+  *resident = ten + mod + tiled_res + slack;
+  *transient = std::max(2 * al256(8 * nnz) + 2 * al256(4 * nnz) + al256(tb) + al256(16 * maxunits), tiled_tr) + slack;
 }
 
 // Device memory of a server: one block of the budget's size, handed out in
@@ -1677,7 +1838,8 @@ sacd_status rebuild_tables(sacd_server *S) {
       for (int i : g.jobs) {
         const sacd_model *m = S->active[i].m;
         const int I = (int)m->t->dims[n];
-        g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
+        // a mode in the tiled form runs its own MTTKRP launch (below)
+        if (!m->btab[n]) g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
         g.nb_fx[n] += fix_blocks(m->plan[n].nlong);
         g.nb_im[n] += importance_blocks(g.RP, I);
         g.nb_up[n] += update_blocks(g.RP, I);
@@ -1721,7 +1883,7 @@ sacd_status rebuild_tables(sacd_server *S) {
       const sacd_model *m = S->active[g.jobs[k]].m;
       const int I = (int)m->t->dims[n];
       int nb = 0;
-      if (which == 0) nb = mttkrp_blocks(g.RP, m->plan[n].nunits);
+      if (which == 0) nb = m->btab[n] ? 0 : mttkrp_blocks(g.RP, m->plan[n].nunits);
       else if (which == 1) nb = fix_blocks(m->plan[n].nlong);
       else if (which == 2) nb = importance_blocks(g.RP, I);
       else if (which == 3) nb = gram_final_blocks(g.RP);
@@ -1788,6 +1950,10 @@ sacd_status enqueue_batched_iteration(sacd_server *S) {
     HIP_TRY(hipStreamWaitEvent(s, S->ev_fork, 0));
     for (int n = 0; n < 3; ++n) {
       HIP_TRY(launch_mttkrp_b(g.RP, g.mt[n], g.bm_mt[n], g.nb_mt[n], s));
+      for (int i : g.jobs) {
+        const sacd_model *m = S->active[i].m;
+        if (m->btab[n]) HIP_TRY(launch_mode_mttkrp(m, n, s));  // the tiled form, as the job alone runs it
+      }
       HIP_TRY(launch_mttkrp_fix_b(g.RP, g.fx[n], g.bm_fx[n], g.nb_fx[n], s));
       HIP_TRY(launch_importance_b(g.RP, bf, g.big, g.im[n], g.bm_im[n], g.nb_im[n], s));
       HIP_TRY(launch_select_update_b(g.RP, bf, g.big, g.up[n], g.bm_up[n], g.nb_up[n], s));

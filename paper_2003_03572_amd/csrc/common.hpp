@@ -105,6 +105,11 @@ hipError_t launch_rekey(const unsigned long long *keys0, long long n, KeyLayout 
                         KeyLayout layn, unsigned long long *keysn, hipStream_t s);
 hipError_t build_ptr(const unsigned long long *keys, long long n, int sh_n, int I, int *ptr,
                      void *temp, hipStream_t s);
+// Tiled order of mode n's keys (the MTTKRP's tiled form): (i_n, i_b >> tsh,
+// i_a, i_b) with a tile field of tb bits; sorting on bits [sh_n, sh_n + tb +
+// bits(i_n)) of the stable mode-n order gives that order.
+hipError_t launch_tile_keys(const unsigned long long *keys, long long n, KeyLayout lay, int tsh, int tb,
+                            unsigned long long *out, hipStream_t s);
 size_t build_ptr_temp_bytes(long long n, int I);
 hipError_t launch_gather_keys(const unsigned long long *keys, const int *pos, int n,
                               unsigned long long *out, hipStream_t s);
@@ -160,8 +165,14 @@ struct FixArgs {
 hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s);
 // LDS-staged form (same M, bit for bit): CS columns of A_b (Ib rows) per slab;
 // mttkrp_lds_cols gives CS for a table of Ib rows, or 0 when it does not apply.
+// Tiled form (btab not null, nbt blocks): each block stages kTileRows rows of
+// A_b, btab[q] = (first unit, units, first row, rows) over a plan whose
+// entries are ordered by (i_n, i_b / kTileRows, i_a, i_b).
+constexpr int kTileRows = 512;  // 64 columns x 512 rows x 4 B = the 128 KB LDS table
 int mttkrp_lds_cols(int RP, long long Ib);
-hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, hipStream_t s);
+int mttkrp_lds_units_per_block(int CS);
+hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, const int4 *btab, int nbt,
+                             hipStream_t s);
 hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);
 hipError_t launch_mttkrp_fix(int RP, const FixArgs &a, hipStream_t s);
 hipError_t launch_mttkrp_fix_b(int RP, const FixArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s);

@@ -237,6 +237,20 @@ __global__ __launch_bounds__(kThreads) void k_rekey(const unsigned long long *__
   }
 }
 
+// Keys of mode n re-encoded for the tiled MTTKRP form: the tile i_b >> tsh
+// inserted between i_n and i_a, (i_n, tile, i_a, i_b), tile field tb bits wide.
+__global__ __launch_bounds__(kThreads) void k_tile_keys(const unsigned long long *__restrict__ keys, long long n,
+                                                        KeyLayout lay, int tsh, int tb,
+                                                        unsigned long long *__restrict__ out) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const unsigned long long low = lay.sh_n >= 64 ? ~0ull : ((1ull << lay.sh_n) - 1ull);
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    const unsigned long long k = keys[p];
+    const unsigned long long in = k >> lay.sh_n, ib = k & lay.mask_b;
+    out[p] = ((((in << tb) | (ib >> tsh)) << lay.sh_n)) | (k & low);
+  }
+}
+
 // ---------------------------------------------------------------- ptr ----
 
 // Slice pointers from sorted keys: position p is the start of every row in
@@ -379,6 +393,13 @@ hipError_t launch_rekey(const unsigned long long *keys0, long long n, KeyLayout 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rekey, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, keys0, n, lay0,
                      mode, layn, keysn);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_keys(const unsigned long long *keys, long long n, KeyLayout lay, int tsh, int tb,
+                            unsigned long long *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_keys, dim3(grid_for(n, kThreads * 4)), dim3(kThreads), 0, s, keys, n, lay, tsh, tb, out);
   return hipGetLastError();
 }
 

@@ -265,12 +265,21 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp(MttkrpArgs solo, const Mttk
 // order, so M is bit for bit that of k_mttkrp.  The S slab blocks of a unit
 // block are numbered so that they go to one XCD one after the other, and the
 // entry stream they all read is fetched from HBM about once.
+//
+// Tiled form (btab not null): for a mode whose A_b is too large for LDS, the
+// model keeps its own copy of the mode's entries ordered by (i_n, i_b tile,
+// i_a, i_b), tiles of kTileRows rows of A_b, and a block table: block q runs
+// units [u0, u0 + nu) of the plan, all inside one tile, with rows
+// [b0, b0 + rows) of A_b staged (btab[q] = (u0, nu, b0, rows)).  The entries
+// a block reads then gather only their A_a rows through the vector memory
+// path, and the A_b rows of a tile are read from HBM about once per slab.
 constexpr int kLdsThreads = 1024;
 constexpr int kLdsU = 6;  // entries per step: 1024 threads leave 128 VGPRs per lane (measured: 4, 6, 8 at 512 to 1024 threads)
 constexpr long long kLdsTableBytes = 128 * 1024;  // the A_b slab; the run sums add 16 KB
 
 template <int RP, int CS>
-__global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int Ib, int nub) {
+__global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int Ib, int nub,
+                                                            const int4 *__restrict__ btab) {
   constexpr int S = RP / CS, LPN = CS / 4, UPB = kLdsThreads / LPN, U = kLdsU;
   extern __shared__ __align__(16) float smem[];  // A_b slab (Ib x CS), then UPB x CS run sums
   __shared__ int s_slot[UPB];
@@ -285,16 +294,25 @@ __global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int
   const float *__restrict__ Ab = args.Ab;
   float *__restrict__ M = args.M;
   float *__restrict__ part = args.part;
+  // units of this block and the rows of A_b it stages
+  int u0 = ublk * UPB, nu = UPB, b0 = 0, rows = Ib;
+  if (btab) {
+    const int4 bt = btab[ublk];
+    u0 = bt.x;
+    nu = bt.y;
+    b0 = bt.z;
+    rows = bt.w;
+  }
   float *sB = smem;
-  float *s_acc = smem + (size_t)Ib * CS;
-  for (int i = threadIdx.x; i < Ib * (CS / 4); i += kLdsThreads) {
+  float *s_acc = smem + (size_t)(btab ? kTileRows : Ib) * CS;
+  for (int i = threadIdx.x; i < rows * (CS / 4); i += kLdsThreads) {
     const int r = i / (CS / 4), q = i % (CS / 4);
-    st4(sB + (size_t)r * CS + 4 * q, ld4(Ab + (long long)r * RP + c0 + 4 * q));
+    st4(sB + (size_t)r * CS + 4 * q, ld4(Ab + (long long)(b0 + r) * RP + c0 + 4 * q));
   }
   __syncthreads();
   const int ub = threadIdx.x / LPN;
-  const int gid = ublk * UPB + ub;
-  const bool active = gid < args.nunits;
+  const int gid = u0 + ub;
+  const bool active = ub < nu && gid < args.nunits;
   const int sub = threadIdx.x % LPN;
   const int4 unit = active ? args.units[gid] : make_int4(0, 0, 0, -1);
   const long long p0 = unit.y;
@@ -304,6 +322,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int
   const unsigned mb = (unsigned)lay.mask_b, ma = (unsigned)lay.mask_a, sha = (unsigned)lay.sh_a;
   const char *__restrict__ Aa_l = (const char *)(Aa + c0 + 4 * sub);
   const float *sB_l = sB + 4 * sub;
+  const unsigned ub0 = (unsigned)b0;  // row i_b sits at i_b - b0 of the staged rows
   constexpr int kRowShift = RP == 16 ? 6 : (RP == 32 ? 7 : (RP == 64 ? 8 : 9));
   static_assert((1 << kRowShift) == 4 * RP, "row size");
   unsigned fa = ~0u;
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       if (nf[u]) av[u] = ld4((const float *)(Aa_l + ((size_t)ia[u] << kRowShift)));
-      bv[u] = *(const f32x4 *)(sB_l + (size_t)ib[u] * CS);
+      bv[u] = *(const f32x4 *)(sB_l + (size_t)(ib[u] - ub0) * CS);
       xc[u] = xv[u];
     }
 #pragma unroll
@@ -373,7 +392,7 @@ __global__ __launch_bounds__(kLdsThreads) void k_mttkrp_lds(MttkrpArgs args, int
       const bool ok = e + u < len;
       nf[u] = ok && ia[u] != fa;
       if (ok) fa = ia[u];
-      if (ok) bv[u] = *(const f32x4 *)(sB_l + (size_t)ib[u] * CS);
+      if (ok) bv[u] = *(const f32x4 *)(sB_l + (size_t)(ib[u] - ub0) * CS);
       if (nf[u]) av[u] = ld4((const float *)(Aa_l + ((size_t)ia[u] << kRowShift)));
     }
 #pragma unroll
@@ -576,32 +595,36 @@ int mttkrp_lds_cols(int RP, long long Ib) {
 }
 
 template <int RP, int CS>
-static hipError_t launch_lds(const MttkrpArgs &a, int Ib, hipStream_t s) {
+static hipError_t launch_lds(const MttkrpArgs &a, int Ib, const int4 *btab, int nbt, hipStream_t s) {
   constexpr int UPB = kLdsThreads / (CS / 4);
   static_assert(UPB % (kThreads / MCfg<RP>::LPN) == 0, "a block covers whole blocks of the plain kernel");
-  const int nub = (a.nunits + UPB - 1) / UPB;
+  const int nub = btab ? nbt : (a.nunits + UPB - 1) / UPB;
   if (nub == 0) return hipSuccess;
   const int S = RP / CS;
   const int nb = 8 * S * ((nub + 7) / 8);
-  const size_t shm = ((size_t)Ib * CS + (size_t)UPB * CS) * sizeof(float);
-  if ((long long)Ib * CS * 4 > kLdsTableBytes) return hipErrorInvalidValue;
+  const long long rows = btab ? kTileRows : Ib;
+  const size_t shm = ((size_t)rows * CS + (size_t)UPB * CS) * sizeof(float);
+  if (rows * CS * 4 > kLdsTableBytes) return hipErrorInvalidValue;
   // more dynamic LDS than the default limit: allowed once per kernel
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void *>(&k_mttkrp_lds<RP, CS>), hipFuncAttributeMaxDynamicSharedMemorySize,
       (int)(kLdsTableBytes + (long long)UPB * CS * sizeof(float)));
   if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_mttkrp_lds<RP, CS>), dim3(nb), dim3(kLdsThreads), shm, s, a, Ib, nub);
+  hipLaunchKernelGGL((k_mttkrp_lds<RP, CS>), dim3(nb), dim3(kLdsThreads), shm, s, a, Ib, nub, btab);
   return hipGetLastError();
 }
 
-hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, hipStream_t s) {
+hipError_t launch_mttkrp_lds(int RP, int CS, const MttkrpArgs &a, int Ib, const int4 *btab, int nbt,
+                             hipStream_t s) {
   if (CS != 64) return hipErrorInvalidValue;
   switch (RP) {
-    case 64: return launch_lds<64, 64>(a, Ib, s);
-    case 128: return launch_lds<128, 64>(a, Ib, s);
+    case 64: return launch_lds<64, 64>(a, Ib, btab, nbt, s);
+    case 128: return launch_lds<128, 64>(a, Ib, btab, nbt, s);
     default: return hipErrorInvalidValue;
   }
 }
+
+int mttkrp_lds_units_per_block(int CS) { return kLdsThreads / (CS / 4); }
 
 int mttkrp_blocks(int RP, int nunits) {
   const int upb = mttkrp_units_per_block(RP);

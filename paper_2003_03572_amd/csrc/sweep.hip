@@ -44,13 +44,21 @@ constexpr int upd_rows() {
 // only sets how many waves work on a block's chain of dependent steps, and
 // no result depends on it (tiles are summed per wave in a fixed order, see
 // tile_sums_total).  A job alone takes 1024 threads at RP <= 32 and 512
-// above (measured fastest: the chain, not bandwidth, bounds these passes);
+// above, except the update pass at RP = 128 (below) (measured fastest: the
+// chain, not bandwidth, bounds these passes);
 // the job-batched forms take 256, which suits many small jobs resident at
 // once, or, at RP <= 32, 1024 when the jobs of a launch have few row blocks
 // in all (the caller's choice, `big`).
 template <int RP>
 constexpr int elem_threads() {
   return RP <= 32 ? 1024 : 512;
+}
+// The update pass of a job alone at RP = 128 takes 1024 threads (16 lanes
+// per row): measured 94 against 115 us per mode at I = 20000 (one 132 KB
+// block per compute unit either way); at RP = 64, 512 stays faster.
+template <int RP>
+constexpr int upd_threads() {
+  return RP == 128 ? 1024 : elem_threads<RP>();
 }
 
 template <int RP, int RB_, int NTH_ = kThreads>
@@ -1054,12 +1062,11 @@ struct ImpBL {
 
 template <int RP, int UPD, bool DIAG>
 hipError_t upd_launch(bool bf, const UpdArgs &a, int nb, hipStream_t s) {
+  constexpr int T = upd_threads<RP>();
   if (bf)
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
-                       nullptr, 0);
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, true, false, T>), dim3(nb), dim3(T), 0, s, a, nullptr, nullptr, 0);
   else
-    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false, elem_threads<RP>()>), dim3(nb), dim3(elem_threads<RP>()), 0, s, a, nullptr,
-                       nullptr, 0);
+    hipLaunchKernelGGL((k_select_update<RP, UPD, DIAG, false, false, T>), dim3(nb), dim3(T), 0, s, a, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 

@@ -522,3 +522,27 @@ def test_step_parity_full_size_uniform_r128(sacd, oracle_mod):
         r = step_parity(gm, om, n, where=f"full size R=128 mode {n}")
         print(f"FULL_SIZE uniform-r128 mode {n}", json.dumps(r), flush=True)
         assert_tie_bounds(r, f"full size uniform mode {n}")
+
+
+@pytest.mark.parametrize("R", [48, 100])
+def test_tiled_mttkrp_step_parity(sacd, oracle_mod, R):
+    """Mode 2 of this tensor runs the MTTKRP in the tiled form (its A_1 of
+    3000 rows is staged in LDS 512 rows at a time, over a copy of the entries
+    ordered by row tile); modes 0 and 1 stage all of A_2 (200 rows).  Step
+    parity of every mode against the oracle, two iterations, from the GPU's
+    own carried state."""
+    dims, idx, vals = gen.uniform_coords((3000, 3000, 200), 1_100_000, 4242, "int1to5")
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    T_o = oracle_mod.Tensor(dims, idx, vals)
+    gm = sacd.Model(T_g, R, seed=3)
+    gm.set_diagnostics(True)
+    om = oracle_mod.Model(T_o, R, seed=3)
+    rep = []
+    for it in range(2):
+        for n in range(3):
+            load_gpu_factors_into_oracle(gm, om)
+            before = sweep_both(gm, om, n)
+            r = compare_sweep(gm, om, n, before, where=f"tiled R={R} iter {it} mode {n}")
+            assert_tie_bounds(r, f"tiled R={R} iter {it} mode {n}")
+            rep.append(r)
+    print(f"TILED R={R}", json.dumps(summarize(rep)))

@@ -121,3 +121,37 @@ def test_actual_bytes_within_estimate(sacd, prec):
         m = sacd.Model(T, R, seed=seed, precision=prec)
         resident, _ = sacd.job_bytes(dims, idx.shape[0], R, prec)
         assert T.info()["device_bytes"] + m.device_bytes() <= resident
+
+
+def _tiled_job():
+    """A job whose mode 2 takes the tiled MTTKRP form (at least 2^20 entries,
+    padded rank 64, A_1 of 3000 rows: too large for the LDS kernel's whole
+    table)."""
+    dims, idx, vals = gen.uniform_coords((3000, 3000, 200), 1_100_000, 4242, "int1to5")
+    return (77, dims, idx, vals, 48)
+
+
+def test_tiled_form_served_equals_alone(sacd):
+    """A job whose mode-2 MTTKRP runs in the tiled form is launched on its
+    own inside the server's iteration, with the same kernel as alone: results
+    stay bit-identical, beside small jobs batched as usual."""
+    jobs = [_tiled_job()] + _small_jobs(2, ranks=[64, 16])
+    S, tickets, served, trace, est = _serve(sacd, jobs, budget=1 << 33, precision=0)
+    for t, (seed, dims, idx, vals, R) in zip(tickets, jobs):
+        it, fit, A = _alone(sacd, dims, idx, vals, R, seed, 0)
+        it_s, fit_s, A_s = served[t]
+        assert it_s == it and fit_s == fit, (t, it, it_s, fit, fit_s)
+        for n in range(3):
+            np.testing.assert_array_equal(A_s[n].view(np.uint32), A[n].view(np.uint32))
+
+
+def test_tiled_form_bytes_within_estimate(sacd):
+    seed, dims, idx, vals, R = _tiled_job()
+    T = sacd.Tensor.from_numpy(dims, idx, vals)
+    m = sacd.Model(T, R, seed=seed)
+    resident, _ = sacd.job_bytes(dims, idx.shape[0], R)
+    used = T.info()["device_bytes"] + m.device_bytes()
+    # the tiled copy of mode 2 (12 B per entry) is part of the model
+    m32 = sacd.Model(T, 32, seed=seed)
+    assert m.device_bytes() - m32.device_bytes() >= 12 * idx.shape[0]
+    assert used <= resident

@@ -42,6 +42,9 @@ CASES = {
     "n4-uniform": lambda: gen.nway_coords((60, 50, 40, 30), 20_000, 501),
     "n4-zipf-unit": lambda: gen.nway_coords((300, 1, 120, 45), 12_000, 502, (1.2, None, 1.1, None)),
     "n5-zipf": lambda: gen.nway_coords((40, 33, 25, 19, 7), 15_000, 503, (1.2, 1.2, None, None, 0.8)),
+    # the degenerate two-mode case (a sparse matrix) and the largest N
+    "n2-matrix": lambda: gen.nway_coords((700, 300), 30_000, 504, (1.1, None)),
+    "n8": lambda: gen.nway_coords((6, 5, 7, 4, 5, 6, 3, 5), 20_000, 505),
 }
 
 
@@ -106,6 +109,8 @@ def test_nway_init_factors_bitexact(sacd, oracle_mod, R):
     ("n4-zipf-unit", 20, 3),
     ("n5-zipf", 40, 3),
     ("n4-uniform", 100, 2),
+    ("n2-matrix", 16, 4),
+    ("n8", 12, 2),
 ])
 def test_nway_step_parity(sacd, oracle_mod, case, R, iters):
     """From the same (FP32-rounded) state, one sweep of each mode on both

@@ -258,6 +258,7 @@ FixArgs fix_args(const sacd_model *m, int n) {
   FixArgs x;
   x.longs = m->plan[n].longs;
   x.nlong = m->plan[n].nlong;
+  x.nbig = m->plan[n].nbig;
   x.part = m->part;
   x.M = m->M[n];
   x.Ga = m->G64[a];
@@ -350,6 +351,7 @@ sacd_status enqueue_sweep_columns(sacd_model *m, int n, const hipEvent_t *mark) 
   const int ncb = Rc / CB, nrb = col_row_blocks(I);
   FixArgs fx = fix_args(m, n);
   fx.nlong = 0;  // H, L and the diagonal only: no split slices of a whole M to add
+  fx.nbig = 0;
   HIP_TRY(launch_mttkrp_fix(RP, fx, s));
   if (mark) HIP_TRY(hipEventRecord(mark[0], s));
   HIP_TRY(launch_zero_words(m->bits, (int)(((long long)I * RP + 15) / 16), s));
@@ -563,7 +565,18 @@ const char *sacd_status_string(sacd_status s) {
 // slice, and *longs gets (slice, first slot, slots, 0) per split slice.
 // Sets each such unit's w to its run's slot; returns the number of slots.
 static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *longs,
-                       const std::vector<int> *block_of = nullptr) {
+                       const std::vector<int> *block_of = nullptr);
+
+// The fix-up's order of the split slices: those with more than kFixSmall
+// slots first (a block each), then the others (a lane group each); returns
+// how many are big.
+static int order_longs(std::vector<int4> *longs) {
+  std::stable_partition(longs->begin(), longs->end(), [](const int4 &l) { return l.z > kFixSmall; });
+  return (int)std::count_if(longs->begin(), longs->end(), [](const int4 &l) { return l.z > kFixSmall; });
+}
+
+static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *longs,
+                       const std::vector<int> *block_of) {
   std::vector<int> run_of(units.size(), -1);
   std::vector<int> run_slice;
   auto blk = [&](size_t u) { return block_of ? (size_t)(*block_of)[u] : u / (size_t)upb; };
@@ -668,6 +681,7 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
   }
   std::vector<int4> longs;
   const int nslots = number_runs(units, upb, &longs);
+  const int nbig = order_longs(&longs);
   // one slot per unit of a split slice, numbered slice by slice in entry order
   std::vector<int> uslot(units.size(), -1);
   std::vector<int4> ulongs;
@@ -689,6 +703,7 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
   p.nnz = t->nnz;
   p.nunits = (int)units.size();
   p.nlong = (int)longs.size();
+  p.nbig = nbig;
   p.nslots = nslots;
   int4 *du = nullptr, *dl = nullptr, *dul = nullptr;
   int *dus = nullptr;
@@ -1027,10 +1042,12 @@ static sacd_status build_tiled(sacd_model *m, int n, MttkrpPlan *out) {
   for (int4 &x : units) x.w = units_of_slice[x.x] > 1 ? -2 : -1;
   std::vector<int4> longs;
   const int nslots = number_runs(units, upb, &longs, &block_of);
+  const int nbig = order_longs(&longs);
   MttkrpPlan p{};
   p.nnz = u;
   p.nunits = (int)units.size();
   p.nlong = (int)longs.size();
+  p.nbig = nbig;
   p.nslots = nslots;
   int4 *du = nullptr, *dl = nullptr, *db = nullptr;
   SACD_TRY(m->mem.get_t(units.size() + 1, &du));
@@ -1840,7 +1857,7 @@ sacd_status rebuild_tables(sacd_server *S) {
         const int I = (int)m->t->dims[n];
         // a mode in the tiled form runs its own MTTKRP launch (below)
         if (!m->btab[n]) g.nb_mt[n] += mttkrp_blocks(g.RP, m->plan[n].nunits);
-        g.nb_fx[n] += fix_blocks(m->plan[n].nlong);
+        g.nb_fx[n] += fix_blocks(g.RP, m->plan[n].nlong, m->plan[n].nbig);
         g.nb_im[n] += importance_blocks(g.RP, I);
         g.nb_up[n] += update_blocks(g.RP, I);
         g.nb_gf[n] += gram_final_blocks(g.RP);
@@ -1884,7 +1901,7 @@ sacd_status rebuild_tables(sacd_server *S) {
       const int I = (int)m->t->dims[n];
       int nb = 0;
       if (which == 0) nb = m->btab[n] ? 0 : mttkrp_blocks(g.RP, m->plan[n].nunits);
-      else if (which == 1) nb = fix_blocks(m->plan[n].nlong);
+      else if (which == 1) nb = fix_blocks(g.RP, m->plan[n].nlong, m->plan[n].nbig);
       else if (which == 2) nb = importance_blocks(g.RP, I);
       else if (which == 3) nb = gram_final_blocks(g.RP);
       else nb = update_blocks(g.RP, I);
@@ -2384,10 +2401,12 @@ sacd_status build_nplan(const sacd_ntensor *t, int n, int upb, DevAlloc &mem, Mt
   std::stable_sort(units.begin(), units.end(), [](const int4 &x, const int4 &y) { return x.z > y.z; });
   std::vector<int4> longs;
   const int nslots = number_runs(units, upb, &longs);
+  const int nbig = order_longs(&longs);
   MttkrpPlan p{};
   p.nnz = t->nnz;
   p.nunits = (int)units.size();
   p.nlong = (int)longs.size();
+  p.nbig = nbig;
   p.nslots = nslots;
   int4 *du = nullptr, *dl = nullptr;
   SACD_TRY(mem.get_t(units.size() + 1, &du));
@@ -2573,6 +2592,7 @@ sacd_status enqueue_nsweep(sacd_nmodel *m, int n, const hipEvent_t *mark = nullp
   FixArgs fx{};
   fx.longs = m->plan[n].longs;
   fx.nlong = m->plan[n].nlong;
+  fx.nbig = m->plan[n].nbig;
   fx.part = m->part;
   fx.M = m->M[n];
   fx.Ga = m->P;

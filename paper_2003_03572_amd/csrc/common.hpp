@@ -132,6 +132,7 @@ struct MttkrpPlan {
   int nunits;         // work units, longest first
   const int4 *units;  // device: (slice, first entry, entries, partial slot or -1)
   int nlong;          // slices split over several units
+  int nbig;           // of them, those with more than kFixSmall slots (first in longs)
   const int4 *longs;  // device: (slice, first partial slot, slots, 0)
   int nslots;         // partial slots
   // one partial slot per unit of a split slice (the column-at-a-time form):
@@ -142,7 +143,10 @@ struct MttkrpPlan {
 };
 int mttkrp_units_per_block(int RP);
 int mttkrp_blocks(int RP, int nunits);
-int fix_blocks(int nlong);
+// Split slices of at most kFixSmall slots are added by one lane group each,
+// kThreads / (RP / 4) of them per block; larger ones by a block each.
+constexpr int kFixSmall = 8;
+int fix_blocks(int RP, int nlong, int nbig);
 struct MttkrpArgs {
   const unsigned long long *keys;
   const float *vals;
@@ -153,8 +157,9 @@ struct MttkrpArgs {
   float *M, *part;
 };
 struct FixArgs {
-  const int4 *longs;
+  const int4 *longs;  // big split slices first (nbig of them), then the small ones
   int nlong;
+  int nbig;
   const float *part;
   float *M;
   const double *Ga, *Gb;

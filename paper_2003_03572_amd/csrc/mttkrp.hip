@@ -437,8 +437,10 @@ int mttkrp_units_per_block(int RP) {
 
 namespace {
 
-// Fix-up: blocks [0, nlong) add the partial sums of one split slice in a
-// fixed tree order; the last block forms H = Gram_a * Gram_b, L = ||H||_F
+// Fix-up: blocks [0, nbig) add the partial sums of one split slice with more
+// than kFixSmall slots each, in a fixed tree order; the next blocks add those
+// of the smaller split slices, one per row of lanes, in slot order; the last
+// block forms H = Gram_a * Gram_b, L = ||H||_F
 // and the diagonal of H for the element kernels of this sweep (eq. 10,
 // eq. 15, Alg. 1).  Empty slices are never written: M is zeroed when the
 // model is set up.  The slice sums need every MTTKRP block to have finished,
@@ -471,10 +473,13 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const Fix
   HInfo *hinfo = args.hinfo;
   ModeState *st = args.st;
   const int b = blk, tid = threadIdx.x;
-  if (b < nlong) {
+  constexpr int Q = RP / 4;          // lanes per row (float4 each)
+  constexpr int NS = kThreads / Q;   // rows of lanes per block
+  const int nbig = args.nbig;
+  const int nsb = (nlong - nbig + NS - 1) / NS;  // blocks of small split slices
+  if (b < nbig) {
+    // a split slice with many slots: NS lanes rows over its slots, then a tree
     const int4 L = longs[b];  // (slice, first slot, slots, -)
-    constexpr int Q = RP / 4;
-    constexpr int NS = kThreads / Q;
     __shared__ f32x4 red[NS][Q];
     const int slot = tid / Q, q = tid % Q;
     f32x4 s = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -488,14 +493,51 @@ __global__ __launch_bounds__(kThreads) void k_mttkrp_fix(FixArgs solo, const Fix
     if (slot == 0) st4(M + (long long)L.x * RP + 4 * q, red[0][q]);
     break;
   }
-  // H, L, diagonal
+  if (b < nbig + nsb) {
+    // small split slices, one per row of lanes: its (at most kFixSmall)
+    // slots loaded together, then added in slot order
+    const int g = nbig + (b - nbig) * NS + tid / Q, q = tid % Q;
+    if (g < nlong) {
+      const int4 L = longs[g];
+      f32x4 v[kFixSmall];
+#pragma unroll
+      for (int j = 0; j < kFixSmall; ++j)
+        v[j] = j < L.z ? ld4(part + (long long)(L.y + j) * RP + 4 * q) : f32x4{0.f, 0.f, 0.f, 0.f};
+      f32x4 s = v[0];
+#pragma unroll
+      for (int j = 1; j < kFixSmall; ++j)
+        if (j < L.z) s += v[j];
+      st4(M + (long long)L.x * RP + 4 * q, s);
+    }
+    break;
+  }
+  // H, L, diagonal.  The loads of a chunk of CH entries per thread are
+  // issued before any of them is used (one block does all RP x RP entries: a
+  // load, multiply and store at a time would wait on every load).
   __shared__ double l2[kThreads];
   __shared__ float mx[kThreads];
   double s2 = 0.0;
-  for (int i = tid; i < RP * RP; i += kThreads) {
-    const double h = Ga[i] * Gb[i];
-    H[i] = (float)h;
-    s2 += h * h;
+  {
+    constexpr int PER = (RP * RP + kThreads - 1) / kThreads;  // entries per thread
+    constexpr int CH = PER < 16 ? PER : 16;
+    static_assert(PER % CH == 0, "whole chunks");
+#pragma unroll 1
+    for (int c0 = 0; c0 < PER; c0 += CH) {
+      double ga[CH], gb[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (c0 + k) * kThreads;
+        ga[k] = i < RP * RP ? Ga[i] : 0.0;
+        gb[k] = i < RP * RP ? Gb[i] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int i = tid + (c0 + k) * kThreads;
+        const double h = ga[k] * gb[k];
+        if (i < RP * RP) H[i] = (float)h;
+        s2 += h * h;
+      }
+    }
   }
   float dmax = 0.0f;
   for (int r = tid; r < RP; r += kThreads) {
@@ -565,7 +607,7 @@ struct MtBL {
 template <int RP>
 struct FxL {
   static hipError_t run(const FixArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_mttkrp_fix<RP, false>), dim3(fix_blocks(a.nlong)), dim3(kThreads), 0, s, a, nullptr,
+    hipLaunchKernelGGL((k_mttkrp_fix<RP, false>), dim3(fix_blocks(RP, a.nlong, a.nbig)), dim3(kThreads), 0, s, a, nullptr,
                        nullptr, 0);
     return hipGetLastError();
   }
@@ -630,7 +672,10 @@ int mttkrp_blocks(int RP, int nunits) {
   const int upb = mttkrp_units_per_block(RP);
   return (nunits + upb - 1) / upb;
 }
-int fix_blocks(int nlong) { return nlong + 1; }
+int fix_blocks(int RP, int nlong, int nbig) {
+  const int ns = kThreads / (RP / 4);
+  return nbig + (nlong - nbig + ns - 1) / ns + 1;
+}
 
 hipError_t launch_mttkrp(int RP, const MttkrpArgs &a, hipStream_t s) { return rp_dispatch<MtL>(RP, a, s); }
 hipError_t launch_mttkrp_b(int RP, const MttkrpArgs *jobs, const int4 *bmap, int nblocks, hipStream_t s) {

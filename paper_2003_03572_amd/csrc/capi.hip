@@ -938,8 +938,10 @@ void sacd_destroy_tensor(sacd_tensor *t) {
 // when A_b (the per-entry table) is too large for the LDS kernel's whole
 // table and the tensor has at least kTileMinEntries entries (smaller ones
 // keep the plain form: the copy and its sort would not pay).  The bits of
-// the tile field must fit the key.
+// the tile field must fit the key, and the (slice, tile) pairs number at
+// most kTileMaxRuns.
 constexpr long long kTileMinEntries = 1ll << 20;
+constexpr long long kTileMaxRuns = 1ll << 24;  // slices x tiles of a tiled mode, at most
 
 static int tile_bits(long long Ib) { return bits_for((Ib + kTileRows - 1) / kTileRows); }
 
@@ -949,7 +951,8 @@ static bool tiled_mode(const int64_t dims[3], long long nnz, int RP, int cb, int
   if (cb != 0 || RP < 64 || nnz < kTileMinEntries || mttkrp_lds_cols(RP, dims[b]) != 0) return false;
   const int tb = tile_bits(dims[b]);
   if (bits_for(dims[0]) + bits_for(dims[1]) + bits_for(dims[2]) + tb > 64) return false;
-  return ((long long)dims[n] << tb) < 2147483647LL;
+  // (slice, tile) offsets are built on the host and the device: keep them modest
+  return ((long long)dims[n] << tb) <= kTileMaxRuns;
 }
 
 // Tiled copy of mode n's entries and its plan: keys in (i_n, i_b tile, i_a,

@@ -5,12 +5,13 @@ one piece of code that both the GPU library's callers and the CPU oracle's
 tests use.  The paper's own datasets (Sec. 6.1) are not used; these
 generators stand in for its synthetic tensors (Sec. 6.4: cubes of growing
 mode length at fixed density) and for its user x item x tag tensors (skewed
-index popularity), with the shapes and value ranges described in the design doc.
+index popularity), with the shapes and value ranges of the named workloads
+below.
 
-Every tensor is returned as ``(dims, idx, vals)`` with ``idx`` an (nnz, 3)
-int32 array of 0-based coordinates and ``vals`` a float32 array.  Coordinates
-are distinct (duplicates are removed at generation time, keeping the first
-draw).
+Every tensor is returned as ``(dims, idx, vals)`` with ``idx`` an (nnz, N)
+int32 array of 0-based coordinates (N = 3, except for ``nway_coords``) and
+``vals`` a float32 array.  Coordinates are distinct (duplicates are removed at
+generation time, keeping the first draw).
 """
 from __future__ import annotations
 

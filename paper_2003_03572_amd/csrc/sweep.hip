@@ -21,6 +21,8 @@
 // result.
 #include "common.hpp"
 
+#include <utility>
+
 namespace sacd {
 
 namespace {
@@ -401,25 +403,106 @@ __global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs 
  }
 }
 
-// Gauss-Seidel / Jacobi update of one row (eq. 11-13), LPR lanes per row:
-// lane `part` keeps the row's columns [part CPL, (part + 1) CPL) of a and g
-// in registers.  For each selected column r in order, the lane owning r
-// takes the one-variable step; under Gauss-Seidel the step d is passed to
+// A lane with at most this many of a row's columns holds their h_rr and
+// near-zero flags in registers through the chain; one with more reads them
+// from their LDS copy at each step (registers would spill).
+constexpr int kPreCols = 16;
+
+// Value of lane OWNER of the caller's row group of LPR lanes, to every lane
+// of the group, by a DPP lane move (row groups are aligned to LPR lanes):
+// quad_perm within quads of 4 lanes, row_newbcast within rows of 16.
+template <int LPR, int OWNER>
+__device__ __forceinline__ float row_bcast(float d) {
+  const int x = __float_as_int(d);
+  if constexpr (LPR == 2) {
+    constexpr int q = OWNER | (OWNER << 2) | ((2 + OWNER) << 4) | ((2 + OWNER) << 6);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, q, 0xF, 0xF, false));
+  } else if constexpr (LPR == 4) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, OWNER * 0x55, 0xF, 0xF, false));
+  } else if constexpr (LPR == 8) {
+    const int lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + OWNER, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, x, 0x158 + OWNER, 0xF, 0xF, false);
+    return __int_as_float((threadIdx.x & 8u) ? hi : lo);
+  } else if constexpr (LPR == 16) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x150 + OWNER, 0xF, 0xF, false));
+  } else {
+    return __shfl(d, OWNER, LPR);
+  }
+}
+
+// Step r of a row's chain (r a constant): skipped unless column r is
+// selected (with h_rr > 0).
+template <int RP, int UPD, int LPR, int NW, int R>
+__device__ __forceinline__ void chain_step(float *a, float *g, const float *hl, const bool *nzl,
+                                           const unsigned long long *sel, const float *sH, const float *sHd,
+                                           const int *sNz, int part) {
+  constexpr int CPL = RP / LPR, OWNER = R / CPL, J = R % CPL;
+  constexpr bool PRE = CPL <= kPreCols;
+  if (!((sel[R >> 6] >> (R & 63)) & 1ull)) return;
+  float d = 0.0f;
+  if (LPR == 1 || part == OWNER) {
+    const float h = PRE ? hl[J] : sHd[R];
+    const bool nz = PRE ? nzl[J] : (sNz[R] != 0);
+    const float q = nz ? (float)((double)g[J] / (double)h) : __fdiv_rn(g[J], h);
+    const float an = fmaxf(__fsub_rn(a[J], q), 0.0f);  // eq. 11-13
+    d = __fsub_rn(an, a[J]);
+    a[J] = an;
+  }
+  if (UPD == 0) {
+    if constexpr (LPR > 1) d = row_bcast<LPR, OWNER>(d);
+    if (d != 0.0f) {
+      if constexpr (LPR == 1) {
+#pragma unroll
+        for (int s = R + 1; s < RP; ++s) g[s] = __fmaf_rn(d, sH[R * (RP + 1) + s], g[s]);
+      } else if (part * CPL + CPL - 1 > R) {
+#pragma unroll
+        for (int jj = 0; jj < CPL; ++jj) g[jj] = __fmaf_rn(d, sH[R * (RP + 1) + part * CPL + jj], g[jj]);
+      }
+    }
+  }
+}
+
+template <int RP, int UPD, int LPR, int NW, int... Rs>
+__device__ __forceinline__ void chain_steps(float *a, float *g, const float *hl, const bool *nzl,
+                                            const unsigned long long *sel, const float *sH, const float *sHd,
+                                            const int *sNz, int part, std::integer_sequence<int, Rs...>) {
+  (chain_step<RP, UPD, LPR, NW, Rs>(a, g, hl, nzl, sel, sH, sHd, sNz, part), ...);
+}
+
+// One row's Gauss-Seidel (UPD 0) or Jacobi (UPD 1) steps over its selected
+// columns in increasing order (Alg. 1, eq. 11-13).  The row's LPR lanes
+// share it: lane `part` keeps the row's columns [part CPL, (part + 1) CPL) of
+// a and g in registers.  For each selected column r in order, the lane owning
+// r takes the one-variable step; under Gauss-Seidel the step d is passed to
 // the row's other lanes, which refresh their columns' gradient,
 // g_s += d H_rs.  Only columns s > r are read again, so the refresh of the
 // others (done to keep the loop free of per-lane bounds) changes nothing.
 template <int RP, int UPD, int LPR>
 __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const unsigned short *s_l,
-                                           const float *sH, const HInfo *__restrict__ hi, int part) {
+                                           const float *sH, const float *sHd, const int *sNz,
+                                           const unsigned long long *hpos, int part) {
   constexpr int CPL = RP / LPR;  // columns per lane
+  constexpr bool PRE = CPL <= kPreCols;
+  constexpr int NPRE = PRE ? CPL : 1;
   const int c0 = part * CPL;
-  float a[CPL], g[CPL];
+  float a[CPL], g[CPL], hl[NPRE];
+  bool nzl[NPRE];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
     a[j] = a_l[c0 + j];
     g[j] = g_l[c0 + j];
   }
-  // selection bits of the whole row: the row's lanes walk the same steps
+  // h_rr and its near-zero flag of the lane's columns (from their LDS copy)
+  // are held in registers through the chain when the lane has few columns
+  if constexpr (PRE) {
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      hl[j] = sHd[c0 + j];
+      nzl[j] = sNz[c0 + j] != 0;
+    }
+  }
+  // selection bits of the whole row, less the columns with h_rr <= 0 (no
+  // step there): the row's lanes walk the same steps
   constexpr int NW = (RP + 63) / 64;
   unsigned long long sel[NW];
 #pragma unroll
@@ -428,33 +511,9 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
 #pragma unroll
     for (int k = 0; k < 4 && 4 * w + k < RP / 16; ++k)
       sel[w] |= (unsigned long long)s_l[4 * w + k] << (16 * k);
+    sel[w] &= hpos[w];
   }
-#pragma unroll
-  for (int r = 0; r < RP; ++r) {
-    if (!((sel[r >> 6] >> (r & 63)) & 1ull)) continue;
-    const float h = hi->hdiag[r];
-    if (!(h > 0.0f)) continue;
-    const int owner = r / CPL, j = r % CPL;
-    float d = 0.0f;
-    if (LPR == 1 || part == owner) {
-      const float q = hi->nearzero[r] ? (float)((double)g[j] / (double)h) : __fdiv_rn(g[j], h);
-      const float an = fmaxf(__fsub_rn(a[j], q), 0.0f);  // eq. 11-13
-      d = __fsub_rn(an, a[j]);
-      a[j] = an;
-    }
-    if (UPD == 0) {
-      if (LPR > 1) d = __shfl(d, owner, LPR);
-      if (d != 0.0f) {
-        if (LPR == 1) {
-#pragma unroll
-          for (int s = r + 1; s < RP; ++s) g[s] = __fmaf_rn(d, sH[r * (RP + 1) + s], g[s]);
-        } else if (c0 + CPL - 1 > r) {
-#pragma unroll
-          for (int jj = 0; jj < CPL; ++jj) g[jj] = __fmaf_rn(d, sH[r * (RP + 1) + c0 + jj], g[jj]);
-        }
-      }
-    }
-  }
+  chain_steps<RP, UPD, LPR, NW>(a, g, hl, nzl, sel, sH, sHd, sNz, part, std::make_integer_sequence<int, RP>{});
 #pragma unroll
   for (int j = 0; j < CPL; ++j) a_l[c0 + j] = a[j];
 }
@@ -497,8 +556,20 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
   __shared__ unsigned short sSel[Cf::RB * (RP / 16)];  // selection bits, 16 columns a word
   __shared__ double sT[Cf::NT];  // per-tile sums
   __shared__ int sCnt[RP];
+  __shared__ unsigned long long sHpos[(RP + 63) / 64];  // bit r: h_rr > 0
+  __shared__ float sHd[RP];  // h_rr
+  __shared__ int sNz[RP];    // h_rr near zero: divide in FP64
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
+  for (int c = tid; c < RP; c += Cf::NTH) {
+    sHd[c] = hi->hdiag[c];
+    sNz[c] = hi->nearzero[c];
+  }
+  if (wv < (RP + 63) / 64) {
+    const int c = 64 * wv + lane;
+    const unsigned long long b = __ballot(c < RP && hi->hdiag[c < RP ? c : 0] > 0.0f);
+    if (lane == 0) sHpos[wv] = b;
+  }
   // this thread's MTTKRP and previous-importance entries for all its tiles,
   // fetched before anything waits on them
   float mreg[Cf::NTW][4], zpreg[Cf::NTW][4];
@@ -559,8 +630,8 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
     constexpr int LPR = Cf::NTH / Cf::RB;  // lanes per row
     const int row = tid / LPR;
     if (row0 + row < I)  // the same for all lanes of a row
-      update_row<RP, UPD, LPR>(sA + row * Cf::STR, sG + row * Cf::STR, sSel + row * (RP / 16), sH, hi,
-                               tid % LPR);
+      update_row<RP, UPD, LPR>(sA + row * Cf::STR, sG + row * Cf::STR, sSel + row * (RP / 16), sH, sHd, sNz,
+                               sHpos, tid % LPR);
   }
   __syncthreads();
   for (int i = tid; i < Cf::RB * RP; i += Cf::NTH) {

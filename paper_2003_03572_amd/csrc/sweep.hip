@@ -436,7 +436,7 @@ template <int RP, int UPD, int LPR, int NW, int R>
 __device__ __forceinline__ void chain_step(float *a, float *g, const float *hl, const bool *nzl,
                                            const unsigned long long *sel, const float *sH, const float *sHd,
                                            const int *sNz, int part) {
-  constexpr int CPL = RP / LPR, OWNER = R / CPL, J = R % CPL;
+  constexpr int CPL = RP / LPR, OWNER = R % LPR, J = R / LPR;
   constexpr bool PRE = CPL <= kPreCols;
   if (!((sel[R >> 6] >> (R & 63)) & 1ull)) return;
   float d = 0.0f;
@@ -454,9 +454,10 @@ __device__ __forceinline__ void chain_step(float *a, float *g, const float *hl, 
       if constexpr (LPR == 1) {
 #pragma unroll
         for (int s = R + 1; s < RP; ++s) g[s] = __fmaf_rn(d, sH[R * (RP + 1) + s], g[s]);
-      } else if (part * CPL + CPL - 1 > R) {
+      } else if (part + LPR * (CPL - 1) > R) {
+        // the row group reads consecutive words of H's row R for each jj
 #pragma unroll
-        for (int jj = 0; jj < CPL; ++jj) g[jj] = __fmaf_rn(d, sH[R * (RP + 1) + part * CPL + jj], g[jj]);
+        for (int jj = 0; jj < CPL; ++jj) g[jj] = __fmaf_rn(d, sH[R * (RP + 1) + part + LPR * jj], g[jj]);
       }
     }
   }
@@ -471,8 +472,8 @@ __device__ __forceinline__ void chain_steps(float *a, float *g, const float *hl,
 
 // One row's Gauss-Seidel (UPD 0) or Jacobi (UPD 1) steps over its selected
 // columns in increasing order (Alg. 1, eq. 11-13).  The row's LPR lanes
-// share it: lane `part` keeps the row's columns [part CPL, (part + 1) CPL) of
-// a and g in registers.  For each selected column r in order, the lane owning
+// share it: lane `part` keeps the row's columns part, part + LPR, ... of a
+// and g in registers.  For each selected column r in order, the lane owning
 // r takes the one-variable step; under Gauss-Seidel the step d is passed to
 // the row's other lanes, which refresh their columns' gradient,
 // g_s += d H_rs.  Only columns s > r are read again, so the refresh of the
@@ -484,21 +485,20 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
   constexpr int CPL = RP / LPR;  // columns per lane
   constexpr bool PRE = CPL <= kPreCols;
   constexpr int NPRE = PRE ? CPL : 1;
-  const int c0 = part * CPL;
   float a[CPL], g[CPL], hl[NPRE];
   bool nzl[NPRE];
 #pragma unroll
   for (int j = 0; j < CPL; ++j) {
-    a[j] = a_l[c0 + j];
-    g[j] = g_l[c0 + j];
+    a[j] = a_l[part + LPR * j];
+    g[j] = g_l[part + LPR * j];
   }
   // h_rr and its near-zero flag of the lane's columns (from their LDS copy)
   // are held in registers through the chain when the lane has few columns
   if constexpr (PRE) {
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
-      hl[j] = sHd[c0 + j];
-      nzl[j] = sNz[c0 + j] != 0;
+      hl[j] = sHd[part + LPR * j];
+      nzl[j] = sNz[part + LPR * j] != 0;
     }
   }
   // selection bits of the whole row, less the columns with h_rr <= 0 (no
@@ -515,7 +515,7 @@ __device__ __forceinline__ void update_row(float *a_l, const float *g_l, const u
   }
   chain_steps<RP, UPD, LPR, NW>(a, g, hl, nzl, sel, sH, sHd, sNz, part, std::make_integer_sequence<int, RP>{});
 #pragma unroll
-  for (int j = 0; j < CPL; ++j) a_l[c0 + j] = a[j];
+  for (int j = 0; j < CPL; ++j) a_l[part + LPR * j] = a[j];
 }
 
 // Block blk of the selection / update pass of one sweep.

@@ -11,8 +11,9 @@
 //                    row's gradient, or Jacobi), and emits per-block partials
 //                    of the new Gram matrix (MFMA), of <M, A_n> (FP64) and of
 //                    the per-column selection counts.
-//   k_gram_final     reduces the Gram partials in FP64 in a fixed order; the
-//                    last block forms the objective eq. 6 in FP64.
+//   k_gram_final     reduces the Gram partials in FP64 in a fixed order; its
+//                    last block, or k_gram_finish at RP >= 64, forms the
+//                    objective eq. 6 in FP64.
 //
 // Rows are split into blocks of RB rows (256 at RP <= 32, fewer above); a
 // block keeps its rows of A_n and H in LDS (row stride RP + 1 floats:
@@ -746,6 +747,44 @@ constexpr int gram_strips() {
   return 16 * (RP / 16) * (RP / 16 + 1) / 2;
 }
 
+// The sweep's objective (eq. 6) and total selection count from the shares
+// k_gram_final wrote, by one block in a fixed order:
+//   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs.
+// The shares must be visible to the block: written by an earlier kernel, or
+// by blocks that issued a device-scope fence before the caller's arrival
+// counter showed them done.  red holds kGramThreads / 64 values.
+template <int RP>
+__device__ __forceinline__ void gram_finish_body(const GramArgs &args, double *red) {
+  constexpr int NS = gram_strips<RP>();
+  const int tid = threadIdx.x;
+  ModeState *st = args.st;
+  double mv = 0.0;
+  long long cv = 0;
+  if (args.with_f)
+    for (int k = tid; k < NS; k += kGramThreads) mv += ld_coherent(&args.mpart[k]);
+  if (args.cnt_part && tid < RP) cv = ld_coherent(&args.colcnt[tid]);
+  if (args.with_f) {
+    const double inner = ld_coherent(&st->inner);
+    const double model = block_sum<kGramThreads>(mv, red);
+    if (tid == 0) st->f = args.normX2 - 2.0 * inner + model;
+  }
+  if (args.cnt_part) {
+    const double all = block_sum<kGramThreads>((double)cv, red);
+    if (tid == 0) st->nsel = (long long)all;
+  }
+}
+
+// Where the objective is formed: at RP >= 64 (hundreds of strip blocks) by
+// k_gram_finish after k_gram_final; at smaller ranks by the last block of
+// k_gram_final to arrive.  An arrival counter needs a device-scope fence in
+// every block (measured 10 us per launch at R = 128, 585 blocks), a kernel of
+// its own about 4 us per launch (more than the fences of the 51 blocks at
+// R = 32).  The result is the same either way.
+template <int RP>
+constexpr bool gram_split() {
+  return RP >= 64;
+}
+
 // Gram reduction in FP64 and the sweep's scalars, one level, fixed order.
 // Blocks [0, NS): one 16-entry strip (row i, columns 16 tj .. 16 tj + 15,
 // tile tj >= tile of i) of Gram_n each; thread (e, s) = (tid % 16, tid / 16)
@@ -754,10 +793,9 @@ constexpr int gram_strips() {
 // mirrored, and with with_f the block also writes its share of
 //   sum_rs (Gram_n * Gram_a * Gram_b)_rs
 // (entries of off-diagonal tiles count twice).  Blocks [NS, NS + RP/16):
-// selection counts of 16 columns.  Block NS + RP/16: <M, A_n>.  The last
-// block to arrive forms the objective
-//   f = ||X||^2 - 2 <M_n, A_n> + sum_rs (Gram_0 * Gram_1 * Gram_2)_rs   (eq. 6)
-// and the total selection count.
+// selection counts of 16 columns.  Block NS + RP/16: <M, A_n>.  Then
+// gram_finish_body forms the objective and the total selection count (see
+// gram_split).
 template <int RP, bool BATCHED>
 __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, const GramArgs *__restrict__ jobs,
                                                          const int4 *__restrict__ bmap, int nb) {
@@ -789,9 +827,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
   const double *__restrict__ inner_part = args.inner_part;
   const int *__restrict__ cnt_part = args.cnt_part;
   long long *__restrict__ colcnt = args.colcnt;
-  const double normX2 = args.normX2;
   const int with_f = args.with_f;
-  unsigned *counter = args.counter;
   ModeState *st = args.st;
   constexpr int RR = RP * RP, n16 = RP / 16, NS = gram_strips<RP>();
   __shared__ double red[kGramThreads / 4];
@@ -853,33 +889,44 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
       if (tid == 0) st->inner = in;
     }
   }
-  __syncthreads();
-  if (tid == 0) {
+  if constexpr (!gram_split<RP>()) {
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      const unsigned prev = atomicAdd(args.counter, 1u);
+      s_last = (prev == (unsigned)nblk - 1);
+    }
+    __syncthreads();
+    if (!s_last) break;
     __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == (unsigned)nblk - 1);
+    gram_finish_body<RP>(args, red);
+    if (tid == 0) *args.counter = 0;
   }
-  __syncthreads();
-  if (!s_last) break;
-  __threadfence();
-  double mv = 0.0;
-  long long cv = 0;
-  for (int k = tid; k < NS; k += kGramThreads)
-    if (with_f) mv += ld_coherent(&mpart[k]);
-  if (cnt_part && tid < RP) cv = ld_coherent(&colcnt[tid]);
-  const double inner = with_f ? ld_coherent(&st->inner) : 0.0;
-  if (with_f) {
-    const double model = block_sum<kGramThreads>(mv, red);
-    if (tid == 0) st->f = normX2 - 2.0 * inner + model;
-  }
-  if (cnt_part) {
-    const double all = block_sum<kGramThreads>((double)cv, red);
-    if (tid == 0) st->nsel = (long long)all;
-  }
-  if (tid == 0) *counter = 0;
   } while (0);
   if constexpr (!BATCHED) break;
   __syncthreads();  // the block's LDS is reused by its next work item
+ }
+}
+
+// The objective and total selection count as a kernel of its own, one block
+// per job (batched form: the block map's first block of each job), for
+// gram_split ranks.
+template <int RP, bool BATCHED>
+__global__ __launch_bounds__(kGramThreads) void k_gram_finish(GramArgs solo, const GramArgs *__restrict__ jobs,
+                                                          const int4 *__restrict__ bmap, int nb) {
+ for (int item = blockIdx.x;; item += gridDim.x) {
+  GramArgs args;
+  if constexpr (BATCHED) {
+    if (item >= nb) break;
+    const int4 m = bmap[item];
+    if (m.y != 0) continue;  // uniform over the block
+    args = jobs[m.x];
+  } else {
+    args = solo;
+  }
+  __shared__ double red[kGramThreads / 64];
+  gram_finish_body<RP>(args, red);
+  if constexpr (!BATCHED) break;
  }
 }
 
@@ -1194,6 +1241,8 @@ struct GfL {
   static hipError_t run(const GramArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_gram_final<RP, false>), dim3(gram_final_blocks(RP)), dim3(kGramThreads), 0, s, a, nullptr,
                        nullptr, 0);
+    if constexpr (gram_split<RP>())
+      hipLaunchKernelGGL((k_gram_finish<RP, false>), dim3(1), dim3(kGramThreads), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
 };
@@ -1204,6 +1253,9 @@ struct GfBL {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL((k_gram_final<RP, true>), dim3(persistent_grid(nb)), dim3(kGramThreads), 0, s, GramArgs{}, jobs,
                        bmap, nb);
+    if constexpr (gram_split<RP>())
+      hipLaunchKernelGGL((k_gram_finish<RP, true>), dim3(persistent_grid(nb)), dim3(kGramThreads), 0, s, GramArgs{},
+                         jobs, bmap, nb);
     return hipGetLastError();
   }
 };

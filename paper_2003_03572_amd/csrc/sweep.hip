@@ -411,23 +411,20 @@ constexpr int kPreCols = 16;
 
 // Value of lane OWNER of the caller's row group of LPR lanes, to every lane
 // of the group, by a DPP lane move (row groups are aligned to LPR lanes):
-// quad_perm within quads of 4 lanes, row_newbcast within rows of 16.
+// quad_perm within quads of 4 lanes, row_newbcast within rows of 16 (the
+// row groups the element passes use: 4, 8 or 16 lanes).
 template <int LPR, int OWNER>
 __device__ __forceinline__ float row_bcast(float d) {
+  static_assert(LPR == 4 || LPR == 8 || LPR == 16, "row groups of 4, 8 or 16 lanes");
   const int x = __float_as_int(d);
-  if constexpr (LPR == 2) {
-    constexpr int q = OWNER | (OWNER << 2) | ((2 + OWNER) << 4) | ((2 + OWNER) << 6);
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, q, 0xF, 0xF, false));
-  } else if constexpr (LPR == 4) {
+  if constexpr (LPR == 4) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, x, OWNER * 0x55, 0xF, 0xF, false));
   } else if constexpr (LPR == 8) {
     const int lo = __builtin_amdgcn_update_dpp(0, x, 0x150 + OWNER, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, x, 0x158 + OWNER, 0xF, 0xF, false);
     return __int_as_float((threadIdx.x & 8u) ? hi : lo);
-  } else if constexpr (LPR == 16) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x150 + OWNER, 0xF, 0xF, false));
   } else {
-    return __shfl(d, OWNER, LPR);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, x, 0x150 + OWNER, 0xF, 0xF, false));
   }
 }
 

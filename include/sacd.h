@@ -302,7 +302,7 @@ typedef struct {
   int32_t use_graphs;       /* 1: replay unchanged job sets from a HIP graph */
 } sacd_server_config;
 
-enum { SACD_JOB_QUEUED = 0, SACD_JOB_RUNNING = 1, SACD_JOB_DONE = 2, SACD_JOB_FAILED = 3 };
+enum { SACD_JOB_QUEUED = 0, SACD_JOB_RUNNING = 1, SACD_JOB_DONE = 2, SACD_JOB_FAILED = 3, SACD_JOB_CANCELLED = 4 };
 
 typedef struct {
   int32_t running, queued;
@@ -327,7 +327,9 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
  * budget.  *ticket identifies the job in later calls. */
 sacd_status sacd_server_submit(sacd_server *s, const int64_t dims[3], int64_t nnz, const int32_t *idx,
                                const float *vals, int32_t R, uint64_t seed, int64_t *ticket);
-/* Admit, iterate every running job once, retire finished ones. */
+/* Admit, iterate every running job once, retire finished ones.  A job whose
+ * objective turns non-finite fails there (state FAILED, status NUMERIC, its
+ * memory freed, no result); the other jobs run on unchanged. */
 sacd_status sacd_server_step(sacd_server *s, int32_t *n_running, int32_t *n_queued);
 /* Tickets that finished (done or failed) in the last step: the first
  * min(cap, *n) are written to tickets (host). */
@@ -338,8 +340,20 @@ sacd_status sacd_server_poll(const sacd_server *s, int64_t ticket, int32_t *stat
                              double *fit, double *objective);
 /* Factor `mode` of a done job into dst (HOST, I_n x R row-major f32). */
 sacd_status sacd_server_result(const sacd_server *s, int64_t ticket, int32_t mode, float *dst);
-/* Forget a done or failed job's result. */
+/* Forget a done, failed or cancelled job's result. */
 sacd_status sacd_server_release(sacd_server *s, int64_t ticket);
+/* Cancel a queued or running job (between steps): it leaves the queue, or
+ * stops and frees its device memory at once; state CANCELLED, no result; the
+ * other jobs run on unchanged.  Errors: INVALID_ARG (unknown ticket),
+ * BAD_STATE (the job has already finished). */
+sacd_status sacd_server_cancel(sacd_server *s, int64_t ticket);
+/* Set the budget of later admissions to budget_bytes (at most the budget the
+ * server was created with).  Running jobs keep their memory even above a
+ * lowered budget; no job is admitted until the running jobs' bytes plus its
+ * bound fit.  Queued jobs whose bound alone exceeds the new budget fail
+ * (status NO_MEMORY), as sacd_server_submit refuses such jobs.  Errors:
+ * INVALID_ARG (budget not in (0, creation budget]). */
+sacd_status sacd_server_set_budget(sacd_server *s, int64_t budget_bytes);
 sacd_status sacd_server_stats(const sacd_server *s, sacd_server_stats_t *out);
 void sacd_server_destroy(sacd_server *s);
 

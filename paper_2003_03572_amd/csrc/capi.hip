@@ -1758,6 +1758,7 @@ struct sacd_server {
   std::vector<int64_t> finished;  // tickets finished in the last step
   int64_t next_ticket = 1;
   int64_t bytes_in_use = 0, peak_bytes = 0;
+  int64_t budget_cap = 0;  // the budget at creation: the arena's size
   // launch tables
   DevAlloc tables;
   char *h_stage = nullptr;
@@ -2057,6 +2058,21 @@ sacd_status retire(sacd_server *S, ServerJob &j, int state) {
   return SACD_OK;
 }
 
+// A running job that stops without a result (a non-finite objective, or a
+// cancel): its state, its last iteration count, fit and objective; its device
+// memory is freed.
+void retire_without_result(sacd_server *S, ServerJob &j, int state, sacd_status err) {
+  ServerResult &r = S->results[j.ticket];
+  r.state = state;
+  r.err = err;
+  r.iters = j.iters;
+  r.fit = j.fit;
+  r.f = j.f;
+  r.R = j.m ? j.m->R : 0;
+  S->bytes_in_use -= j.bytes;
+  destroy_job(j);
+}
+
 }  // namespace
 
 extern "C" {
@@ -2111,6 +2127,7 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
     return st;
   }
   S->arena.init(base, (size_t)cfg->budget_bytes);
+  S->budget_cap = cfg->budget_bytes;
   S->alloc.alloc = arena_alloc;
   S->alloc.release = arena_release;
   S->alloc.user = &S->arena;
@@ -2192,6 +2209,12 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
       j.f = S->h_f[i];
       const double nx = std::sqrt(j.t->norm2);
       j.fit = nx > 0.0 ? 1.0 - std::sqrt(j.f > 0.0 ? j.f : 0.0) / nx : 0.0;
+      if (!std::isfinite(j.f)) {  // a non-finite value arose: the job fails, the others run on
+        retire_without_result(S, j, SACD_JOB_FAILED, SACD_ERR_NUMERIC);
+        S->finished.push_back(j.ticket);
+        S->dirty = true;
+        continue;
+      }
       // the stopping rule of sacd_run_until
       const bool conv = j.iters >= 2 && std::fabs(j.fit - j.prev_fit) < S->cfg.tol * std::fabs(j.prev_fit);
       j.prev_fit = j.fit;
@@ -2255,9 +2278,59 @@ sacd_status sacd_server_release(sacd_server *S, int64_t ticket) {
   if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
   auto it = S->results.find(ticket);
   if (it == S->results.end()) return fail(SACD_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
-  if (it->second.state != SACD_JOB_DONE && it->second.state != SACD_JOB_FAILED)
+  const int st = it->second.state;
+  if (st != SACD_JOB_DONE && st != SACD_JOB_FAILED && st != SACD_JOB_CANCELLED)
     return fail(SACD_ERR_BAD_STATE, "job %lld is still queued or running", (long long)ticket);
   S->results.erase(it);
+  return SACD_OK;
+}
+
+sacd_status sacd_server_cancel(sacd_server *S, int64_t ticket) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  auto it = S->results.find(ticket);
+  if (it == S->results.end()) return fail(SACD_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+  ServerResult &r = it->second;
+  if (r.state == SACD_JOB_QUEUED) {
+    for (auto q = S->queue.begin(); q != S->queue.end(); ++q)
+      if (q->ticket == ticket) {
+        S->queue.erase(q);
+        break;
+      }
+    r.state = SACD_JOB_CANCELLED;
+    return SACD_OK;
+  }
+  if (r.state != SACD_JOB_RUNNING)
+    return fail(SACD_ERR_BAD_STATE, "job %lld has already finished", (long long)ticket);
+  SACD_TRY(enter(S->dev));
+  // the server's work is synchronous: no launch of this job is in flight
+  for (size_t i = 0; i < S->active.size(); ++i)
+    if (S->active[i].ticket == ticket) {
+      retire_without_result(S, S->active[i], SACD_JOB_CANCELLED, SACD_OK);
+      S->active.erase(S->active.begin() + (long)i);
+      S->dirty = true;
+      server_drop_graph(S);
+      break;
+    }
+  return SACD_OK;
+}
+
+sacd_status sacd_server_set_budget(sacd_server *S, int64_t budget_bytes) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  if (budget_bytes <= 0 || budget_bytes > S->budget_cap)
+    return fail(SACD_ERR_INVALID_ARG, "budget %lld outside (0, %lld]", (long long)budget_bytes,
+                (long long)S->budget_cap);
+  S->cfg.budget_bytes = budget_bytes;
+  // queued requests that can no longer fit at all fail now
+  for (auto q = S->queue.begin(); q != S->queue.end();) {
+    if (q->est_resident + q->est_transient > budget_bytes) {
+      ServerResult &r = S->results[q->ticket];
+      r.state = SACD_JOB_FAILED;
+      r.err = SACD_ERR_NO_MEMORY;
+      q = S->queue.erase(q);
+    } else {
+      ++q;
+    }
+  }
   return SACD_OK;
 }
 

@@ -54,7 +54,7 @@ class _ServerStats(C.Structure):
                 ("sec_retire", C.c_double)]
 
 
-JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED, JOB_CANCELLED = 0, 1, 2, 3, 4
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 _RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -110,6 +110,8 @@ def lib():
             "sacd_server_poll": [p, i64, p, p, p, p],
             "sacd_server_result": [p, i64, i32, p],
             "sacd_server_release": [p, i64],
+            "sacd_server_cancel": [p, i64],
+            "sacd_server_set_budget": [p, i64],
             "sacd_server_stats": [p, p],
             "sacd_create_ntensor": [i32, p, i64, p, p, p, p, C.POINTER(p)],
             "sacd_ntensor_info": [p, p, p, p, p, p],
@@ -682,6 +684,12 @@ class Server:
 
     def release(self, ticket: int):
         _check(lib().sacd_server_release(self._h, int(ticket)), "sacd_server_release")
+
+    def cancel(self, ticket: int):
+        _check(lib().sacd_server_cancel(self._h, int(ticket)), "sacd_server_cancel")
+
+    def set_budget(self, budget_bytes: int):
+        _check(lib().sacd_server_set_budget(self._h, int(budget_bytes)), "sacd_server_set_budget")
 
     def stats(self) -> dict:
         s = _ServerStats()

@@ -123,6 +123,127 @@ def test_actual_bytes_within_estimate(sacd, prec):
         assert T.info()["device_bytes"] + m.device_bytes() <= resident
 
 
+def _run_to_end(S, budget=None):
+    trace = []
+    for _ in range(10_000):
+        running, queued = S.step()
+        st = S.stats()
+        trace.append(st)
+        if budget is not None:
+            assert st["bytes_in_use"] <= budget
+        if running == 0 and queued == 0:
+            break
+    return trace
+
+
+def _assert_same_as_alone(sacd, S, t, job, precision=0):
+    seed, dims, idx, vals, R = job
+    p = S.poll(t)
+    assert p["state"] == sacd.JOB_DONE, p
+    it, fit, A = _alone(sacd, dims, idx, vals, R, seed, precision)
+    assert p["iters"] == it and p["fit"] == fit, (t, it, p)
+    A_s = S.result(t, dims, R)
+    for n in range(3):
+        np.testing.assert_array_equal(A_s[n].view(np.uint32), A[n].view(np.uint32))
+
+
+def test_nonfinite_job_fails_and_the_others_run_on(sacd):
+    """A job whose values overflow FP32 in the MTTKRP (sixteen entries of 3e38
+    in its fullest mode-0 slice, so the slice's row of M sums to infinity)
+    gets a non-finite objective once it runs: it fails with NUMERIC, its
+    memory is freed and it has no result, while the jobs iterated with it
+    give the same results as alone, bit for bit."""
+    jobs = _small_jobs(3, ranks=[8, 32, 16])
+    seed, dims, idx, vals, R = jobs[1]
+    s0 = np.bincount(idx[:, 0]).argmax()
+    bad = vals.copy()
+    bad[np.flatnonzero(idx[:, 0] == s0)[:16]] = 3e38
+    S = sacd.Server(1 << 32, max_iter=MAX_ITER, tol=TOL)
+    t0 = S.submit(jobs[0][1], jobs[0][2], jobs[0][3], jobs[0][4], jobs[0][0])
+    tb = S.submit(dims, idx, bad, R, seed)
+    t2 = S.submit(jobs[2][1], jobs[2][2], jobs[2][3], jobs[2][4], jobs[2][0])
+    running, queued = S.step()  # all three admitted and iterated once together
+    assert (running, queued) == (2, 0)
+    assert S.finished() == [tb]
+    p = S.poll(tb)
+    assert p["state"] == sacd.JOB_FAILED and p["status"] == -6 and p["iters"] == 1, p
+    _run_to_end(S)
+    with pytest.raises(sacd.SacdError):
+        S.result(tb, dims, R)
+    _assert_same_as_alone(sacd, S, t0, jobs[0])
+    _assert_same_as_alone(sacd, S, t2, jobs[2])
+    assert S.stats()["bytes_in_use"] == 0
+    S.release(tb)
+
+
+def test_cancel_queued_and_running_jobs(sacd):
+    """Cancelling a running job frees it between steps and cancelling a
+    queued one takes it off the queue; the other jobs finish as alone."""
+    jobs = _small_jobs(4, ranks=[8, 16, 32, 8])
+    S = sacd.Server(1 << 32, max_slots=2, max_iter=MAX_ITER, tol=TOL)
+    t = [S.submit(d, i, v, R, sd) for (sd, d, i, v, R) in jobs]
+    running, queued = S.step()
+    assert (running, queued) == (2, 2)
+    assert S.poll(t[1])["state"] == sacd.JOB_RUNNING and S.poll(t[3])["state"] == sacd.JOB_QUEUED
+    held = S.stats()["bytes_in_use"]
+    S.cancel(t[1])
+    S.cancel(t[3])
+    assert S.stats()["bytes_in_use"] < held
+    for k in (1, 3):
+        assert S.poll(t[k])["state"] == sacd.JOB_CANCELLED
+        with pytest.raises(sacd.SacdError) as e:
+            S.cancel(t[k])
+        assert e.value.status == -4
+    _run_to_end(S)
+    _assert_same_as_alone(sacd, S, t[0], jobs[0])
+    _assert_same_as_alone(sacd, S, t[2], jobs[2])
+    assert S.stats()["bytes_in_use"] == 0
+    for k in (1, 3):
+        S.release(t[k])
+
+
+def test_budget_shrinks_while_jobs_run(sacd):
+    """Lowering the budget while jobs run: the running jobs keep their memory
+    and finish as alone; no job is admitted until the running bytes plus its
+    bound fit the new budget; a queued job that cannot fit at all fails, and
+    so does a later submission of one."""
+    jobs = _small_jobs(6, ranks=[8, 16, 8, 16, 8, 128])
+    est = [sum(sacd.job_bytes(j[1], j[2].shape[0], j[4])) for j in jobs]
+    big = 4 * sum(est)
+    S = sacd.Server(big, max_iter=MAX_ITER, tol=TOL)
+    first = [S.submit(d, i, v, R, sd) for (sd, d, i, v, R) in jobs[:3]]
+    running, _ = S.step()
+    assert running == 3
+    small = max(est[:5]) + 1  # each of jobs 0-4 fits alone; job 5 may not
+    later = [S.submit(d, i, v, R, sd) for (sd, d, i, v, R) in jobs[3:5]]
+    tail = S.submit(jobs[5][1], jobs[5][2], jobs[5][3], jobs[5][4], jobs[5][0]) if est[5] > small else None
+    S.set_budget(small)
+    if tail is not None:
+        assert S.poll(tail)["state"] == sacd.JOB_FAILED and S.poll(tail)["status"] == -3
+        with pytest.raises(sacd.SacdError) as e:
+            S.submit(jobs[5][1], jobs[5][2], jobs[5][3], jobs[5][4], jobs[5][0])
+        assert e.value.status == -3
+    with pytest.raises(sacd.SacdError):
+        S.set_budget(big + 1)
+    # a queued job is admitted only when the bytes held after the previous
+    # step plus its bound fit the new budget
+    prev_bytes = S.stats()["bytes_in_use"]
+    assert prev_bytes + min(est[3:5]) > small  # the shrink holds them back at first
+    waiting = dict(zip(later, est[3:5]))
+    for _ in range(10_000):
+        running, queued = S.step()
+        for x in list(waiting):
+            if S.poll(x)["state"] != sacd.JOB_QUEUED:
+                assert prev_bytes + waiting.pop(x) <= small
+        prev_bytes = S.stats()["bytes_in_use"]
+        if running == 0 and queued == 0:
+            break
+    assert not waiting
+    for t_, j in zip(first + later, jobs[:5]):
+        _assert_same_as_alone(sacd, S, t_, j)
+    assert S.stats()["bytes_in_use"] == 0
+
+
 def _tiled_job():
     """A job whose mode 2 takes the tiled MTTKRP form (at least 2^20 entries,
     padded rank 64, A_1 of 3000 rows: too large for the LDS kernel's whole

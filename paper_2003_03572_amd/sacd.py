@@ -8,6 +8,7 @@ stream the library orders its work on.  The library must be built
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 from typing import Optional, Sequence, Tuple
 
@@ -302,11 +303,42 @@ class Model:
         _check(lib().sacd_fit(self._h, C.byref(fit), C.byref(f)), "sacd_fit")
         return fit.value, f.value
 
-    def run_until(self, tol: float, max_iter: int) -> Tuple[int, float]:
-        it, fit = C.c_int32(), C.c_double()
-        _check(lib().sacd_run_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit)),
-               "sacd_run_until")
-        return it.value, fit.value
+    def run_until(self, tol: float, max_iter: int, record=None) -> Tuple[int, float]:
+        """Outer iterations until the relative fit change is below tol (from the
+        second on) or max_iter (sacd_run_until).  With `record` (a path, or a
+        text file open for writing) the same iterations run sweep by sweep and
+        each sweep writes one JSON line: iteration, mode, the mode's sweep
+        counter k, objective f (eq. 6), fit, total importance ti (eq. 25), the
+        eq. 27 branch (flip), the number of selected elements |E| and L."""
+        if record is None:
+            it, fit = C.c_int32(), C.c_double()
+            _check(lib().sacd_run_until(self._h, float(tol), int(max_iter), C.byref(it), C.byref(fit)),
+                   "sacd_run_until")
+            return it.value, fit.value
+        if int(max_iter) < 1 or not float(tol) >= 0.0:
+            raise ValueError("max_iter < 1 or tol < 0")
+        nx = float(np.sqrt(self.t.norm2))
+        if not nx > 0.0:
+            raise ValueError("||X|| = 0: the fit is undefined")
+        own = isinstance(record, (str, os.PathLike))
+        fh = open(record, "w") if own else record
+        try:
+            prev = fit = 0.0
+            it = 0
+            for it in range(1, int(max_iter) + 1):
+                for n in range(3):
+                    self.sweep(n)
+                    s = self.stats(n)
+                    fit = 1.0 - float(np.sqrt(max(s["f"], 0.0))) / nx
+                    fh.write(json.dumps(dict(iter=it, mode=n, k=s["k"], f=s["f"], fit=fit, ti=s["ti"],
+                                             flip=s["flip"], nsel=s["nsel"], L=s["L"])) + "\n")
+                if it >= 2 and abs(fit - prev) < float(tol) * abs(prev):
+                    break
+                prev = fit
+            return it, fit
+        finally:
+            if own:
+                fh.close()
 
     def factor(self, mode: int) -> torch.Tensor:
         out = torch.empty((self.dims[mode], self.R), dtype=torch.float32, device=self.t.device)

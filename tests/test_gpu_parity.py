@@ -306,6 +306,42 @@ def test_run_until_matches_oracle(sacd, oracle_mod):
         assert it2 == it_g and abs(fit2 - fit_g) <= 1e-5 * abs(fit2)
 
 
+def test_run_until_record_per_sweep(sacd, oracle_mod, tmp_path):
+    """run_until with a per-sweep JSONL record runs the same iterations as
+    without (bit for bit) and writes one line per sweep: k counts each mode's
+    sweeps, f is that sweep's objective (eq. 6; the FP64 oracle's own run of
+    the first sweeps within the parity bound), fit the matching fit, and the
+    last line's fit is the one returned."""
+    w = gen.SMALL_UNIFORM
+    dims, idx, vals = gen.make(w)
+    T_g = gpu_tensor(sacd, dims, idx, vals)
+    a = sacd.Model(T_g, w.rank, seed=w.init_seed)
+    it_a, fit_a = a.run_until(1e-4, 40)
+    b = sacd.Model(T_g, w.rank, seed=w.init_seed)
+    path = tmp_path / "sweeps.jsonl"
+    it_b, fit_b = b.run_until(1e-4, 40, record=str(path))
+    assert (it_b, fit_b) == (it_a, fit_a)
+    for n in range(3):
+        np.testing.assert_array_equal(to_np(a.factor(n)).view(np.uint32), to_np(b.factor(n)).view(np.uint32))
+    rows = [json.loads(line) for line in path.read_text().splitlines()]
+    assert len(rows) == 3 * it_b
+    nx = math.sqrt(T_g.norm2)
+    for q, r in enumerate(rows):
+        assert (r["iter"], r["mode"], r["k"]) == (q // 3 + 1, q % 3, q // 3 + 1)
+        assert r["fit"] == 1.0 - math.sqrt(max(r["f"], 0.0)) / nx
+        assert isinstance(r["flip"], bool) and 0 <= r["nsel"] <= dims[r["mode"]] * w.rank and r["L"] > 0
+        if q:
+            assert r["f"] <= rows[q - 1]["f"] * (1 + 1e-6)  # Gauss-Seidel sweeps do not raise f
+    assert rows[-1]["fit"] == fit_b
+    # the first iteration's objectives against the oracle from the same start
+    om = oracle_mod.Model(oracle_mod.Tensor(dims, idx, vals), w.rank, seed=w.init_seed)
+    S_norm = float(np.sum(vals.astype(np.float64) ** 2))
+    for n in range(3):
+        om.sweep(n)
+        f_o = om.info(n)["f"]
+        assert abs(rows[n]["f"] - f_o) <= 1e-5 * abs(f_o) + 1e-6 * S_norm, (n, rows[n]["f"], f_o)
+
+
 def test_objective_nonincreasing_and_nonnegative(sacd):
     dims, idx, vals = gen.make(gen.ZIPF_UIT, scale=0.01)
     T_g = gpu_tensor(sacd, dims, idx, vals)

@@ -68,6 +68,15 @@ struct KeyLayout {
 
 __device__ __forceinline__ int key_row(unsigned long long k, int sh_n) { return (int)(k >> sh_n); }
 
+// The two halves of a device-scope fence for an arrival counter: a block
+// stores its partial results, issues the release half, then increments the
+// counter (a relaxed atomic); the block that sees the count complete issues
+// the acquire half before it reads the others' results.  The release half
+// writes back the L2; only the last block needs the acquire half, which
+// invalidates the caches that later reads would otherwise hit.
+__device__ __forceinline__ void fence_release_device() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire_device() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Importance of one element (eq. 20) from the MTTKRP entry m, the entry ah of
 // A_n H, the current value a, h = h_rr and L / 2.  Explicitly rounded FP32
 // operations: the importance and the update kernels recompute the same z

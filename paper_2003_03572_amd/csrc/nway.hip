@@ -262,12 +262,12 @@ __global__ __launch_bounds__(kThreads) void k_inner_full_n(const unsigned long l
     double t = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) t += red[w];
     part[blockIdx.x] = t;
-    __threadfence();
+    fence_release_device();
     s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
   }
   __syncthreads();
   if (!s_last || threadIdx.x != 0) return;
-  __threadfence();
+  fence_acquire_device();
   double t = 0.0;
   for (unsigned b = 0; b < gridDim.x; ++b) t += *(volatile double *)&part[b];
   *out = t;

@@ -96,11 +96,11 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x4 a, bf16x4 b, f32x4 c) {
 }
 
 // Load of data stored by other blocks of the same grid.  Every block stores,
-// then issues a device-scope fence (release) before it increments the
-// arrival counter; the last block issues a device-scope fence (acquire) after
-// reading the counter, which invalidates its caches, so plain loads that
-// follow observe the other blocks' stores.  Plain loads can be pipelined,
-// unlike atomic ones.
+// then issues the release half of a device-scope fence before it increments
+// the arrival counter; the last block issues the acquire half after reading
+// the counter, which invalidates its caches, so plain loads that follow
+// observe the other blocks' stores (fence_release_device /
+// fence_acquire_device).  Plain loads can be pipelined, unlike atomic ones.
 template <typename T>
 __device__ __forceinline__ T ld_coherent(const T *p) {
   return *p;
@@ -375,13 +375,13 @@ __global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs 
   __syncthreads();
   if (tid == 0) {
     ti_part[blk] = tile_sums_total<Cf::NT>(sT);
-    __threadfence();
+    fence_release_device();
     const unsigned prev = atomicAdd(&st->cnt_imp, 1u);
     s_last = (prev == (unsigned)nblk - 1);
   }
   __syncthreads();
   if (!s_last) break;
-  __threadfence();
+  fence_acquire_device();
   // the block partials in a fixed 256-lane pattern whatever the block size
   // (extra waves add exact zeros at the end)
   double s = 0.0;
@@ -889,13 +889,13 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
   if constexpr (!gram_split<RP>()) {
     __syncthreads();
     if (tid == 0) {
-      __threadfence();
+      fence_release_device();
       const unsigned prev = atomicAdd(args.counter, 1u);
       s_last = (prev == (unsigned)nblk - 1);
     }
     __syncthreads();
     if (!s_last) break;
-    __threadfence();
+    fence_acquire_device();
     gram_finish_body<RP>(args, red);
     if (tid == 0) *args.counter = 0;
   }
@@ -975,13 +975,13 @@ __global__ __launch_bounds__(kThreads) void k_inner_full(const unsigned long lon
   const double bs = block_sum(s, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = bs;
-    __threadfence();
+    fence_release_device();
     const unsigned prev = atomicAdd(counter, 1u);
     s_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
+  fence_acquire_device();
   double t = 0.0;
   for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) t += ld_coherent(&part[i]);
   const double tot = block_sum(t, red);
@@ -1037,13 +1037,13 @@ __global__ __launch_bounds__(kThreads) void k_sq_error(const int32_t *__restrict
   const double bs = block_sum(s, red);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = bs;
-    __threadfence();
+    fence_release_device();
     const unsigned prev = atomicAdd(counter, 1u);
     s_last = (prev == gridDim.x - 1);
   }
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
+  fence_acquire_device();
   double t = 0.0;
   for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) t += ld_coherent(&part[i]);
   const double tot = block_sum(t, red);

@@ -106,52 +106,89 @@ __device__ __forceinline__ T ld_coherent(const T *p) {
   return *p;
 }
 
+// A block's rows of A_n and H are staged in LDS in two halves: fetch issues
+// the global loads into registers, commit stores them to LDS.  A kernel
+// fetches everything it reads before the first commit, so that the block
+// waits on memory once instead of once per array.
 template <int RP, int RB, int NTH = kThreads>
-__device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
-  using Cf = UCfg<RP, RB, NTH>;
-  // all loads of the tile are issued before the first LDS store waits on one
-  static_assert((Cf::RB * RP / 4) % NTH == 0, "whole float4 per thread");
-  constexpr int N4 = Cf::RB * RP / 4 / NTH;  // float4 per thread
+struct RowStage {
+  static_assert((RB * RP / 4) % NTH == 0, "whole float4 per thread");
+  static constexpr int N4 = RB * RP / 4 / NTH;  // float4 per thread
   f32x4 v[N4];
+  // Rows past I read row I - 1 and keep zeros: a load whose value is used
+  // on every path is not sunk past the first wait, as a branch around it
+  // would allow.  A block exists only for row0 < I.
+  __device__ __forceinline__ void fetch(const float *__restrict__ A, int row0, int I) {
 #pragma unroll
-  for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * NTH) * 4;
-    const int r = i / RP;
-    v[k] = (row0 + r < I) ? *(const f32x4 *)(A + (long long)(row0 + r) * RP + i % RP)
-                          : f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < N4; ++k) {
+      const int i = (threadIdx.x + k * NTH) * 4;
+      const int r = row0 + i / RP;
+      const f32x4 x = *(const f32x4 *)(A + (long long)(r < I ? r : I - 1) * RP + i % RP);
+      v[k] = (r < I) ? x : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
   }
+  __device__ __forceinline__ void commit(float *sA) const {
 #pragma unroll
-  for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * NTH) * 4;
-    float *d = sA + (i / RP) * Cf::STR + i % RP;
-    d[0] = v[k][0];
-    d[1] = v[k][1];
-    d[2] = v[k][2];
-    d[3] = v[k][3];
-  }
-}
-
-// Stage H (RP x RP, row stride RP + 1) in LDS.
-template <int RP, int NTH = kThreads>
-__device__ __forceinline__ void load_h(float *sH, const float *__restrict__ H) {
-  constexpr int N4 = (RP * RP / 4 + NTH - 1) / NTH;
-  f32x4 v[N4];
-#pragma unroll
-  for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * NTH) * 4;
-    v[k] = (i < RP * RP) ? *(const f32x4 *)(H + i) : f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-#pragma unroll
-  for (int k = 0; k < N4; ++k) {
-    const int i = (threadIdx.x + k * NTH) * 4;
-    if (i < RP * RP) {
-      float *d = sH + (i / RP) * (RP + 1) + i % RP;
+    for (int k = 0; k < N4; ++k) {
+      const int i = (threadIdx.x + k * NTH) * 4;
+      float *d = sA + (i / RP) * (RP + 1) + i % RP;
       d[0] = v[k][0];
       d[1] = v[k][1];
       d[2] = v[k][2];
       d[3] = v[k][3];
     }
   }
+};
+
+// H (RP x RP) into LDS with row stride RP + 1, VEC consecutive words per
+// load.  Where the block's threads divide H evenly (every RP >= 32 with the
+// thread counts used here) every thread loads and stores unconditionally,
+// so that the load stays where it is issued.
+template <int RP, int NTH = kThreads>
+struct HStage {
+  static constexpr int TOT = RP * RP;
+  static constexpr int VEC = (TOT % (4 * NTH) == 0 || TOT < NTH) ? 4 : 1;
+  static constexpr bool EXACT = TOT % (VEC * NTH) == 0;
+  static constexpr int N = (TOT / VEC + NTH - 1) / NTH;  // loads per thread
+  static_assert(VEC == 4 || EXACT, "single words only where every thread has one");
+  f32x4 v[N];
+  __device__ __forceinline__ void fetch(const float *__restrict__ H) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int i = (threadIdx.x + k * NTH) * VEC;
+      if constexpr (VEC == 4) {
+        v[k] = *(const f32x4 *)(H + (i < TOT ? i : 0));
+      } else {
+        v[k][0] = H[i];
+      }
+    }
+  }
+  __device__ __forceinline__ void commit(float *sH) const {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int i = (threadIdx.x + k * NTH) * VEC;
+      if (EXACT || i < TOT) {
+        float *d = sH + (i / RP) * (RP + 1) + i % RP;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) d[e] = v[k][e];
+      }
+    }
+  }
+};
+
+// With 512 or more threads a block fetches its rows and H together; the
+// 256-thread blocks of the job-batched forms hold 4-8 times as many words per
+// thread and fetch H after committing the rows, which keeps them from spilling.
+template <int NTH>
+constexpr bool stage_together() {
+  return NTH >= 512;
+}
+
+template <int RP, int RB, int NTH = kThreads>
+__device__ __forceinline__ void load_rows(float *sA, const float *__restrict__ A, int row0, int I) {
+  RowStage<RP, RB, NTH> rs;
+  rs.fetch(A, row0, I);
+  rs.commit(sA);
 }
 
 // C tile (16 x 16) of the block's rows times H: rows tr*16.., columns tc*16..
@@ -333,32 +370,51 @@ __global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs 
   __shared__ int s_last;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
-  // this thread's MTTKRP entries for all its tiles, fetched before anything
-  // waits on them
-  float mv[Cf::NTW][4];
+  // everything the block reads is requested before the first wait: L, h_rr
+  // and its near-zero flag for this thread's columns, the MTTKRP entries of
+  // its tiles, the block's rows and H (the 256-thread blocks read h_rr per
+  // tile and H after the rows, with fewer registers)
+  const float halfL = hi->halfL;
+  float mv[Cf::NTW][4], hv[Cf::NTW];
+  int nzv[Cf::NTW];
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const int cc = tc * 16 + (lane & 15);
+    if constexpr (stage_together<Cf::NTH>()) {
+      hv[ti] = hi->hdiag[cc];
+      nzv[ti] = hi->nearzero[cc];
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const long long q = row0 + tr * 16 + 4 * (lane >> 4) + v;
       mv[ti][v] = (q < I) ? M[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP, Cf::RB, Cf::NTH>(sA, A, row0, I);
-  load_h<RP, Cf::NTH>(sH, H);
+  RowStage<RP, Cf::RB, Cf::NTH> rows;
+  HStage<RP, Cf::NTH> hst;
+  rows.fetch(A, row0, I);
+  if constexpr (stage_together<Cf::NTH>()) hst.fetch(H);
+  rows.commit(sA);
+  if constexpr (!stage_together<Cf::NTH>()) hst.fetch(H);
+  hst.commit(sH);
   __syncthreads();
-  const float halfL = hi->halfL;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
-    const float h = hi->hdiag[cc];
-    const int nz = hi->nearzero[cc];
+    float h;
+    int nz;
+    if constexpr (stage_together<Cf::NTH>()) {
+      h = hv[ti];
+      nz = nzv[ti];
+    } else {
+      h = hi->hdiag[cc];
+      nz = hi->nearzero[cc];
+    }
     double zs = 0.0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -382,6 +438,9 @@ __global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs 
   __syncthreads();
   if (!s_last) break;
   fence_acquire_device();
+  // the sweep count and ti^{k-1}, read while the partials are summed
+  const long long kprev = st->k;
+  const double tprev = st->ti_prev;
   // the block partials in a fixed 256-lane pattern whatever the block size
   // (extra waves add exact zeros at the end)
   double s = 0.0;
@@ -389,9 +448,9 @@ __global__ __launch_bounds__(NTH) void k_importance(ImpArgs solo, const ImpArgs 
     for (int i = tid; i < nblk; i += kThreads) s += ld_coherent(&ti_part[i]);
   const double ti = block_sum<Cf::NTH>(s, red);
   if (tid == 0) {
-    const long long k = st->k + 1;
+    const long long k = kprev + 1;
     const int first = (k == 1);
-    st->flip = (!first && ti > st->ti_prev) ? 1 : 0;  // eq. 27 condition: "more than"
+    st->flip = (!first && ti > tprev) ? 1 : 0;  // eq. 27 condition: "more than"
     st->first = first;
     st->k = k;
     st->ti = ti;
@@ -559,17 +618,16 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
   __shared__ int sNz[RP];    // h_rr near zero: divide in FP64
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int row0 = blk * Cf::RB;
-  for (int c = tid; c < RP; c += Cf::NTH) {
-    sHd[c] = hi->hdiag[c];
-    sNz[c] = hi->nearzero[c];
-  }
-  if (wv < (RP + 63) / 64) {
-    const int c = 64 * wv + lane;
-    const unsigned long long b = __ballot(c < RP && hi->hdiag[c < RP ? c : 0] > 0.0f);
-    if (lane == 0) sHpos[wv] = b;
-  }
-  // this thread's MTTKRP and previous-importance entries for all its tiles,
-  // fetched before anything waits on them
+  // everything the block reads is requested before the first wait: the
+  // sweep's selection state, L, h_rr and its near-zero flag (thread c holds
+  // column c), the MTTKRP and previous-importance entries of this thread's
+  // tiles, the block's rows and H
+  static_assert(RP <= Cf::NTH, "a thread per column of H");
+  const int first = st->first, flip = st->flip;
+  const float halfL = hi->halfL;
+  const int cown = tid < RP ? tid : 0;
+  const float hd_own = hi->hdiag[cown];
+  const int nz_own = hi->nearzero[cown];
   float mreg[Cf::NTW][4], zpreg[Cf::NTW][4];
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
@@ -583,20 +641,31 @@ __global__ __launch_bounds__(NTH) void k_select_update(UpdArgs solo, const UpdAr
       zpreg[ti][v] = (q < I) ? Z[q * RP + cc] : 0.0f;
     }
   }
-  load_rows<RP, Cf::RB, Cf::NTH>(sA, A, row0, I);
-  load_h<RP, Cf::NTH>(sH, H);
+  RowStage<RP, Cf::RB, Cf::NTH> rows;
+  HStage<RP, Cf::NTH> hst;
+  rows.fetch(A, row0, I);
+  if constexpr (stage_together<Cf::NTH>()) hst.fetch(H);
+  if (tid < RP) {
+    sHd[tid] = hd_own;
+    sNz[tid] = nz_own;
+  }
+  if (wv < (RP + 63) / 64) {
+    const unsigned long long b = __ballot(tid < RP && hd_own > 0.0f);  // lane l: column 64 wv + l
+    if (lane == 0) sHpos[wv] = b;
+  }
+  rows.commit(sA);
+  if constexpr (!stage_together<Cf::NTH>()) hst.fetch(H);
+  hst.commit(sH);
   for (int c = tid; c < RP; c += Cf::NTH) sCnt[c] = 0;
   __syncthreads();
-  const int first = st->first, flip = st->flip;
-  const float halfL = hi->halfL;
 #pragma unroll
   for (int ti = 0; ti < Cf::NTW; ++ti) {
     const int t = wv + Cf::W * ti;
     const int tr = t / Cf::TC, tc = t % Cf::TC;
     const f32x4 ah = tile_AH<RP, Cf::RB, BF>(sA, sH, tr, tc, lane);
     const int cc = tc * 16 + (lane & 15);
-    const float h = hi->hdiag[cc];
-    const int nz = hi->nearzero[cc];
+    const float h = sHd[cc];
+    const int nz = sNz[cc];
     int cnt = 0;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

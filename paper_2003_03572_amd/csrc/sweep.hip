@@ -12,8 +12,8 @@
 //                    of the new Gram matrix (MFMA), of <M, A_n> (FP64) and of
 //                    the per-column selection counts.
 //   k_gram_final     reduces the Gram partials in FP64 in a fixed order; its
-//                    last block, or k_gram_finish at RP >= 64, forms the
-//                    objective eq. 6 in FP64.
+//                    last block, or k_gram_finish (RP >= 64 and the
+//                    job-batched form), forms the objective eq. 6 in FP64.
 //
 // Rows are split into blocks of RB rows (256 at RP <= 32, fewer above); a
 // block keeps its rows of A_n and H in LDS (row stride RP + 1 floats:
@@ -840,15 +840,18 @@ __device__ __forceinline__ void gram_finish_body(const GramArgs &args, double *r
   }
 }
 
-// Where the objective is formed: at RP >= 64 (hundreds of strip blocks) by
-// k_gram_finish after k_gram_final; at smaller ranks by the last block of
-// k_gram_final to arrive.  An arrival counter needs a device-scope fence in
-// every block (measured 10 us per launch at R = 128, 585 blocks), a kernel of
-// its own about 4 us per launch (more than the fences of the 51 blocks at
-// R = 32).  The result is the same either way.
-template <int RP>
+// Where the objective is formed: at RP >= 64 (hundreds of strip blocks) and
+// in the job-batched form by k_gram_finish after k_gram_final; for a job alone
+// at smaller ranks by the last block of k_gram_final to arrive.  An arrival
+// counter needs a device-scope fence and an atomic round trip in every block
+// (measured 10 us per launch at R = 128, 585 blocks), a kernel of its own
+// about 4 us per launch (more than the fences of the 51 blocks at R = 32).  A
+// persistent block of the batched form works through the strips of many
+// jobs, one fence and round trip per strip.  The result is the same either
+// way.
+template <int RP, bool BATCHED>
 constexpr bool gram_split() {
-  return RP >= 64;
+  return BATCHED || RP >= 64;
 }
 
 // Gram reduction in FP64 and the sweep's scalars, one level, fixed order.
@@ -955,7 +958,7 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
       if (tid == 0) st->inner = in;
     }
   }
-  if constexpr (!gram_split<RP>()) {
+  if constexpr (!gram_split<RP, BATCHED>()) {
     __syncthreads();
     if (tid == 0) {
       fence_release_device();
@@ -975,8 +978,8 @@ __global__ __launch_bounds__(kGramThreads) void k_gram_final(GramArgs solo, cons
 }
 
 // The objective and total selection count as a kernel of its own, one block
-// per job (batched form: the block map's first block of each job), for
-// gram_split ranks.
+// per job (batched form: the block map's first block of each job), where
+// gram_split holds.
 template <int RP, bool BATCHED>
 __global__ __launch_bounds__(kGramThreads) void k_gram_finish(GramArgs solo, const GramArgs *__restrict__ jobs,
                                                           const int4 *__restrict__ bmap, int nb) {
@@ -1307,7 +1310,7 @@ struct GfL {
   static hipError_t run(const GramArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_gram_final<RP, false>), dim3(gram_final_blocks(RP)), dim3(kGramThreads), 0, s, a, nullptr,
                        nullptr, 0);
-    if constexpr (gram_split<RP>())
+    if constexpr (gram_split<RP, false>())
       hipLaunchKernelGGL((k_gram_finish<RP, false>), dim3(1), dim3(kGramThreads), 0, s, a, nullptr, nullptr, 0);
     return hipGetLastError();
   }
@@ -1319,7 +1322,7 @@ struct GfBL {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL((k_gram_final<RP, true>), dim3(persistent_grid(nb)), dim3(kGramThreads), 0, s, GramArgs{}, jobs,
                        bmap, nb);
-    if constexpr (gram_split<RP>())
+    if constexpr (gram_split<RP, true>())
       hipLaunchKernelGGL((k_gram_finish<RP, true>), dim3(persistent_grid(nb)), dim3(kGramThreads), 0, s, GramArgs{},
                          jobs, bmap, nb);
     return hipGetLastError();

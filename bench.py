@@ -436,11 +436,14 @@ def run_served(sacd, gen, pool, prec, rates, requests, budget_mb, tol, max_iter)
         t0 = time.perf_counter()
         nxt, lat, info = 0, {}, {}
         max_running = 0
+        sec_submit = 0.0
         while len(lat) < requests:
             now = time.perf_counter() - t0
             while nxt < requests and arr[nxt] <= now:
                 sp, dims, idx, vals = pool[pick[nxt]]
+                ts = time.perf_counter()
                 tk = S.submit(dims, idx, vals, sp.rank, sp.seed)
+                sec_submit += time.perf_counter() - ts
                 info[tk] = nxt
                 nxt += 1
             running, queued = S.step()
@@ -467,6 +470,8 @@ def run_served(sacd, gen, pool, prec, rates, requests, budget_mb, tol, max_iter)
              "served_nnzR_per_s": sum(nnzR[pick[k]] * lat[k][1] for k in range(requests)) / T_total,
              "max_running": max_running, "peak_bytes": st["peak_bytes"], "steps": st["steps"],
              "graph_launches": st["graph_launches"], "eager_launches": st["eager_launches"],
+             "host_seconds": {"submit": sec_submit, "admit": st["sec_admit"], "tables": st["sec_tables"],
+                              "iterate": st["sec_iterate"], "retire": st["sec_retire"], "total": T_total},
              "results_equal_to_serial": equal}
         per_rate[str(int(lam))] = r
         log(f"[bench] rate {lam:.0f}/s: served p50 {r['served_p50_ms']:.1f} ms p99 {r['served_p99_ms']:.1f} ms "

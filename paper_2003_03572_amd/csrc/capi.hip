@@ -1752,6 +1752,9 @@ struct sacd_server {
   // forked from and joined back to s
   hipStream_t gs[4] = {};
   hipEvent_t ev_fork = nullptr, ev_join[4] = {};
+  // uploads and ingests of admitted jobs, which run while the running jobs'
+  // iteration is in flight on s
+  hipStream_t s_admit = nullptr;
   std::deque<ServerReq> queue;
   std::vector<ServerJob> active;
   std::map<int64_t, ServerResult> results;
@@ -1813,21 +1816,26 @@ sacd_status admit(sacd_server *S, ServerReq &q, ServerJob *out) {
     st = up.get_t((size_t)q.nnz * 3, &didx);
     if (st == SACD_OK) st = up.get_t((size_t)q.nnz, &dvals);
     if (st == SACD_OK) {
-      hipError_t e = hipMemcpyAsync(didx, q.idx.data(), sizeof(int32_t) * 3 * q.nnz, hipMemcpyHostToDevice, S->s);
+      hipError_t e =
+          hipMemcpyAsync(didx, q.idx.data(), sizeof(int32_t) * 3 * q.nnz, hipMemcpyHostToDevice, S->s_admit);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(dvals, q.vals.data(), sizeof(float) * q.nnz, hipMemcpyHostToDevice, S->s);
+        e = hipMemcpyAsync(dvals, q.vals.data(), sizeof(float) * q.nnz, hipMemcpyHostToDevice, S->s_admit);
       if (e != hipSuccess) st = fail(SACD_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
     }
   }
   if (st == SACD_OK)
-    st = sacd_create_tensor(q.dims, q.nnz, didx, dvals, &S->alloc, S->s, &j.t);
-  (void)hipStreamSynchronize(S->s);
+    st = sacd_create_tensor(q.dims, q.nnz, didx, dvals, &S->alloc, S->s_admit, &j.t);
+  (void)hipStreamSynchronize(S->s_admit);
   up.release_all();
   if (st == SACD_OK) st = sacd_init_factors(j.t, q.R, q.seed, S->cfg.precision, SACD_UPDATE_GS, &j.m);
+  if (j.t) (void)hipStreamSynchronize(S->s_admit);
   if (st != SACD_OK) {
     destroy_job(j);
     return st;
   }
+  // from here on the job's work is ordered on the server's stream
+  j.t->stream = S->s;
+  j.m->s = S->s;
   j.bytes = j.t->mem.bytes + j.m->mem.bytes;
   *out = j;
   return SACD_OK;
@@ -2122,6 +2130,8 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
   }
   if (st == SACD_OK && hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming) != hipSuccess)
     st = fail(SACD_ERR_DEVICE, "event creation failed");
+  if (st == SACD_OK && hipStreamCreateWithFlags(&S->s_admit, hipStreamNonBlocking) != hipSuccess)
+    st = fail(SACD_ERR_DEVICE, "stream creation failed");
   if (st != SACD_OK) {
     sacd_server_destroy(S);
     return st;
@@ -2161,18 +2171,17 @@ sacd_status sacd_server_submit(sacd_server *S, const int64_t dims[3], int64_t nn
   return SACD_OK;
 }
 
-sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queued) {
-  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
-  SACD_TRY(enter(S->dev));
-  S->finished.clear();
-  double t0 = now_sec();
-  // admission, first come first served, while the budget and slots allow
-  while (!S->queue.empty() && (int)S->active.size() < S->cfg.max_slots) {
+namespace {
+// Admission, first come first served, while the budget and the slots allow;
+// the admitted jobs are appended to *out (not yet to the running set).
+void admit_queue(sacd_server *S, std::vector<ServerJob> *out) {
+  const double t0 = now_sec();
+  while (!S->queue.empty() && (int)(S->active.size() + out->size()) < S->cfg.max_slots) {
     ServerReq &q = S->queue.front();
     if (S->bytes_in_use + q.est_resident + q.est_transient > S->cfg.budget_bytes) break;
     ServerJob j;
     sacd_status st = admit(S, q, &j);
-    if (st == SACD_ERR_NO_MEMORY && !S->active.empty()) break;  // fragmented: retry when jobs leave
+    if (st == SACD_ERR_NO_MEMORY && !(S->active.empty() && out->empty())) break;  // fragmented: retry when jobs leave
     ServerResult &r = S->results[q.ticket];
     if (st != SACD_OK) {
       r.state = SACD_JOB_FAILED;
@@ -2180,15 +2189,32 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
       S->finished.push_back(q.ticket);
     } else {
       r.state = SACD_JOB_RUNNING;
-      S->active.push_back(j);
+      out->push_back(j);
       S->bytes_in_use += j.bytes;
       S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
-      S->dirty = true;
     }
     S->queue.pop_front();
   }
+  S->sec_admit += now_sec() - t0;
+}
+}  // namespace
+
+sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queued) {
+  if (!S) return fail(SACD_ERR_INVALID_ARG, "server is NULL");
+  SACD_TRY(enter(S->dev));
+  S->finished.clear();
+  // With jobs running, their iteration is launched first and the queue is
+  // admitted (upload and ingest on s_admit) while it runs; the admitted jobs
+  // join the running set after it, for the next step.  With none running,
+  // admission comes first and the admitted jobs iterate in this step.
+  std::vector<ServerJob> admitted;
+  if (S->active.empty()) {
+    admit_queue(S, &admitted);
+    for (ServerJob &j : admitted) S->active.push_back(j);
+    if (!admitted.empty()) S->dirty = true;
+    admitted.clear();
+  }
   double t1 = now_sec();
-  S->sec_admit += t1 - t0;
   if (!S->active.empty()) {
     if (S->dirty) SACD_TRY(rebuild_tables(S));
     double t2 = now_sec();
@@ -2196,9 +2222,11 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
     SACD_TRY(run_iteration(S));
     const int J = (int)S->active.size();
     HIP_TRY(hipMemcpyAsync(S->h_f, S->d_f, sizeof(double) * J, hipMemcpyDeviceToHost, S->s));
+    const double sa = S->sec_admit;
+    admit_queue(S, &admitted);
     HIP_TRY(hipStreamSynchronize(S->s));
     t1 = now_sec();
-    S->sec_iterate += t1 - t2;
+    S->sec_iterate += t1 - t2 - (S->sec_admit - sa);
     S->steps++;
     S->stable_steps++;
     std::vector<ServerJob> keep;
@@ -2226,6 +2254,8 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
       }
     }
     S->active.swap(keep);
+    for (ServerJob &j : admitted) S->active.push_back(j);
+    if (!admitted.empty()) S->dirty = true;
     if (S->dirty) server_drop_graph(S);
     S->sec_retire += now_sec() - t1;
   }
@@ -2368,6 +2398,7 @@ void sacd_server_destroy(sacd_server *S) {
     if (S->ev_join[g]) (void)hipEventDestroy(S->ev_join[g]);
   }
   if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+  if (S->s_admit) (void)hipStreamDestroy(S->s_admit);
   if (S->own_stream && S->s) (void)hipStreamDestroy(S->s);
   delete S;
 }

@@ -280,9 +280,11 @@ void sacd_destroy_model(sacd_model *m);
  * Requests are queued by sacd_server_submit and admitted first come first
  * served while the device bytes of the running jobs plus the new job's upper
  * bound (sacd_job_bytes: resident + transient ingest bytes) stay within the
- * budget and a slot is free.  Each sacd_server_step admits what fits, then
- * runs one outer iteration (Alg. 1: sweeps of modes 0, 1, 2) of every running
- * job with persistent job-batched kernels -- per mode and per padded rank one
+ * budget and a slot is free.  Each sacd_server_step runs one outer iteration
+ * (Alg. 1: sweeps of modes 0, 1, 2) of every running job and admits what fits
+ * while it runs (uploads and ingests on a stream the server owns; the
+ * admitted jobs iterate from the next step, or in this step when no job was
+ * running).  The iteration uses persistent job-batched kernels -- per mode and per padded rank one
  * launch of each sweep kernel covers all jobs, its blocks looping over the
  * jobs' work items -- replayed from a HIP graph while the
  * set of running jobs is unchanged, and retires the jobs that met the
@@ -290,7 +292,8 @@ void sacd_destroy_model(sacd_model *m);
  * two iterations, or max_iter).  A job's arithmetic is the same as when it
  * runs alone (sacd_init_factors + sacd_run_until with the same arguments):
  * results are bit-identical alone and in the mix.  Updates are Gauss-Seidel.
- * The server's work runs on its stream; calls synchronise it. */
+ * The server's iterations run on its stream, admissions on a second stream
+ * it creates; calls synchronise both. */
 typedef struct sacd_server sacd_server;
 
 typedef struct {
@@ -327,7 +330,8 @@ sacd_status sacd_server_create(const sacd_server_config *cfg, const sacd_allocat
  * budget.  *ticket identifies the job in later calls. */
 sacd_status sacd_server_submit(sacd_server *s, const int64_t dims[3], int64_t nnz, const int32_t *idx,
                                const float *vals, int32_t R, uint64_t seed, int64_t *ticket);
-/* Admit, iterate every running job once, retire finished ones.  A job whose
+/* Iterate every running job once while admitting what fits, retire finished
+ * ones, then add the admitted jobs to the running set.  A job whose
  * objective turns non-finite fails there (state FAILED, status NUMERIC, its
  * memory freed, no result); the other jobs run on unchanged. */
 sacd_status sacd_server_step(sacd_server *s, int32_t *n_running, int32_t *n_queued);

@@ -784,8 +784,19 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
   TMP_TRY(tmp.get(tb, &temp));
   TMP_HIP(hipMemsetAsync(err, 0, sizeof(int), s));
   TMP_HIP(launch_make_keys0(idx, vals, n, dims, t->lay[0], k0, v0, err, s));
-  int herr = 0;
+  // mode 0: stable sort by the full key, then merge duplicates; the error
+  // flags and the count of distinct entries are read back together (with a
+  // flag set, the sort and merge ran on keys that are discarded)
+  bool in_alt = false;
+  TMP_HIP(radix_sort_pairs(k0, v0, k1, v1, n, 0, total_bits, temp, s, &in_alt));
+  unsigned long long *ks = in_alt ? k1 : k0;
+  float *vs = in_alt ? v1 : v0;
+  unsigned long long *kd = in_alt ? k0 : k1;  // free pair of buffers
+  float *vd = in_alt ? v0 : v1;
+  TMP_HIP(dedup_sorted(ks, vs, n, kd, vd, cnt, temp, s));
+  int herr = 0, hcnt = 0;
   TMP_HIP(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  TMP_HIP(hipMemcpyAsync(&hcnt, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
   TMP_HIP(hipStreamSynchronize(s));
   if (herr & 1) {
     cleanup();
@@ -796,17 +807,6 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
     cleanup();
     return fail(SACD_ERR_NUMERIC, "a value is NaN or Inf");
   }
-  // mode 0: stable sort by the full key, then merge duplicates
-  bool in_alt = false;
-  TMP_HIP(radix_sort_pairs(k0, v0, k1, v1, n, 0, total_bits, temp, s, &in_alt));
-  unsigned long long *ks = in_alt ? k1 : k0;
-  float *vs = in_alt ? v1 : v0;
-  unsigned long long *kd = in_alt ? k0 : k1;  // free pair of buffers
-  float *vd = in_alt ? v0 : v1;
-  TMP_HIP(dedup_sorted(ks, vs, n, kd, vd, cnt, temp, s));
-  int hcnt = 0;
-  TMP_HIP(hipMemcpyAsync(&hcnt, cnt, sizeof(int), hipMemcpyDeviceToHost, s));
-  TMP_HIP(hipStreamSynchronize(s));
   const long long u = hcnt;
   t->nnz = u;
   for (int m = 0; m < 3; ++m) {
@@ -840,8 +840,7 @@ static sacd_status create_tensor_impl(sacd_tensor *t, const int64_t dims[3], int
     TMP_HIP(hipMemcpyAsync(t->hptr[m].data(), t->ptr[m], sizeof(int) * ((size_t)dims[m] + 1),
                            hipMemcpyDeviceToHost, s));
   }
-  TMP_HIP(hipStreamSynchronize(s));
-  // ||X||^2
+  // ||X||^2, read back with the slice pointers
   {
     const int nparts = 512;
     double *part = (double *)temp;  // temp holds at least 512 doubles

@@ -611,7 +611,20 @@ static int number_runs(std::vector<int4> &units, int upb, std::vector<int4> *lon
 // unit u runs in block u / upb.  Segments of a split slice that sit next to
 // each other in one block form a run that shares one partial slot; the slots
 // of a slice are numbered consecutively.
-static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &mem, MttkrpPlan *out) {
+// Host arrays whose uploads may still be in flight on a stream, kept until
+// the stream has passed them (the destructor waits, also on an error
+// return), so that a model's plans take one wait instead of one per mode.
+struct HostHold {
+  hipStream_t s = nullptr;
+  std::vector<std::vector<int4>> v4;
+  std::vector<std::vector<int>> v1;
+  ~HostHold() {
+    if (s && (!v4.empty() || !v1.empty())) (void)hipStreamSynchronize(s);
+  }
+};
+
+static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &mem, MttkrpPlan *out,
+                              HostHold *hold) {
   const std::vector<int> &ptr = t->hptr[m];
   const int I = (int)t->dims[m];
   std::vector<int4> units;
@@ -719,7 +732,6 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
     HIP_TRY(hipMemcpyAsync(dl, longs.data(), sizeof(int4) * longs.size(), hipMemcpyHostToDevice, t->stream));
   if (!ulongs.empty())
     HIP_TRY(hipMemcpyAsync(dul, ulongs.data(), sizeof(int4) * ulongs.size(), hipMemcpyHostToDevice, t->stream));
-  HIP_TRY(hipStreamSynchronize(t->stream));
   p.units = du;
   p.longs = dl;
   p.uslot = dus;
@@ -727,6 +739,11 @@ static sacd_status build_plan(const sacd_tensor *t, int m, int upb, DevAlloc &me
   p.nuslots = (int)std::count_if(uslot.begin(), uslot.end(), [](int v) { return v >= 0; });
   p.nulong = (int)ulongs.size();
   *out = p;
+  // the arrays move (their buffers stay where the copies read them)
+  hold->v4.push_back(std::move(units));
+  hold->v4.push_back(std::move(longs));
+  hold->v4.push_back(std::move(ulongs));
+  hold->v1.push_back(std::move(uslot));
   return SACD_OK;
 }
 
@@ -1076,13 +1093,15 @@ static sacd_status init_model_impl(sacd_model *m, uint64_t seed) {
   DevAlloc &A = m->mem;
   int maxI = 0;
   long long maxslots = 1;
+  HostHold hold;  // plan arrays in flight until the wait at the end
+  hold.s = t->stream;
   for (int n = 0; n < 3; ++n) {
     const int I = (int)t->dims[n];
     if (I > maxI) maxI = I;
     if (tiled_mode(t->dims, t->nnz, RP, m->cb, n)) {
       SACD_TRY(build_tiled(m, n, &m->plan[n]));
     } else {
-      SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n]));
+      SACD_TRY(build_plan(t, n, mttkrp_units_per_block(RP), A, &m->plan[n], &hold));
       int a, b;
       other_modes(n, &a, &b);
       m->lds_cols[n] = mttkrp_lds_cols(RP, t->dims[b]);

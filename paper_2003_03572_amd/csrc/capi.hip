@@ -2242,7 +2242,13 @@ sacd_status sacd_server_step(sacd_server *S, int32_t *n_running, int32_t *n_queu
     HIP_TRY(hipMemcpyAsync(S->h_f, S->d_f, sizeof(double) * J, hipMemcpyDeviceToHost, S->s));
     const double sa = S->sec_admit;
     admit_queue(S, &admitted);
-    HIP_TRY(hipStreamSynchronize(S->s));
+    const hipError_t e = hipStreamSynchronize(S->s);
+    if (e != hipSuccess) {
+      // the admitted jobs stay with the server (freed with it)
+      for (ServerJob &j : admitted) S->active.push_back(j);
+      S->dirty = true;
+      return fail(SACD_ERR_DEVICE, "server iteration failed: %s", hipGetErrorString(e));
+    }
     t1 = now_sec();
     S->sec_iterate += t1 - t2 - (S->sec_admit - sa);
     S->steps++;

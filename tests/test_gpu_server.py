@@ -147,6 +147,30 @@ def _assert_same_as_alone(sacd, S, t, job, precision=0):
         np.testing.assert_array_equal(A_s[n].view(np.uint32), A[n].view(np.uint32))
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "mixed_bf16"])
+def test_jobs_admitted_while_others_iterate(sacd, precision):
+    """Jobs submitted while others run are admitted during a step's iteration
+    (upload and ingest on the server's second stream) and join the running
+    set at the next step: such a job has no iteration after the step that
+    admitted it, and every job still ends bit-identical to the job alone."""
+    jobs = _small_jobs(5, ranks=[16, 32, 8, 64, 16])
+    S = sacd.Server(1 << 32, max_iter=MAX_ITER, tol=TOL, precision=precision)
+    first = [S.submit(d, i, v, R, sd) for (sd, d, i, v, R) in jobs[:2]]
+    running, queued = S.step()  # none running: admitted first, then iterated
+    assert running == 2 and queued == 0
+    assert all(S.poll(t)["iters"] == 1 for t in first)
+    later = [S.submit(d, i, v, R, sd) for (sd, d, i, v, R) in jobs[2:]]
+    running, queued = S.step()  # admitted while the first two iterate
+    assert running == 5 and queued == 0
+    assert all(S.poll(t)["iters"] == 2 for t in first)
+    assert all(S.poll(t)["iters"] == 0 for t in later)
+    S.step()
+    assert all(S.poll(t)["iters"] == 1 for t in later)
+    _run_to_end(S)
+    for t, job in zip(first + later, jobs):
+        _assert_same_as_alone(sacd, S, t, job, precision)
+
+
 def test_nonfinite_job_fails_and_the_others_run_on(sacd):
     """A job whose values overflow FP32 in the MTTKRP (sixteen entries of 3e38
     in its fullest mode-0 slice, so the slice's row of M sums to infinity)

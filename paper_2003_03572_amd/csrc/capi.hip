@@ -1790,6 +1790,8 @@ struct sacd_server {
   size_t h_f_cap = 0;
   float *h_res = nullptr;  // pinned staging of a retiring job's factors
   size_t h_res_cap = 0;
+  char *h_up = nullptr;  // pinned staging of an admitted job's coordinates and values
+  size_t h_up_cap = 0;
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1834,10 +1836,28 @@ sacd_status admit(sacd_server *S, ServerReq &q, ServerJob *out) {
     st = up.get_t((size_t)q.nnz * 3, &didx);
     if (st == SACD_OK) st = up.get_t((size_t)q.nnz, &dvals);
     if (st == SACD_OK) {
-      hipError_t e =
-          hipMemcpyAsync(didx, q.idx.data(), sizeof(int32_t) * 3 * q.nnz, hipMemcpyHostToDevice, S->s_admit);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(dvals, q.vals.data(), sizeof(float) * q.nnz, hipMemcpyHostToDevice, S->s_admit);
+      // through a pinned buffer, grown to powers of two (the previous
+      // admission's copies are complete: every admission waits on s_admit
+      // before it returns)
+      const size_t bi = sizeof(int32_t) * 3 * (size_t)q.nnz, bv = sizeof(float) * (size_t)q.nnz;
+      if (S->h_up_cap < bi + bv) {
+        if (S->h_up) (void)hipHostFree(S->h_up);
+        S->h_up = nullptr;
+        S->h_up_cap = 0;
+        size_t cap = 1 << 20;
+        while (cap < bi + bv) cap *= 2;
+        if (hipHostMalloc((void **)&S->h_up, cap, hipHostMallocDefault) == hipSuccess) S->h_up_cap = cap;
+        else S->h_up = nullptr;
+      }
+      const void *src_i = q.idx.data(), *src_v = q.vals.data();
+      if (S->h_up) {
+        std::memcpy(S->h_up, q.idx.data(), bi);
+        std::memcpy(S->h_up + bi, q.vals.data(), bv);
+        src_i = S->h_up;
+        src_v = S->h_up + bi;
+      }
+      hipError_t e = hipMemcpyAsync(didx, src_i, bi, hipMemcpyHostToDevice, S->s_admit);
+      if (e == hipSuccess) e = hipMemcpyAsync(dvals, src_v, bv, hipMemcpyHostToDevice, S->s_admit);
       if (e != hipSuccess) st = fail(SACD_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
     }
   }
@@ -2417,6 +2437,7 @@ void sacd_server_destroy(sacd_server *S) {
   if (S->h_stage) (void)hipHostFree(S->h_stage);
   if (S->h_f) (void)hipHostFree(S->h_f);
   if (S->h_res) (void)hipHostFree(S->h_res);
+  if (S->h_up) (void)hipHostFree(S->h_up);
   for (int g = 0; g < 4; ++g) {
     if (S->gs[g]) (void)hipStreamDestroy(S->gs[g]);
     if (S->ev_join[g]) (void)hipEventDestroy(S->ev_join[g]);
